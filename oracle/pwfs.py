@@ -1,0 +1,279 @@
+"""FP64 CPU oracle of the modulated pyramid wavefront sensor and its slope stage.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import or call
+this module: only the tests, the smoke check of the entry file and the CPU
+baseline leg of the benchmark do.  It shares no code with the HIP library;
+its only common dependency is the ``workloads`` package of seeded inputs.
+
+What it computes is the plain Fourier-optics result of the sensor named by
+the paper's ``ModulatedPyramid`` -> ``PyrSlopec`` chain (Section 2.3, Table 4;
+parameters of the pyramid block in the SOUL listing of Appendix B).  The
+paper never writes the sensor's equations down, so the forward model is the
+textbook one, evaluated in complex128 with numpy's FFT as a library step:
+
+  1. pupil amplitude A on a D x D grid, pixel centres at i - (D-1)/2;
+  2. field A exp(i 2 pi OPD / lambda) times the modulation tilt of point k,
+     zero-padded to N x N at offset (N-D)/2, times the half-pixel tilt h;
+  3. unnormalised 2-D DFT, times the separable pyramid mask m (x) m;
+  4. inverse 2-D DFT (1/N^2), |e|^2, averaged over k, weighted over lambda,
+     divided by sum(A^2);
+  5. the four pupil images are binned into b x b subapertures, slopes are
+     the normalised face differences minus the flat-wavefront reference.
+
+The readings taken where the paper is silent (apex on the corner of the four
+central pixels, separable faces, centre-to-centre separation, geometric valid
+map, global normaliser, reference-slope subtraction, sign) are the ones listed
+in the design doc; each is stated again at the function that uses it.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+FLAG_REF_SLOPES = 1
+FLAG_FULL_PLANE = 2
+FLAG_LOCAL_NORM = 4
+
+
+# ---------------------------------------------------------------- geometry --
+
+def centred(n: int) -> np.ndarray:
+    """Pixel-centre coordinates of an n-pixel pupil axis, zero at its middle."""
+    return np.arange(n, dtype=np.float64) - (n - 1) / 2.0
+
+
+def pupil_amplitude(n_pupil: int, obstruction: float) -> np.ndarray:
+    """Circular pupil stop (Table 3, ``PupilStop``): 1 where the pixel centre
+    lies in the annulus obstruction*D/2 <= r <= D/2, else 0 (linear ratio)."""
+    c = centred(n_pupil)
+    r2 = c[None, :] ** 2 + c[:, None] ** 2
+    R = n_pupil / 2.0
+    Ro = obstruction * R
+    return ((r2 <= R * R) & (r2 >= Ro * Ro)).astype(np.float64)
+
+
+def focal_coords(n_fft: int) -> np.ndarray:
+    """Focal-plane coordinate of DFT bin u in pixels.  With the half-pixel
+    input tilt the bins sit at half integers, so the pyramid apex falls on
+    the corner between the four central pixels: u + 1/2 below N/2, u - N + 1/2
+    from N/2 on."""
+    u = np.arange(n_fft, dtype=np.float64)
+    return np.where(u < n_fft // 2, u + 0.5, u - n_fft + 0.5)
+
+
+def mask_vector(n_fft: int, pupil_sep: float) -> np.ndarray:
+    """One axis of the four-face pyramid phase mask, exp(i pi S |u_bar| / N).
+
+    The faces split along both axes, so the 2-D mask is m[v] m[u]; a face
+    of slope pi S / N shifts its pupil image by S/2 pixels, which puts the
+    four image centres S apart (the SOUL block's 'separation between pupil
+    centers')."""
+    ub = focal_coords(n_fft)
+    return np.exp(1j * np.pi * pupil_sep * np.abs(ub) / n_fft)
+
+
+def half_pixel_tilt(n_fft: int) -> np.ndarray:
+    """h[X] = exp(-i pi X / N), X the array index: moves the DFT samples to
+    half-integer focal coordinates."""
+    return np.exp(-1j * np.pi * np.arange(n_fft, dtype=np.float64) / n_fft)
+
+
+def modulation_angles(n_mod: int) -> np.ndarray:
+    """Equispaced points on the modulation circle, counter-clockwise from +x."""
+    return 2.0 * np.pi * np.arange(n_mod, dtype=np.float64) / n_mod
+
+
+def modulation_ramp(n_pupil: int, radius_lod: float, theta: float) -> np.ndarray:
+    """Pupil-plane tilt exp(i 2 pi r (x cos t + y sin t) / D) that moves the
+    focal spot to r lambda/D along angle t (x = column, y = row)."""
+    c = centred(n_pupil)
+    arg = 2.0 * np.pi * radius_lod * (c[None, :] * np.cos(theta) + c[:, None] * np.sin(theta)) / n_pupil
+    return np.exp(1j * arg)
+
+
+def image_origins(s) -> list:
+    """Top-left corner (row, col) of the four pupil images, quadrant order
+    q = 2*iy + ix with iy, ix = 0 for the image at N/2 - S/2 and 1 for N/2 + S/2."""
+    N, D, S = s.n_fft, s.n_pupil, int(round(s.pupil_sep_px))
+    out = []
+    for sy in (-1, 1):
+        for sx in (-1, 1):
+            out.append((N // 2 + sy * S // 2 - D // 2, N // 2 + sx * S // 2 - D // 2))
+    return out
+
+
+# ----------------------------------------------------------------- forward --
+
+def focal_field(E_pupil: np.ndarray, n_fft: int) -> np.ndarray:
+    """Zero-pad a D x D pupil field to N x N at offset (N-D)/2, apply the
+    half-pixel tilt and take the unnormalised 2-D DFT (exp(-2 pi i u x / N))."""
+    D = E_pupil.shape[-1]
+    o = (n_fft - D) // 2
+    E = np.zeros((n_fft, n_fft), np.complex128)
+    E[o:o + D, o:o + D] = E_pupil
+    h = half_pixel_tilt(n_fft)
+    E *= h[:, None] * h[None, :]
+    return np.fft.fft2(E)
+
+
+def pyramid_image(E_pupil: np.ndarray, n_fft: int, m: np.ndarray) -> np.ndarray:
+    """Complex field after the pyramid: IDFT2(DFT2(pad(E) h h) (m m)), with
+    the inverse carrying 1/N^2."""
+    F = focal_field(E_pupil, n_fft)
+    return np.fft.ifft2(F * (m[:, None] * m[None, :]))
+
+
+def forward_frame(opd_nm: np.ndarray, s, mask: np.ndarray | None = None) -> np.ndarray:
+    """Normalised modulated intensity of one frame, float64 [N][N].
+
+    I = sum_l w_l (1/n_mod) sum_k |e_{l,k}|^2 / sum(A^2); phase 2 pi OPD / lambda,
+    modulation radius r_ref * lambda_ref / lambda (a fixed angle on the sky),
+    mask in pixel units independent of lambda."""
+    D, N = s.n_pupil, s.n_fft
+    A = pupil_amplitude(D, s.obstruction)
+    sA2 = float((A * A).sum())
+    m = mask_vector(N, s.pupil_sep_px) if mask is None else mask
+    th = modulation_angles(s.n_mod)
+    opd = np.asarray(opd_nm, dtype=np.float64)
+    I = np.zeros((N, N), np.float64)
+    for lam, w in zip(s.lambdas_nm, s.lambda_weights):
+        E0 = A * np.exp(1j * 2.0 * np.pi * opd / lam)
+        r = s.mod_radius_lod * s.lambda_ref_nm / lam
+        acc = np.zeros((N, N), np.float64)
+        for t in th:
+            e = pyramid_image(E0 * modulation_ramp(D, r, t), N, m)
+            acc += e.real ** 2 + e.imag ** 2
+        I += w * acc / (s.n_mod * sA2)
+    return I
+
+
+def forward(opd_nm: np.ndarray, s, mask: np.ndarray | None = None) -> np.ndarray:
+    """Intensity for a batch of frames, float64 [F][N][N]."""
+    opd_nm = np.asarray(opd_nm)
+    if opd_nm.ndim == 2:
+        opd_nm = opd_nm[None]
+    return np.stack([forward_frame(o, s, mask) for o in opd_nm])
+
+
+# ------------------------------------------ separable (matrix) form of 3-4 --
+
+def separable_operator(n_fft: int, n_pupil: int, pupil_sep: float) -> np.ndarray:
+    """P = IDFT diag(m) DFT diag(h) restricted to the D pupil columns, N x D.
+
+    Because the mask and the tilt are separable, the padded 2-D chain of
+    steps 3-4 equals e = P E P^T for a D x D pupil field E."""
+    N, D = n_fft, n_pupil
+    x = np.arange(N, dtype=np.float64)
+    W = np.exp(-2j * np.pi * np.outer(x, x) / N)          # DFT matrix
+    Winv = np.conj(W) / N
+    m = mask_vector(N, pupil_sep)
+    h = half_pixel_tilt(N)
+    P = Winv @ (m[:, None] * W) * h[None, :]
+    o = (N - D) // 2
+    return P[:, o:o + D]
+
+
+def forward_frame_separable(opd_nm: np.ndarray, s) -> np.ndarray:
+    """The same intensity as ``forward_frame`` through e_k = P (E o R_k) P^T."""
+    D, N = s.n_pupil, s.n_fft
+    A = pupil_amplitude(D, s.obstruction)
+    sA2 = float((A * A).sum())
+    P = separable_operator(N, D, s.pupil_sep_px)
+    opd = np.asarray(opd_nm, dtype=np.float64)
+    I = np.zeros((N, N), np.float64)
+    for lam, w in zip(s.lambdas_nm, s.lambda_weights):
+        E0 = A * np.exp(1j * 2.0 * np.pi * opd / lam)
+        r = s.mod_radius_lod * s.lambda_ref_nm / lam
+        acc = np.zeros((N, N), np.float64)
+        for t in modulation_angles(s.n_mod):
+            e = P @ (E0 * modulation_ramp(D, r, t)) @ P.T
+            acc += np.abs(e) ** 2
+        I += w * acc / (s.n_mod * sA2)
+    return I
+
+
+# ------------------------------------------------------ binning and slopes --
+
+def bin_images(I: np.ndarray, s) -> np.ndarray:
+    """Sum each of the four D x D pupil images over b x b blocks:
+    Q[f][q][i][j], b = D / n_subap."""
+    I = np.asarray(I, dtype=np.float64)
+    if I.ndim == 2:
+        I = I[None]
+    D, n = s.n_pupil, s.n_subap
+    b = D // n
+    Q = np.zeros((I.shape[0], 4, n, n), np.float64)
+    for q, (r0, c0) in enumerate(image_origins(s)):
+        win = I[:, r0:r0 + D, c0:c0 + D]
+        Q[:, q] = win.reshape(I.shape[0], n, b, n, b).sum(axis=(2, 4))
+    return Q
+
+
+def valid_subapertures(s) -> np.ndarray:
+    """Geometric valid map: a subaperture is valid when at least half of its
+    b x b pixels are inside the pupil stop."""
+    A = pupil_amplitude(s.n_pupil, s.obstruction)
+    n = s.n_subap
+    b = s.n_pupil // n
+    frac = A.reshape(n, b, n, b).sum(axis=(1, 3)) / (b * b)
+    return frac >= 0.5
+
+
+def raw_slopes(Q: np.ndarray, valid: np.ndarray, local_norm: bool = False):
+    """Normalised face differences before reference subtraction.
+
+    The image from the faces covering positive focal x sits at N/2 - S/2
+    (quadrants with ix = 0); a positive x tilt moves light onto those faces,
+    so s_x = (Q[ix=0] - Q[ix=1]) / T_bar is positive for it (likewise in y).
+    T_bar is the mean total flux over valid subapertures (summed in float64);
+    with ``local_norm`` each subaperture uses its own total flux instead.
+    Returns (slopes [F][2][n][n], flux [F]) with flux = sum over valid T."""
+    Q = np.asarray(Q, dtype=np.float64)
+    T = Q.sum(axis=1)                                     # [F][n][n]
+    sx = (Q[:, 0] + Q[:, 2]) - (Q[:, 1] + Q[:, 3])
+    sy = (Q[:, 0] + Q[:, 1]) - (Q[:, 2] + Q[:, 3])
+    flux = T[:, valid].sum(axis=1)
+    if local_norm:
+        norm = np.where(valid[None], T, 1.0)
+    else:
+        norm = (flux / valid.sum())[:, None, None]
+    s = np.stack([sx / norm, sy / norm], axis=1)
+    s[:, :, ~valid] = 0.0
+    return s, flux
+
+
+def reference_slopes(s) -> np.ndarray:
+    """Raw slopes of a flat wavefront, [2][n][n]."""
+    D = s.n_pupil
+    I = forward(np.zeros((1, D, D)), s)
+    return raw_slopes(bin_images(I, s), valid_subapertures(s), bool(s.flags & FLAG_LOCAL_NORM))[0][0]
+
+
+def slopes(I: np.ndarray, s, ref: np.ndarray | None = None):
+    """Slopes of intensities I [F][N][N] (``PyrSlopec``): raw slopes minus the
+    flat-wavefront reference when the sensor asks for it, zero outside the
+    valid map.  Returns (slopes [F][2][n][n], flux [F])."""
+    valid = valid_subapertures(s)
+    sl, flux = raw_slopes(bin_images(I, s), valid, bool(s.flags & FLAG_LOCAL_NORM))
+    if s.flags & FLAG_REF_SLOPES:
+        if ref is None:
+            ref = reference_slopes(s)
+        sl = sl - ref[None]
+        sl[:, :, ~valid] = 0.0
+    return sl, flux
+
+
+# --------------------------------------------------------- error metrics --
+
+def intensity_rel_error(I: np.ndarray, I_ref: np.ndarray) -> np.ndarray:
+    """Per-frame normwise relative error ||I - I_ref||_2 / ||I_ref||_2."""
+    I = np.asarray(I, np.float64).reshape(len(I_ref), -1)
+    R = np.asarray(I_ref, np.float64).reshape(len(I_ref), -1)
+    return np.linalg.norm(I - R, axis=1) / np.linalg.norm(R, axis=1)
+
+
+def slope_rel_rms(s: np.ndarray, s_ref: np.ndarray, valid: np.ndarray) -> float:
+    """Pooled relative RMS error over valid subapertures and frames."""
+    a = np.asarray(s, np.float64)[:, :, valid]
+    b = np.asarray(s_ref, np.float64)[:, :, valid]
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))

@@ -1,0 +1,126 @@
+"""Sensor descriptions and workload recipes.
+
+Every number here is a parameter of a workload, not a step of the method.
+The sensor parameters follow the pyramid block of the paper's SOUL
+configuration listing (Appendix B: pupil diameter, pupil-centre separation,
+modulation radius in lambda/D, wavelength) scaled to the five workloads the
+build is measured on.  Readings of parameters the paper leaves open (pupil
+separation of the 160 px sensor, the six heterogeneous instances, jitter per
+axis) are listed in the design doc.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import Optional, Tuple
+
+# flags of the sensor description (mirrored by the C header)
+FLAG_REF_SLOPES = 1   # subtract flat-wavefront reference slopes
+FLAG_FULL_PLANE = 2   # compute and write every pixel of the N x N plane
+FLAG_LOCAL_NORM = 4   # normalise slopes by per-subaperture flux
+
+# precision of the forward transform (mirrored by the C header)
+PREC_FP32 = 0
+PREC_BF16 = 1
+PREC_BF16X3 = 2
+PREC_FP16X3 = 3
+
+
+@dataclass(frozen=True)
+class SensorDesc:
+    """One pyramid sensor.  Lengths in pupil pixels unless stated."""
+    n_pupil: int                 # D: pupil diameter in pixels
+    n_fft: int                   # N: padded transform size
+    n_subap: int                 # subapertures across the pupil
+    n_mod: int                   # modulation points on the circle
+    pupil_sep_px: float          # S: centre-to-centre pupil image separation
+    mod_radius_lod: float        # modulation radius in lambda/D at lambda_ref
+    obstruction: float = 0.0     # linear central-obstruction ratio
+    diameter_m: float = 8.0      # telescope diameter (only used by input generation)
+    lambda_ref_nm: float = 750.0
+    lambdas_nm: Tuple[float, ...] = (750.0,)
+    lambda_weights: Tuple[float, ...] = (1.0,)
+    precision: int = PREC_FP32
+    flags: int = FLAG_REF_SLOPES
+
+    @property
+    def n_lambda(self) -> int:
+        return len(self.lambdas_nm)
+
+    def with_(self, **kw) -> "SensorDesc":
+        return replace(self, **kw)
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    sensors: Tuple[SensorDesc, ...]
+    n_frames: int
+    r0_m: float                  # Fried parameter at r0_lambda_nm
+    L0_m: float                  # outer scale
+    seeds: Tuple[int, ...]       # one screen seed per sensor
+    r0_lambda_nm: float = 500.0
+    jitter_mas: float = 0.0      # RMS tip and tilt per axis
+    jitter_seed: Optional[int] = None
+    extra: dict = field(default_factory=dict)
+
+
+def _cfg1() -> Workload:
+    s = SensorDesc(n_pupil=64, n_fft=128, n_subap=16, n_mod=16, pupil_sep_px=64.0,
+                   mod_radius_lod=3.0, obstruction=0.0, diameter_m=8.0)
+    return Workload("pwfs-64px-N128-16mod-16sub", (s,), n_frames=100,
+                    r0_m=0.15, L0_m=25.0, seeds=(1,))
+
+
+def _cfg2() -> Workload:
+    s = SensorDesc(n_pupil=160, n_fft=512, n_subap=40, n_mod=48, pupil_sep_px=192.0,
+                   mod_radius_lod=3.0, obstruction=0.12, diameter_m=8.0)
+    return Workload("pwfs-160px-N512-48mod-40sub", (s,), n_frames=1000,
+                    r0_m=0.12, L0_m=40.0, seeds=(2,), jitter_mas=5.0, jitter_seed=12)
+
+
+def _cfg3() -> Workload:
+    w = _cfg1()
+    s = w.sensors[0].with_(precision=PREC_BF16X3)
+    return replace(w, name="pwfs-64px-N128-16mod-16sub-mfma", sensors=(s,))
+
+
+def _cfg4() -> Workload:
+    pupils = (80, 120, 160, 160, 240, 240)
+    ffts = (256, 384, 512, 512, 768, 768)
+    mods = ((2.0, 16), (3.0, 32), (3.0, 48), (4.0, 64), (5.0, 80), (5.0, 96))
+    sens = []
+    for d, n, (r, k) in zip(pupils, ffts, mods):
+        sens.append(SensorDesc(n_pupil=d, n_fft=n, n_subap=d // 4, n_mod=k,
+                               pupil_sep_px=1.2 * d, mod_radius_lod=r, obstruction=0.28,
+                               diameter_m=38.5, lambda_ref_nm=750.0,
+                               lambdas_nm=(600.0, 750.0, 900.0),
+                               lambda_weights=(1 / 3, 1 / 3, 1 / 3)))
+    return Workload("pwfs-hetero6-poly3", tuple(sens), n_frames=500, r0_m=0.157,
+                    L0_m=25.0, seeds=tuple(40 + i for i in range(6)))
+
+
+def _cfg5() -> Workload:
+    w = _cfg2()
+    s = w.sensors[0]
+    return Workload("pwfs-160px-surrogate-500modes", (s,), n_frames=200_000,
+                    r0_m=0.12, L0_m=25.0, seeds=(5,),
+                    extra=dict(n_modes=500, hidden=1024, n_test=20_000, test_seed=6,
+                               residual_rms_nm=100.0))
+
+
+WORKLOADS = {
+    "cfg1": _cfg1, "cfg2": _cfg2, "cfg3": _cfg3, "cfg4": _cfg4, "cfg5": _cfg5,
+}
+
+
+def workload(name: str) -> Workload:
+    return WORKLOADS[name]()
+
+
+def tiny_sensor(**kw) -> SensorDesc:
+    """A sensor small enough for brute-force checks: D=8, N=16, 4 points, 2x2."""
+    base = dict(n_pupil=8, n_fft=16, n_subap=2, n_mod=4, pupil_sep_px=8.0,
+                mod_radius_lod=1.0, obstruction=0.0, diameter_m=8.0)
+    base.update(kw)
+    return SensorDesc(**base)
