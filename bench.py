@@ -1,0 +1,172 @@
+"""Throughput of the pyramid-sensor path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+A step is one pass of the whole path (forward model + binning/slopes) over
+the 1000-frame batch of the 160 px pupil / 512 px transform / 48-point
+modulation / 40 x 40 subaperture workload, with the synthetic von Karman
+inputs already resident in HBM.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PWFS frames/s @160px pupil,48 mod pts: plain vs MFMA/surrogate at stated error"
+FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+
+
+def nominal_flops(s) -> dict:
+    """Nominal work per frame of the plain method (5 M log2 M per complex
+    M-point FFT).  Whole path: per wavelength and modulation point one forward
+    and one inverse N x N transform, the mask product (6 flops/px), the |e|^2
+    accumulation (3 flops/px) and the complex modulation/phase product
+    (6 flops per pupil px); the column pass owns the column halves of both
+    2-D transforms plus mask and accumulation."""
+    N, D = s.n_fft, s.n_pupil
+    K = s.n_mod * len(s.lambdas_nm)
+    fft2d = 5.0 * N * N * math.log2(N * N)
+    path = K * (2 * fft2d + 9.0 * N * N + 6.0 * D * D)
+    cols = K * (2 * 5.0 * N * N * math.log2(N) + 9.0 * N * N)
+    return {"path": path, "cols": cols}
+
+
+def _oracle_frame(args):
+    import numpy as np
+    from oracle import pwfs as O
+    opd, s = args
+    I = O.forward(opd[None], s)
+    O.slopes(I, s)
+    return 0
+
+
+def cpu_baseline(s, opd, n_frames: int, cores: int) -> dict:
+    """The FP64 oracle on the host cores, frames split over a process pool."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    sample = [(opd[i], s) for i in range(n_frames)]
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_frame, sample[:cores])          # warm the workers
+        t0 = time.perf_counter()
+        pool.map(_oracle_frame, sample, chunksize=1)
+        dt = time.perf_counter() - t0
+    return {"value": n_frames / dt, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_frames} of the 1000 frames, forward+slopes in complex128 numpy, "
+                      f"{cores} worker processes, {dt:.1f} s wall"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-frames", type=int, default=32)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the sensor path is measured at its single-GPU shape "
+              "(sharding over GPUs is described in DESIGN.md, not run).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    from workloads import workload, workload_opd
+
+    w = workload("cfg2")
+    s = w.sensors[0]
+    t0 = time.perf_counter()
+    opd = workload_opd(w)
+    print(f"# inputs: {w.n_frames} frames generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        cores = max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(s, opd, args.cpu_frames, cores)
+        print(f"# cpu baseline: {cpu['value']:.2f} frames/s on {cores} processes", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_2602_06688_amd import pwfs as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    plan = P.Plan([s], max_frames=w.n_frames, device=dev, stream=stream)
+    x = torch.from_numpy(opd).to(dev)
+    I = plan.new_intensity(w.n_frames)
+    S = plan.new_slopes(w.n_frames)
+    Fl = torch.zeros((w.n_frames, 1), dtype=torch.float32, device=dev)
+
+    for _ in range(args.warmup):
+        plan.step(x, I, S, Fl, stream=stream)
+    torch.cuda.synchronize(dev)
+    # per-kernel HIP events on the launch stream over the timed region
+    plan.profile(4096)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.step(x, I, S, Fl, stream=stream)
+    torch.cuda.synchronize(dev)
+    dt = time.perf_counter() - t0
+    kern = {k: plan.profile_read(k) for k in ("rows", "cols", "slopes")}
+    plan.profile(0)
+
+    frames = w.n_frames * args.steps
+    value = frames / dt
+    flops = nominal_flops(s)
+    cols_ms, cols_n = kern["cols"]
+    frames_per_launch = w.n_frames * args.steps / max(1, cols_n)
+    achieved = flops["cols"] * frames_per_launch / (cols_ms / max(1, cols_n) / 1e3) / 1e12
+    gpu_ms = sum(v[0] for v in kern.values())
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic von Karman screens (r0 0.12 m, L0 40 m) + 5 mas tip/tilt jitter, seeds 2/12",
+        "config": {"workload": w.name, "frames_per_step": w.n_frames, "n_pupil": s.n_pupil, "n_fft": s.n_fft,
+                   "n_mod": s.n_mod, "n_subap": s.n_subap, "obstruction": s.obstruction,
+                   "lambda_nm": s.lambdas_nm[0], "precision": "fp32", "intensity": "pupil-image windows"},
+        "roofline": {
+            "kernel": "k_cols (column pass: column FFT, mask, column IFFT, |e|^2 accumulate)",
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+            "traffic": None,
+            "launches": cols_n,
+            "avg_launch_ms": round(cols_ms / max(1, cols_n), 4),
+            "frames_per_launch": frames_per_launch,
+            "flops_per_frame": flops["cols"],
+        },
+        "roofline_path": {
+            "achieved": round(flops["path"] * frames / (gpu_ms / 1e3) / 1e12, 3),
+            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(flops["path"] * frames / (gpu_ms / 1e3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+            "flops_per_frame": flops["path"],
+            "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,183 @@
+/*
+ * pwfs.h -- C ABI of the MI355X (gfx950) pyramid wavefront sensor library.
+ *
+ * The library computes the forward model of a tip-tilt-modulated four-face
+ * pyramid wavefront sensor and its slope stage: the ``ModulatedPyramid`` and
+ * ``PyrSlopec`` processing objects of the paper (Section 2.3 and Table 4; the
+ * pyramid block of the SOUL listing in Appendix B gives the parameters).  For
+ * every frame, wavelength and modulation point k:
+ *
+ *   E_k = A exp(i 2 pi OPD / lambda) exp(i 2 pi r (x cos t_k + y sin t_k) / D),
+ *   zero-padded to N x N and tilted by half a focal pixel;
+ *   e_k = IDFT2( DFT2(E_k) . m(x)m ),  m[u] = exp(i pi S |u + 1/2| / N);
+ *   I   = sum_lambda w_lambda (1/n_mod) sum_k |e_k|^2 / sum(A^2);
+ *
+ * then the four pupil images of I are binned into subapertures and turned
+ * into normalised slopes minus the flat-wavefront reference.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns a pwfs_status (0 = success); pwfs_last_error() gives
+ *    a thread-local message for the last failure.  No C++ exception crosses
+ *    this boundary.
+ *  - Device pointers are HIP device addresses owned by the caller; the
+ *    library never allocates or frees device memory.  Streams are hipStream_t
+ *    passed as void* (NULL = the null stream).
+ *  - pwfs_forward / pwfs_slopes only enqueue kernels on the given stream:
+ *    they neither allocate nor synchronise, so they may be captured into a
+ *    HIP graph.  Argument checks are synchronous; launch errors are read with
+ *    hipGetLastError after each launch; asynchronous device faults surface at
+ *    the caller's next synchronisation.
+ *  - One plan is used by one stream at a time.
+ *  - Arrays are row-major float32.  For a plan over several sensors the
+ *    per-sensor blocks of one frame are packed one after another, at the
+ *    offsets pwfs_query reports.
+ */
+#ifndef PWFS_H
+#define PWFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pwfs_plan_s* pwfs_plan_t;
+
+typedef enum {
+  PWFS_OK = 0,
+  PWFS_EINVAL = -1,        /* bad argument or sensor description        */
+  PWFS_EUNSUPPORTED = -2,  /* valid, but a size this build does not run */
+  PWFS_EWORKSPACE = -3,    /* workspace missing, too small or misaligned */
+  PWFS_EHIP = -4,          /* a HIP runtime call or launch failed       */
+  PWFS_ESTATE = -5         /* call out of order (e.g. frames > max)     */
+} pwfs_status;
+
+/* Arithmetic of the two transforms of the forward model. */
+typedef enum {
+  PWFS_FP32 = 0,    /* radix FFTs in float32 on the vector ALUs            */
+  PWFS_BF16 = 1,    /* dense DFT operator as bf16 MFMA products, 1 term     */
+  PWFS_BF16X3 = 2,  /* bf16 MFMA with hi/lo split, 3 products, fp32 accum   */
+  PWFS_FP16X3 = 3   /* fp16 MFMA with scaled hi/lo split, 3 products        */
+} pwfs_precision;
+
+enum {
+  PWFS_F_REF_SLOPES = 1,  /* subtract flat-wavefront reference slopes        */
+  PWFS_F_FULL_PLANE = 2,  /* compute every pixel of the N x N plane; without
+                             it only the four D x D pupil images are written
+                             and the other pixels are left untouched        */
+  PWFS_F_LOCAL_NORM = 4   /* normalise by per-subaperture flux, not mean    */
+};
+
+#define PWFS_MAX_LAMBDA 4
+
+/*
+ * One sensor.  Pixel conventions: pupil pixel centres at i - (D-1)/2; the
+ * pupil sits at offset (N-D)/2 of the N x N grid; focal bins at half-integer
+ * coordinates; image q = 2*iy + ix of the four pupil images starts at
+ * (N/2 + sy S/2 - D/2, N/2 + sx S/2 - D/2) with s = -1 for i = 0, +1 for i = 1.
+ */
+typedef struct {
+  int32_t n_pupil;        /* D, even, >= 4                                     */
+  int32_t n_fft;          /* N: 128, 256, 384, 512 or 768                      */
+  int32_t n_subap;        /* subapertures across; D % n_subap == 0, <= 64       */
+  int32_t n_mod;          /* modulation points, >= 1                           */
+  int32_t n_lambda;       /* 1 .. PWFS_MAX_LAMBDA                              */
+  int32_t precision;      /* pwfs_precision                                    */
+  uint32_t flags;         /* PWFS_F_*                                          */
+  int32_t reserved;       /* must be 0                                         */
+  double diameter_m;      /* telescope diameter (> 0; informational)           */
+  double obstruction;     /* linear central obstruction ratio, [0, 1)          */
+  double pupil_sep_px;    /* S: even integer, D <= S, S + D <= N                */
+  double mod_radius_lod;  /* modulation radius in lambda/D at lambda_ref, >= 0  */
+  double lambda_ref_nm;   /* wavelength at which the radius is given, > 0       */
+  double lambda_nm[PWFS_MAX_LAMBDA];      /* sensing wavelengths, > 0          */
+  double lambda_weight[PWFS_MAX_LAMBDA];  /* >= 0, summing to 1 (to 1e-9)      */
+} pwfs_sensor_desc;
+
+/* What a plan reports about one of its sensors. */
+typedef struct {
+  int32_t n_pupil, n_fft, n_subap, n_valid;
+  size_t opd_offset;        /* floats into one frame of the packed OPD input   */
+  size_t intensity_offset;  /* floats into one frame of the packed intensity   */
+  size_t slope_offset;      /* floats into one frame of the packed slopes      */
+  size_t opd_stride, intensity_stride, slope_stride;  /* floats per frame, all sensors */
+} pwfs_sensor_info;
+
+/*
+ * Checks sensor descriptions on the host; touches no device.  Returns
+ * PWFS_EINVAL for a malformed description (N < D, odd N - D, D % n_subap,
+ * pupil images outside the grid, n_mod <= 0, wavelength <= 0, weights not
+ * summing to 1, ...) and PWFS_EUNSUPPORTED for a valid one whose FFT size
+ * has no radix plan here.
+ */
+int pwfs_validate(const pwfs_sensor_desc* sensors, int n_sensors);
+
+/*
+ * Device workspace, in bytes, that pwfs_plan needs for these sensors and up
+ * to max_frames frames per pwfs_forward call.  Host only.
+ */
+int pwfs_workspace_size(const pwfs_sensor_desc* sensors, int n_sensors, int max_frames,
+                        size_t* bytes);
+
+/*
+ * Builds a plan: validates, builds the float64 tables (pupil, ramps, mask,
+ * twiddles, valid map) on the host and copies them into d_workspace (caller
+ * owned, >= pwfs_workspace_size bytes, 256-byte aligned, alive until
+ * pwfs_destroy), then, if PWFS_F_REF_SLOPES is set, computes the reference
+ * slopes of a flat wavefront on the device.  Synchronises hip_stream before
+ * returning.  The plan handle holds host metadata only.
+ */
+int pwfs_plan(const pwfs_sensor_desc* sensors, int n_sensors, int max_frames,
+              void* d_workspace, size_t ws_bytes, void* hip_stream, pwfs_plan_t* out);
+
+/*
+ * Forward model: d_opd_nm [n_frames][opd_stride] optical path difference in
+ * nm (float32) -> d_intensity [n_frames][intensity_stride], each sensor's
+ * block an N x N plane normalised so that a full plane sums to 1.  Without
+ * PWFS_F_FULL_PLANE only the four pupil-image windows are written.
+ * 1 <= n_frames <= max_frames.  Asynchronous on hip_stream.
+ */
+int pwfs_forward(pwfs_plan_t plan, const float* d_opd_nm, int n_frames, float* d_intensity,
+                 void* hip_stream);
+
+/*
+ * Slope stage: d_intensity as written by pwfs_forward -> d_slopes
+ * [n_frames][slope_stride] (per sensor [2][n_subap][n_subap], x then y,
+ * zero outside the valid map) and, if d_flux is not NULL, d_flux
+ * [n_frames][n_sensors] = total flux of the valid subapertures (summed in
+ * float64).  Asynchronous on hip_stream.
+ */
+int pwfs_slopes(pwfs_plan_t plan, const float* d_intensity, int n_frames, float* d_slopes,
+                float* d_flux, void* hip_stream);
+
+/* Geometry and packing of sensor `sensor` of the plan. */
+int pwfs_query(pwfs_plan_t plan, int sensor, pwfs_sensor_info* info);
+
+/* Copies the valid-subaperture map of `sensor` (n_subap^2 bytes, 0/1) to host. */
+int pwfs_valid_map(pwfs_plan_t plan, int sensor, uint8_t* host_out);
+
+/*
+ * Kernel timing for benchmarks.  pwfs_profile(plan, n) creates a pool of
+ * 2n HIP events and, until called again with n = 0, records a start and a
+ * stop event on the launch stream around each of the next n kernel launches
+ * of this plan (launches beyond n are not timed).  Calling it again resets
+ * the pool.  Not for use under graph capture.
+ * pwfs_profile_read waits for the recorded events of one kernel kind
+ * (0 = row pass, 1 = column pass, 2 = slope stage, 3 = matrix-core forward)
+ * and returns their summed duration in ms and their number.
+ */
+int pwfs_profile(pwfs_plan_t plan, int max_launches);
+int pwfs_profile_read(pwfs_plan_t plan, int kernel, double* total_ms, int* launches);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* pwfs_last_error(void);
+
+/* Frees the host-side plan (the workspace stays the caller's). NULL is a no-op. */
+void pwfs_destroy(pwfs_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWFS_H */

@@ -1,0 +1,95 @@
+// pwfs_internal.hpp -- host-side plan structures shared by the library's
+// translation units (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "pwfs.h"
+
+namespace pwfs {
+
+// per-sensor workspace regions, in order
+enum Region {
+  R_AMP = 0, R_RX, R_RY, R_AK, R_MROW, R_MCOL, R_TW, R_VALID, R_REF, R_REFINT, R_ZERO, R_MFMA,
+  kRegions
+};
+
+struct Geometry {
+  int D, N, n, b, S, o;   // pupil, transform, subapertures, block, separation, pad offset
+  int win_lo, win_hi;     // first row/column of the two image windows
+  int full, Nc, Dp;       // full-plane mode, columns kept by the row pass, padded D
+  int n_mod, n_lam, n_a;  // modulation points, wavelengths, distinct cosines
+  int qmax;               // non-zero first-stage inputs per butterfly
+};
+
+struct SensorPlan {
+  pwfs_sensor_desc desc;
+  Geometry g;
+  void* dev[kRegions];
+  int n_valid;
+  double sumA2;
+  std::vector<uint8_t> valid_host;
+  size_t opd_offset, int_offset, slope_offset;
+};
+
+struct Layout {
+  std::vector<size_t> offsets;  // [sensor][region]
+  size_t rbuf_offset = 0, rbuf_bytes = 0, total = 0;
+  int chunk = 1;
+};
+
+Geometry geometry(const pwfs_sensor_desc& d);
+void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vector<uint8_t>& V);
+int fft_lanes(int N);
+int row_tile(int N);
+
+// MFMA (split-precision DFT-as-GEMM) form
+bool mfma_supported(const pwfs_sensor_desc& d);
+size_t mfma_table_bytes(const pwfs_sensor_desc& d);
+size_t mfma_scratch_frame_bytes(const pwfs_sensor_desc& d);
+int upload_mfma_tables(const pwfs_sensor_desc& d, char* dst, hipStream_t st, std::vector<std::vector<char>>& keep,
+                       double sumA2);
+struct Prof;
+int forward_mfma(const SensorPlan& sp, const float* opd, long long opd_stride, float* out, long long out_stride,
+                 int nf, void* scratch, hipStream_t st, Prof* prof);
+
+// Optional per-kernel timing: HIP events recorded on the launch stream
+// around each kernel (pool created when profiling is switched on).
+enum KernelId { K_ROWS = 0, K_COLS = 1, K_SLOPES = 2, K_MFMA = 3, kKernelIds = 8 };
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // start, stop per slot
+  std::vector<int> kid;
+  int used = 0;
+  int begin(hipStream_t st) {
+    if (!on || used >= (int)kid.size()) return -1;
+    if (hipEventRecord(ev[2 * used], st) != hipSuccess) return -1;
+    return used++;
+  }
+  void end(int slot, hipStream_t st, int kernel) {
+    if (slot < 0) return;
+    kid[slot] = kernel;
+    (void)hipEventRecord(ev[2 * slot + 1], st);
+  }
+};
+
+}  // namespace pwfs
+
+struct pwfs_plan_s {
+  std::vector<pwfs::SensorPlan> s;
+  int max_frames = 0, chunk = 1;
+  size_t opd_stride = 0, int_stride = 0, slope_stride = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  float2* rbuf = nullptr;
+  pwfs::Prof prof;
+};
+
+namespace pwfs {
+int forward_sensor(pwfs_plan_s* p, int i, const float* opd, long long opd_stride, float* out, long long out_stride,
+                   int nf, hipStream_t st);
+}

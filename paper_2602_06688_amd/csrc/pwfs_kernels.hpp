@@ -1,0 +1,295 @@
+// pwfs_kernels.hpp -- HIP kernels of the FP32 pyramid-sensor forward model
+// and of the slope stage, for gfx950.
+//
+// The 2-D chain of one modulation point (pad, DFT2, separable mask, IDFT2)
+// factors into a row transform and a column transform because the mask and
+// the tilts are separable.  The row transform of pupil row y,
+//     R_a[y][X] = IDFT_x( m'(u) DFT_x( E0[y][x] rx_a[x] ) ),
+// depends on the modulation point only through a = cos(theta_k) (points k and
+// n_mod - k share it), so it is computed once per distinct a.  The column
+// transform of column X for point k,
+//     e_k[Y][X] = IDFT_y( m'(v) DFT_y( ry_k[y] R_a(k)[y][X] ) ),
+// is where |e|^2 accumulates over k and wavelength in registers.  Only the D
+// non-zero input rows/columns are transformed (the pupil offset is folded
+// into the mask m'), and in window mode only the 2D image columns of R and
+// the 2D image rows of e are kept.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_device.hpp"
+
+namespace pwfs {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
+
+// rows of one row-pass workgroup tile
+template <int N> struct RowTile { static constexpr int RW = 16; };
+template <> struct RowTile<64> { static constexpr int RW = 32; };
+template <> struct RowTile<768> { static constexpr int RW = 8; };
+
+struct RowArgs {
+  const float* opd;        // sensor's first frame of the chunk; frame stride opd_stride
+  const float* amp;        // [D][D] pupil amplitude
+  const float2* rx;        // [n_lam][n_a][D] row tilt (modulation x-part, half-pixel tilt)
+  const float2* mrow;      // [N] row mask with pupil-offset phase and 1/N
+  const float2* tw;        // [N] exp(-2 pi i n / N)
+  float2* rbuf;            // [frames][n_lam][n_a][Nc][Dp]
+  long long opd_stride;
+  int D, Dp, Nc, n_a, n_lam, n_la, ag, n_agroups, rowblocks;
+  int win_lo, win_hi, full;
+  double two_pi_over_lam[4];
+};
+
+struct ColArgs {
+  const float2* rbuf;      // as written by the row pass
+  const float2* ry;        // [n_lam][n_mod][D] column tilt
+  const float2* mcol;      // [n_lam][N] column mask, offset phase, 1/N, sqrt(weight)
+  const float2* tw;        // [N]
+  const int* ak;           // [n_mod] distinct-cosine index of each point
+  float* out;              // sensor's first frame of the chunk; frame stride out_stride
+  long long out_stride;
+  int D, Dp, Nc, n_a, n_lam, n_mod, colblocks;
+  int win_lo, win_hi, full;
+};
+
+struct SlopeArgs {
+  const float* in;         // intensity of the sensor's first frame, frame stride in_stride
+  float* slopes;           // [frame][slope_stride], sensor block [2][n][n]
+  float* flux;             // [frame][flux_stride] or nullptr
+  const uint8_t* valid;    // [n][n]
+  const float* ref;        // [2][n][n] or nullptr
+  long long in_stride, slope_stride, flux_stride;
+  int N, n, b, n_valid, local_norm;
+  int org_r[4], org_c[4];  // image origins
+};
+
+// compact index of plane coordinate X in window mode, -1 if outside
+__device__ __forceinline__ int window_index(int X, int D, int lo, int hi) {
+  if (X >= lo && X < lo + D) return X - lo;
+  if (X >= hi && X < hi + D) return X - hi + D;
+  return -1;
+}
+__device__ __forceinline__ int window_coord(int xc, int D, int lo, int hi) {
+  return xc < D ? lo + xc : hi + xc - D;
+}
+
+// ---------------------------------------------------------------- rows ----
+template <int N, int QM>
+__global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
+  using P = FftPlan<N>;
+  constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
+  constexpr int RW = RowTile<N>::RW, RPG = RW / G;
+  static_assert(RPG >= 1 && RW % G == 0, "row tile");
+  constexpr int RLAST = P::r[P::NS - 1];
+
+  extern __shared__ float2 smem[];
+  float2* s_tw = smem;
+  float2* s_m = s_tw + N;
+  float2* s_buf = s_m + N;
+  float2* s_tile = s_buf + G * N;
+
+  const int tid = threadIdx.x, g = tid / T, t = tid % T;
+  int bid = blockIdx.x;
+  const int agi = bid % p.n_agroups; bid /= p.n_agroups;
+  const int rb = bid % p.rowblocks;
+  const int f = bid / p.rowblocks;
+  const int y0 = rb * RW;
+  const int la0 = agi * p.ag;
+  const int la1 = min(la0 + p.ag, p.n_la);
+
+  for (int i = tid; i < N; i += kBlock) {
+    s_tw[i] = p.tw[i];
+    s_m[i] = p.mrow[i];
+  }
+  float2* buf = s_buf + g * N;
+  const float* opd = p.opd + (long long)f * p.opd_stride;
+
+  float2 e0[RPG][NB0][QM];
+  int cur_lam = -1;
+  __syncthreads();
+
+  for (int la = la0; la < la1; ++la) {
+    const int lam = la / p.n_a, a = la % p.n_a;
+    if (lam != cur_lam) {
+      cur_lam = lam;
+      const double k2p = p.two_pi_over_lam[lam];
+#pragma unroll
+      for (int rr = 0; rr < RPG; ++rr) {
+        const int y = y0 + g * RPG + rr;
+#pragma unroll
+        for (int i = 0; i < NB0; ++i)
+#pragma unroll
+          for (int q = 0; q < QM; ++q) {
+            const int x = t + T * i + q * (N / R0);
+            float2 e = czero();
+            if (y < p.D && x < p.D) {
+              const float amp = p.amp[y * p.D + x];
+              if (amp != 0.f) {
+                // phase in float64, reduced to [-pi, pi] before float32 sincos
+                const double ph = (double)opd[y * p.D + x] * k2p;
+                const double n = rint(ph * 0.15915494309189533577);
+                const float r = (float)fma(-n, 6.283185307179586477, ph);
+                float s, c;
+                sincosf(r, &s, &c);
+                e = make_float2(amp * c, amp * s);
+              }
+            }
+            e0[rr][i][q] = e;
+          }
+      }
+    }
+    const float2* rx = p.rx + (size_t)la * p.D;
+#pragma unroll
+    for (int rr = 0; rr < RPG; ++rr) {
+      const int yl = g * RPG + rr;
+      float2 v[V];
+#pragma unroll
+      for (int i = 0; i < NB0; ++i)
+#pragma unroll
+        for (int q = 0; q < R0; ++q) {
+          if (q < QM) {
+            const int x = t + T * i + q * (N / R0);
+            v[i * R0 + q] = (x < p.D) ? cmul(e0[rr][i][q], rx[x]) : czero();
+          } else {
+            v[i * R0 + q] = czero();
+          }
+        }
+      fft_from<N, false, 0, QM>(v, t, buf, s_tw);
+#pragma unroll
+      for (int s = 0; s < V; ++s) v[s] = cmul(v[s], s_m[freq_index<N>(t, s)]);
+      fft_from<N, true, 0, RLAST>(v, t, buf, s_tw);
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        const int X = space_index<N>(t, s);
+        const int xc = p.full ? X : window_index(X, p.D, p.win_lo, p.win_hi);
+        if (xc >= 0) s_tile[xc * (RW + 1) + yl] = v[s];
+      }
+    }
+    __syncthreads();
+    float2* dst = p.rbuf + ((((size_t)f * p.n_lam + lam) * p.n_a + a) * p.Nc) * p.Dp;
+    const int rows = min(RW, p.D - y0);
+    for (int e = tid; e < p.Nc * RW; e += kBlock) {
+      const int xc = e / RW, yl = e % RW;
+      if (yl < rows) dst[(size_t)xc * p.Dp + y0 + yl] = s_tile[xc * (RW + 1) + yl];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- columns ----
+template <int N, int QM>
+__global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
+  using P = FftPlan<N>;
+  constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
+  constexpr int RLAST = P::r[P::NS - 1];
+
+  extern __shared__ float2 smem[];
+  float2* s_tw = smem;
+  float2* s_m = s_tw + N;               // [n_lam][N]
+  float2* s_buf = s_m + p.n_lam * N;
+
+  const int tid = threadIdx.x, g = tid / T, t = tid % T;
+  const int cb = blockIdx.x % p.colblocks;
+  const int f = blockIdx.x / p.colblocks;
+  const int xc = cb * G + g;
+  const bool live = xc < p.Nc;
+
+  for (int i = tid; i < N; i += kBlock) s_tw[i] = p.tw[i];
+  for (int i = tid; i < p.n_lam * N; i += kBlock) s_m[i] = p.mcol[i];
+  float2* buf = s_buf + g * N;
+  __syncthreads();
+
+  float acc[V];
+#pragma unroll
+  for (int s = 0; s < V; ++s) acc[s] = 0.f;
+
+  for (int lam = 0; lam < p.n_lam; ++lam) {
+    const float2* mc = s_m + lam * N;
+    for (int k = 0; k < p.n_mod; ++k) {
+      const int a = p.ak[k];
+      const float2* col = p.rbuf + (((((size_t)f * p.n_lam + lam) * p.n_a + a) * p.Nc) + (live ? xc : 0)) * p.Dp;
+      const float2* ry = p.ry + ((size_t)lam * p.n_mod + k) * p.D;
+      float2 v[V];
+#pragma unroll
+      for (int i = 0; i < NB0; ++i)
+#pragma unroll
+        for (int q = 0; q < R0; ++q) {
+          if (q < QM) {
+            const int y = t + T * i + q * (N / R0);
+            v[i * R0 + q] = (live && y < p.D) ? cmul(col[y], ry[y]) : czero();
+          } else {
+            v[i * R0 + q] = czero();
+          }
+        }
+      fft_from<N, false, 0, QM>(v, t, buf, s_tw);
+#pragma unroll
+      for (int s = 0; s < V; ++s) v[s] = cmul(v[s], mc[freq_index<N>(t, s)]);
+      fft_from<N, true, 0, RLAST>(v, t, buf, s_tw);
+#pragma unroll
+      for (int s = 0; s < V; ++s) acc[s] += cabs2(v[s]);
+    }
+  }
+  if (!live) return;
+  const int X = p.full ? xc : window_coord(xc, p.D, p.win_lo, p.win_hi);
+  float* out = p.out + (long long)f * p.out_stride;
+#pragma unroll
+  for (int s = 0; s < V; ++s) {
+    const int Y = space_index<N>(t, s);
+    const bool keep = p.full || window_index(Y, p.D, p.win_lo, p.win_hi) >= 0;
+    if (keep) out[(size_t)Y * N + X] = acc[s];
+  }
+}
+
+// -------------------------------------------------------------- slopes ----
+__global__ __launch_bounds__(kBlock) void k_slopes(SlopeArgs p) {
+  extern __shared__ float s_q[];        // [4][n*n]
+  __shared__ double s_red[kBlock];
+  const int tid = threadIdx.x, f = blockIdx.x;
+  const int nn = p.n * p.n;
+  const float* I = p.in + (long long)f * p.in_stride;
+
+  double tsum = 0.0;
+  for (int s = tid; s < nn; s += kBlock) {
+    const int i = s / p.n, j = s % p.n;
+    float tot = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float* blk = I + (size_t)(p.org_r[q] + i * p.b) * p.N + p.org_c[q] + j * p.b;
+      float acc = 0.f;
+      for (int r = 0; r < p.b; ++r)
+        for (int c = 0; c < p.b; ++c) acc += blk[(size_t)r * p.N + c];
+      s_q[q * nn + s] = acc;
+      tot += acc;
+    }
+    if (p.valid[s]) tsum += (double)tot;
+  }
+  s_red[tid] = tsum;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (tid < w) s_red[tid] += s_red[tid + w];
+    __syncthreads();
+  }
+  const double flux = s_red[0];
+  const float gnorm = (float)(flux / (double)p.n_valid);
+  float* out = p.slopes + (long long)f * p.slope_stride;
+  for (int s = tid; s < nn; s += kBlock) {
+    float sx = 0.f, sy = 0.f;
+    if (p.valid[s]) {
+      const float q0 = s_q[s], q1 = s_q[nn + s], q2 = s_q[2 * nn + s], q3 = s_q[3 * nn + s];
+      const float den = p.local_norm ? (q0 + q1 + q2 + q3) : gnorm;
+      sx = ((q0 + q2) - (q1 + q3)) / den;
+      sy = ((q0 + q1) - (q2 + q3)) / den;
+      if (p.ref) {
+        sx -= p.ref[s];
+        sy -= p.ref[nn + s];
+      }
+    }
+    out[s] = sx;
+    out[nn + s] = sy;
+  }
+  if (p.flux && tid == 0) p.flux[(long long)f * p.flux_stride] = (float)flux;
+}
+
+}  // namespace pwfs

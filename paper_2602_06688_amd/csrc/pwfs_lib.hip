@@ -1,0 +1,709 @@
+// pwfs_lib.hip -- host side of the C ABI declared in include/pwfs.h:
+// validation, float64 table construction, workspace layout, plans and the
+// kernel launches of the FP32 forward model and of the slope stage.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <complex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pwfs.h"
+#include "pwfs_kernels.hpp"
+#include "pwfs_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PWFS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                 \
+  do {                                      \
+    hipError_t e__ = (expr);                \
+    if (e__ != hipSuccess) return hip_fail(e__, what); \
+  } while (0)
+
+bool supported_fft(int n) {
+  return n == 64 || n == 128 || n == 256 || n == 384 || n == 512 || n == 768;
+}
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+namespace pwfs {
+
+int validate_one(const pwfs_sensor_desc& d, int idx) {
+  auto bad = [&](const char* why) { return fail(PWFS_EINVAL, "sensor %d: %s", idx, why); };
+  if (d.reserved != 0) return bad("reserved field must be 0");
+  if (d.flags & ~uint32_t(PWFS_F_REF_SLOPES | PWFS_F_FULL_PLANE | PWFS_F_LOCAL_NORM))
+    return bad("unknown flag bits");
+  if (d.n_pupil < 4 || (d.n_pupil & 1)) return bad("n_pupil must be even and >= 4");
+  if (d.n_fft < d.n_pupil) return bad("n_fft must be >= n_pupil");
+  if ((d.n_fft - d.n_pupil) & 1) return bad("n_fft - n_pupil must be even");
+  if (d.n_subap < 1 || d.n_pupil % d.n_subap) return bad("n_pupil must be a multiple of n_subap");
+  if (d.n_mod < 1 || d.n_mod > 4096) return bad("n_mod must be in [1, 4096]");
+  if (d.n_lambda < 1 || d.n_lambda > PWFS_MAX_LAMBDA) return bad("n_lambda must be in [1, 4]");
+  if (!(d.diameter_m > 0.0) || !std::isfinite(d.diameter_m)) return bad("diameter_m must be > 0");
+  if (!(d.obstruction >= 0.0 && d.obstruction < 1.0)) return bad("obstruction must be in [0, 1)");
+  if (!(d.mod_radius_lod >= 0.0) || !std::isfinite(d.mod_radius_lod)) return bad("mod_radius_lod must be >= 0");
+  if (!(d.lambda_ref_nm > 0.0) || !std::isfinite(d.lambda_ref_nm)) return bad("lambda_ref_nm must be > 0");
+  double wsum = 0.0;
+  for (int l = 0; l < d.n_lambda; ++l) {
+    if (!(d.lambda_nm[l] > 0.0) || !std::isfinite(d.lambda_nm[l])) return bad("wavelengths must be > 0");
+    if (!(d.lambda_weight[l] >= 0.0) || !std::isfinite(d.lambda_weight[l])) return bad("weights must be >= 0");
+    wsum += d.lambda_weight[l];
+  }
+  if (std::fabs(wsum - 1.0) > 1e-9) return bad("wavelength weights must sum to 1");
+  const double S = d.pupil_sep_px;
+  if (!std::isfinite(S) || std::fabs(S - std::round(S)) > 1e-9) return bad("pupil_sep_px must be an integer");
+  const long Si = std::lround(S);
+  if (Si & 1) return bad("pupil_sep_px must be even");
+  if (Si < d.n_pupil) return bad("pupil images overlap (pupil_sep_px < n_pupil)");
+  if (Si + d.n_pupil > d.n_fft) return bad("pupil images fall outside the grid (pupil_sep_px + n_pupil > n_fft)");
+  if (d.precision < PWFS_FP32 || d.precision > PWFS_FP16X3) return bad("unknown precision");
+  if (d.n_subap > 64) return fail(PWFS_EUNSUPPORTED, "sensor %d: n_subap > 64 not supported", idx);
+  if (!supported_fft(d.n_fft))
+    return fail(PWFS_EUNSUPPORTED, "sensor %d: n_fft %d has no radix plan (64,128,256,384,512,768)", idx, d.n_fft);
+  if (d.precision != PWFS_FP32 && !mfma_supported(d))
+    return fail(PWFS_EUNSUPPORTED, "sensor %d: this precision is not supported for these sizes", idx);
+  // at least one valid subaperture
+  std::vector<float> A;
+  std::vector<uint8_t> V;
+  pupil_and_valid(d, A, V);
+  int nv = 0;
+  for (uint8_t v : V) nv += v;
+  if (nv == 0) return bad("no valid subaperture");
+  return PWFS_OK;
+}
+
+void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vector<uint8_t>& V) {
+  const int D = d.n_pupil, n = d.n_subap, b = D / n;
+  A.assign((size_t)D * D, 0.f);
+  const double R = D / 2.0, Ro = d.obstruction * R;
+  for (int y = 0; y < D; ++y)
+    for (int x = 0; x < D; ++x) {
+      const double cy = y - (D - 1) / 2.0, cx = x - (D - 1) / 2.0;
+      const double r2 = cx * cx + cy * cy;
+      A[(size_t)y * D + x] = (r2 <= R * R && r2 >= Ro * Ro) ? 1.f : 0.f;
+    }
+  V.assign((size_t)n * n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      int cnt = 0;
+      for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) cnt += A[(size_t)(i * b + r) * D + j * b + c] != 0.f;
+      V[(size_t)i * n + j] = (2 * cnt >= b * b) ? 1 : 0;
+    }
+}
+
+// ----------------------------------------------------------- geometry ----
+Geometry geometry(const pwfs_sensor_desc& d) {
+  Geometry g;
+  g.D = d.n_pupil;
+  g.N = d.n_fft;
+  g.n = d.n_subap;
+  g.b = g.D / g.n;
+  g.S = (int)std::lround(d.pupil_sep_px);
+  g.o = (g.N - g.D) / 2;
+  g.win_lo = g.N / 2 - g.S / 2 - g.D / 2;
+  g.win_hi = g.N / 2 + g.S / 2 - g.D / 2;
+  g.full = (d.flags & PWFS_F_FULL_PLANE) ? 1 : 0;
+  g.Nc = g.full ? g.N : 2 * g.D;
+  g.Dp = (g.D + 15) & ~15;
+  g.n_mod = d.n_mod;
+  g.n_lam = d.n_lambda;
+  g.n_a = d.n_mod / 2 + 1;
+  if (g.n_a > d.n_mod) g.n_a = d.n_mod;
+  g.qmax = (g.D + (g.N / 8) - 1) / (g.N / 8);
+  return g;
+}
+
+// bytes of each per-sensor region, in workspace order
+static void sensor_regions(const pwfs_sensor_desc& d, size_t out[kRegions]) {
+  const Geometry g = geometry(d);
+  const bool ref = d.flags & PWFS_F_REF_SLOPES;
+  out[R_AMP] = sizeof(float) * g.D * g.D;
+  out[R_RX] = sizeof(float2) * g.n_lam * g.n_a * g.D;
+  out[R_RY] = sizeof(float2) * g.n_lam * g.n_mod * g.D;
+  out[R_AK] = sizeof(int) * g.n_mod;
+  out[R_MROW] = sizeof(float2) * g.N;
+  out[R_MCOL] = sizeof(float2) * g.n_lam * g.N;
+  out[R_TW] = sizeof(float2) * g.N;
+  out[R_VALID] = (size_t)g.n * g.n;
+  out[R_REF] = sizeof(float) * 2 * g.n * g.n;
+  out[R_REFINT] = ref ? sizeof(float) * g.N * g.N : 0;
+  out[R_ZERO] = ref ? sizeof(float) * g.D * g.D : 0;
+  out[R_MFMA] = mfma_table_bytes(d);
+}
+
+size_t rbuf_frame_bytes(const pwfs_sensor_desc& d) {
+  const Geometry g = geometry(d);
+  if (d.precision != PWFS_FP32) return mfma_scratch_frame_bytes(d);
+  return sizeof(float2) * (size_t)g.n_lam * g.n_a * g.Nc * g.Dp;
+}
+
+int choose_chunk(const pwfs_sensor_desc* s, int n, int max_frames) {
+  // enough frames per pass that the column pass launches >= ~2048 workgroups,
+  // with the scratch of one pass capped at 1 GiB
+  size_t per = 0;
+  int want = 1;
+  for (int i = 0; i < n; ++i) {
+    const Geometry g = geometry(s[i]);
+    per = std::max(per, rbuf_frame_bytes(s[i]));
+    const int G = kBlock / fft_lanes(g.N);
+    const int colwg = (g.Nc + G - 1) / G;
+    want = std::max(want, (2048 + colwg - 1) / colwg);
+  }
+  const size_t cap = (size_t)1 << 30;
+  int c = std::min(want, max_frames);
+  if (per > 0) c = (int)std::min<size_t>((size_t)c, std::max<size_t>(1, cap / per));
+  return std::max(1, c);
+}
+
+int fft_lanes(int N) {
+  switch (N) {
+    case 64: return FftPlan<64>::T;
+    case 128: return FftPlan<128>::T;
+    case 256: return FftPlan<256>::T;
+    case 384: return FftPlan<384>::T;
+    case 512: return FftPlan<512>::T;
+    default: return FftPlan<768>::T;
+  }
+}
+
+int row_tile(int N) {
+  switch (N) {
+    case 64: return RowTile<64>::RW;
+    case 768: return RowTile<768>::RW;
+    default: return 16;
+  }
+}
+
+int layout(const pwfs_sensor_desc* s, int n, int max_frames, Layout* L) {
+  size_t off = 0;
+  L->offsets.assign((size_t)n * kRegions, 0);
+  for (int i = 0; i < n; ++i) {
+    size_t sz[kRegions];
+    sensor_regions(s[i], sz);
+    for (int r = 0; r < kRegions; ++r) {
+      L->offsets[(size_t)i * kRegions + r] = off;
+      off += align256(sz[r]);
+    }
+  }
+  L->chunk = choose_chunk(s, n, max_frames);
+  size_t per = 0;
+  for (int i = 0; i < n; ++i) per = std::max(per, rbuf_frame_bytes(s[i]));
+  L->rbuf_offset = off;
+  L->rbuf_bytes = per * (size_t)L->chunk;
+  off += align256(L->rbuf_bytes);
+  L->total = off;
+  return PWFS_OK;
+}
+
+// ------------------------------------------------------ float64 tables ---
+static std::complex<double> cis(double a) { return {std::cos(a), std::sin(a)}; }
+
+// exp(i pi S |u_bar| / N) exp(-2 pi i u o / N) / N, phases reduced exactly
+static std::vector<double> mask_table(const Geometry& g, double extra_scale) {
+  std::vector<double> m(2 * (size_t)g.N);
+  const long long N = g.N, S = g.S;
+  for (long long u = 0; u < N; ++u) {
+    // |u_bar| * 2 = |2u + 1| below N/2, |2u + 1 - 2N| above
+    const long long twice = (u < N / 2) ? (2 * u + 1) : (2 * N - 2 * u - 1);
+    // mask phase pi S twice / (2N) = 2 pi (S twice) / (4N)
+    const long long pm = (S * twice) % (4 * N);
+    // offset phase -2 pi u o / N = -2 pi (4 u o) / (4N)
+    const long long po = (4 * ((u * g.o) % N)) % (4 * N);
+    const long long p = ((pm - po) % (4 * N) + 4 * N) % (4 * N);
+    const std::complex<double> z = cis(2.0 * kPi * (double)p / (4.0 * (double)N)) * (extra_scale / (double)N);
+    m[2 * u] = z.real();
+    m[2 * u + 1] = z.imag();
+  }
+  return m;
+}
+
+static void put_c(std::vector<float>& dst, size_t i, std::complex<double> z) {
+  dst[2 * i] = (float)z.real();
+  dst[2 * i + 1] = (float)z.imag();
+}
+
+int upload_tables(const pwfs_sensor_desc& d, char* ws, const size_t* off, hipStream_t st,
+                  std::vector<std::vector<char>>& keep, double* sumA2_out) {
+  const Geometry g = geometry(d);
+  std::vector<float> A;
+  std::vector<uint8_t> V;
+  pupil_and_valid(d, A, V);
+  double sumA2 = 0.0;
+  for (float a : A) sumA2 += (double)a * a;
+  *sumA2_out = sumA2;
+
+  const double h = -kPi / g.N;  // half-pixel tilt per array index
+  std::vector<float> rx(2 * (size_t)g.n_lam * g.n_a * g.D), ry(2 * (size_t)g.n_lam * g.n_mod * g.D);
+  for (int l = 0; l < g.n_lam; ++l) {
+    const double r = d.mod_radius_lod * d.lambda_ref_nm / d.lambda_nm[l];
+    for (int a = 0; a < g.n_a; ++a) {
+      const double th = 2.0 * kPi * a / d.n_mod;
+      for (int x = 0; x < g.D; ++x) {
+        const double xc = x - (g.D - 1) / 2.0;
+        put_c(rx, ((size_t)l * g.n_a + a) * g.D + x,
+              cis(2.0 * kPi * r * xc * std::cos(th) / g.D + h * (g.o + x)));
+      }
+    }
+    for (int k = 0; k < g.n_mod; ++k) {
+      const double th = 2.0 * kPi * k / d.n_mod;
+      for (int y = 0; y < g.D; ++y) {
+        const double yc = y - (g.D - 1) / 2.0;
+        put_c(ry, ((size_t)l * g.n_mod + k) * g.D + y,
+              cis(2.0 * kPi * r * yc * std::sin(th) / g.D + h * (g.o + y)));
+      }
+    }
+  }
+  std::vector<int> ak(g.n_mod);
+  for (int k = 0; k < g.n_mod; ++k) ak[k] = std::min(k, d.n_mod - k);
+  std::vector<float> mrow(2 * (size_t)g.N), mcol(2 * (size_t)g.n_lam * g.N), tw(2 * (size_t)g.N);
+  {
+    const std::vector<double> m = mask_table(g, 1.0);
+    for (size_t i = 0; i < m.size(); ++i) mrow[i] = (float)m[i];
+    for (int l = 0; l < g.n_lam; ++l) {
+      const double sc = std::sqrt(d.lambda_weight[l] / ((double)d.n_mod * sumA2));
+      const std::vector<double> mc = mask_table(g, sc);
+      for (size_t i = 0; i < mc.size(); ++i) mcol[(size_t)l * 2 * g.N + i] = (float)mc[i];
+    }
+    for (int i = 0; i < g.N; ++i) put_c(tw, i, cis(-2.0 * kPi * i / g.N));
+  }
+  auto up = [&](int region, const void* src, size_t bytes) -> int {
+    if (!bytes) return PWFS_OK;
+    keep.emplace_back((const char*)src, (const char*)src + bytes);
+    HIP_TRY(hipMemcpyAsync(ws + off[region], keep.back().data(), bytes, hipMemcpyHostToDevice, st),
+            "hipMemcpyAsync(tables)");
+    return PWFS_OK;
+  };
+  int rc;
+  if ((rc = up(R_AMP, A.data(), A.size() * sizeof(float)))) return rc;
+  if ((rc = up(R_RX, rx.data(), rx.size() * sizeof(float)))) return rc;
+  if ((rc = up(R_RY, ry.data(), ry.size() * sizeof(float)))) return rc;
+  if ((rc = up(R_AK, ak.data(), ak.size() * sizeof(int)))) return rc;
+  if ((rc = up(R_MROW, mrow.data(), mrow.size() * sizeof(float)))) return rc;
+  if ((rc = up(R_MCOL, mcol.data(), mcol.size() * sizeof(float)))) return rc;
+  if ((rc = up(R_TW, tw.data(), tw.size() * sizeof(float)))) return rc;
+  if ((rc = up(R_VALID, V.data(), V.size()))) return rc;
+  if (d.flags & PWFS_F_REF_SLOPES) {
+    HIP_TRY(hipMemsetAsync(ws + off[R_ZERO], 0, sizeof(float) * g.D * g.D, st), "hipMemsetAsync(zero)");
+  }
+  if (d.precision != PWFS_FP32) {
+    if ((rc = upload_mfma_tables(d, ws + off[R_MFMA], st, keep, sumA2))) return rc;
+  }
+  return PWFS_OK;
+}
+
+// ---------------------------------------------------- kernel launches ----
+template <int N, int QM>
+static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_stride, float* out,
+                       long long out_stride, int nf, float2* rbuf, hipStream_t st, Prof* prof) {
+  constexpr int T = FftPlan<N>::T, G = kBlock / T, RW = RowTile<N>::RW;
+  const Geometry& g = sp.g;
+  RowArgs ra{};
+  ra.opd = opd;
+  ra.amp = (const float*)sp.dev[R_AMP];
+  ra.rx = (const float2*)sp.dev[R_RX];
+  ra.mrow = (const float2*)sp.dev[R_MROW];
+  ra.tw = (const float2*)sp.dev[R_TW];
+  ra.rbuf = rbuf;
+  ra.opd_stride = opd_stride;
+  ra.D = g.D;
+  ra.Dp = g.Dp;
+  ra.Nc = g.Nc;
+  ra.n_a = g.n_a;
+  ra.n_lam = g.n_lam;
+  ra.n_la = g.n_lam * g.n_a;
+  ra.rowblocks = (g.D + RW - 1) / RW;
+  // split the (wavelength, cosine) pairs so a pass launches >= ~2048 groups
+  {
+    const long long base = (long long)ra.rowblocks * nf;
+    int groups = (int)std::min<long long>(ra.n_la, std::max<long long>(1, (2048 + base - 1) / base));
+    ra.ag = (ra.n_la + groups - 1) / groups;
+    ra.n_agroups = (ra.n_la + ra.ag - 1) / ra.ag;
+  }
+  ra.win_lo = g.win_lo;
+  ra.win_hi = g.win_hi;
+  ra.full = g.full;
+  for (int l = 0; l < g.n_lam; ++l) ra.two_pi_over_lam[l] = 2.0 * kPi / sp.desc.lambda_nm[l];
+  const size_t lds_rows = sizeof(float2) * (2 * N + G * N + (size_t)g.Nc * (RW + 1));
+  const unsigned grid_rows = (unsigned)((long long)nf * ra.rowblocks * ra.n_agroups);
+  int slot = prof->begin(st);
+  hipLaunchKernelGGL((k_rows<N, QM>), dim3(grid_rows), dim3(kBlock), lds_rows, st, ra);
+  HIP_TRY(hipGetLastError(), "launch k_rows");
+  prof->end(slot, st, K_ROWS);
+
+  ColArgs ca{};
+  ca.rbuf = rbuf;
+  ca.ry = (const float2*)sp.dev[R_RY];
+  ca.mcol = (const float2*)sp.dev[R_MCOL];
+  ca.tw = (const float2*)sp.dev[R_TW];
+  ca.ak = (const int*)sp.dev[R_AK];
+  ca.out = out;
+  ca.out_stride = out_stride;
+  ca.D = g.D;
+  ca.Dp = g.Dp;
+  ca.Nc = g.Nc;
+  ca.n_a = g.n_a;
+  ca.n_lam = g.n_lam;
+  ca.n_mod = g.n_mod;
+  ca.colblocks = (g.Nc + G - 1) / G;
+  ca.win_lo = g.win_lo;
+  ca.win_hi = g.win_hi;
+  ca.full = g.full;
+  const size_t lds_cols = sizeof(float2) * ((size_t)N + (size_t)g.n_lam * N + (size_t)G * N);
+  slot = prof->begin(st);
+  hipLaunchKernelGGL((k_cols<N, QM>), dim3((unsigned)(nf * ca.colblocks)), dim3(kBlock), lds_cols, st, ca);
+  HIP_TRY(hipGetLastError(), "launch k_cols");
+  prof->end(slot, st, K_COLS);
+  return PWFS_OK;
+}
+
+template <int N>
+static int launch_fp32_q(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost,
+                         int nf, float2* rbuf, hipStream_t st, Prof* pr) {
+  const int q = sp.g.qmax;
+  if (q <= 3) return launch_fp32<N, 3>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+  if (q == 4) return launch_fp32<N, 4>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+  return launch_fp32<N, 8>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+}
+
+int forward_fp32(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost, int nf,
+                 float2* rbuf, hipStream_t st, Prof* pr) {
+  switch (sp.g.N) {
+    case 64: return launch_fp32_q<64>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 128: return launch_fp32_q<128>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 256: return launch_fp32_q<256>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 384: return launch_fp32_q<384>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 512: return launch_fp32_q<512>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 768: return launch_fp32_q<768>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+  }
+  return fail(PWFS_EUNSUPPORTED, "n_fft %d", sp.g.N);
+}
+
+// Raising the dynamic-LDS limit is advisory: if the runtime refuses it, a
+// launch that needs more than the default fails and is reported by
+// hipGetLastError at that launch.
+static void lds_limit(const void* fn) {
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+    (void)hipGetLastError();
+}
+
+template <int N, int QM>
+static int set_lds_limits() {
+  lds_limit((const void*)k_rows<N, QM>);
+  lds_limit((const void*)k_cols<N, QM>);
+  return PWFS_OK;
+}
+
+template <int N>
+static int set_lds_limits_q() {
+  int rc;
+  if ((rc = set_lds_limits<N, 3>())) return rc;
+  if ((rc = set_lds_limits<N, 4>())) return rc;
+  return set_lds_limits<N, 8>();
+}
+
+int prepare_kernels() {
+  static bool done = false;
+  if (done) return PWFS_OK;
+  int rc;
+  if ((rc = set_lds_limits_q<64>())) return rc;
+  if ((rc = set_lds_limits_q<128>())) return rc;
+  if ((rc = set_lds_limits_q<256>())) return rc;
+  if ((rc = set_lds_limits_q<384>())) return rc;
+  if ((rc = set_lds_limits_q<512>())) return rc;
+  if ((rc = set_lds_limits_q<768>())) return rc;
+  lds_limit((const void*)k_slopes);
+  done = true;
+  return PWFS_OK;
+}
+
+int slopes_launch(const SensorPlan& sp, const float* in, long long in_stride, float* slopes, long long slope_stride,
+                  float* flux, long long flux_stride, const float* ref, int nf, hipStream_t st, Prof* prof) {
+  const Geometry& g = sp.g;
+  SlopeArgs a{};
+  a.in = in;
+  a.slopes = slopes;
+  a.flux = flux;
+  a.valid = (const uint8_t*)sp.dev[R_VALID];
+  a.ref = ref;
+  a.in_stride = in_stride;
+  a.slope_stride = slope_stride;
+  a.flux_stride = flux_stride;
+  a.N = g.N;
+  a.n = g.n;
+  a.b = g.b;
+  a.n_valid = sp.n_valid;
+  a.local_norm = (sp.desc.flags & PWFS_F_LOCAL_NORM) ? 1 : 0;
+  int q = 0;
+  for (int sy = -1; sy <= 1; sy += 2)
+    for (int sx = -1; sx <= 1; sx += 2, ++q) {
+      a.org_r[q] = g.N / 2 + sy * g.S / 2 - g.D / 2;
+      a.org_c[q] = g.N / 2 + sx * g.S / 2 - g.D / 2;
+    }
+  const size_t lds = sizeof(float) * 4 * g.n * g.n;
+  const int slot = prof ? prof->begin(st) : -1;
+  hipLaunchKernelGGL(k_slopes, dim3((unsigned)nf), dim3(kBlock), lds, st, a);
+  HIP_TRY(hipGetLastError(), "launch k_slopes");
+  if (prof) prof->end(slot, st, K_SLOPES);
+  return PWFS_OK;
+}
+
+}  // namespace pwfs
+
+// ===================================================================== ABI ==
+using namespace pwfs;
+
+extern "C" {
+
+const char* pwfs_last_error(void) { return g_err.c_str(); }
+
+int pwfs_validate(const pwfs_sensor_desc* s, int n) {
+  g_err.clear();
+  if (!s) return fail(PWFS_EINVAL, "sensors is NULL");
+  if (n < 1 || n > 64) return fail(PWFS_EINVAL, "n_sensors must be in [1, 64]");
+  for (int i = 0; i < n; ++i) {
+    const int rc = validate_one(s[i], i);
+    if (rc) return rc;
+  }
+  return PWFS_OK;
+}
+
+int pwfs_workspace_size(const pwfs_sensor_desc* s, int n, int max_frames, size_t* bytes) {
+  int rc = pwfs_validate(s, n);
+  if (rc) return rc;
+  if (!bytes) return fail(PWFS_EINVAL, "bytes is NULL");
+  if (max_frames < 1) return fail(PWFS_EINVAL, "max_frames must be >= 1");
+  Layout L;
+  layout(s, n, max_frames, &L);
+  *bytes = L.total;
+  return PWFS_OK;
+}
+
+int pwfs_plan(const pwfs_sensor_desc* s, int n, int max_frames, void* ws, size_t ws_bytes, void* stream,
+              pwfs_plan_t* out) {
+  int rc = pwfs_validate(s, n);
+  if (rc) return rc;
+  if (!out) return fail(PWFS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_frames < 1) return fail(PWFS_EINVAL, "max_frames must be >= 1");
+  if (!ws) return fail(PWFS_EWORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws & 255) return fail(PWFS_EWORKSPACE, "workspace must be 256-byte aligned");
+  Layout L;
+  layout(s, n, max_frames, &L);
+  if (ws_bytes < L.total)
+    return fail(PWFS_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  if ((rc = prepare_kernels())) return rc;
+  hipStream_t st = (hipStream_t)stream;
+
+  pwfs_plan_s* p = new (std::nothrow) pwfs_plan_s();
+  if (!p) return fail(PWFS_EINVAL, "out of host memory");
+  p->max_frames = max_frames;
+  p->chunk = L.chunk;
+  p->ws = (char*)ws;
+  p->ws_bytes = ws_bytes;
+  p->rbuf = (float2*)((char*)ws + L.rbuf_offset);
+  size_t opd = 0, inten = 0, sl = 0;
+  std::vector<std::vector<char>> keep;
+  for (int i = 0; i < n; ++i) {
+    SensorPlan sp;
+    sp.desc = s[i];
+    sp.g = geometry(s[i]);
+    for (int r = 0; r < kRegions; ++r) sp.dev[r] = (char*)ws + L.offsets[(size_t)i * kRegions + r];
+    std::vector<float> A;
+    std::vector<uint8_t> V;
+    pupil_and_valid(s[i], A, V);
+    sp.n_valid = 0;
+    for (uint8_t v : V) sp.n_valid += v;
+    sp.valid_host = V;
+    sp.opd_offset = opd;
+    sp.int_offset = inten;
+    sp.slope_offset = sl;
+    opd += (size_t)sp.g.D * sp.g.D;
+    inten += (size_t)sp.g.N * sp.g.N;
+    sl += 2 * (size_t)sp.g.n * sp.g.n;
+    if ((rc = upload_tables(s[i], (char*)ws, &L.offsets[(size_t)i * kRegions], st, keep, &sp.sumA2))) {
+      (void)hipStreamSynchronize(st);
+      delete p;
+      return rc;
+    }
+    p->s.push_back(sp);
+  }
+  p->opd_stride = opd;
+  p->int_stride = inten;
+  p->slope_stride = sl;
+  // reference slopes of a flat wavefront, sensor by sensor
+  for (int i = 0; i < n && rc == 0; ++i) {
+    const SensorPlan& sp = p->s[i];
+    if (!(sp.desc.flags & PWFS_F_REF_SLOPES)) continue;
+    float* I = (float*)sp.dev[R_REFINT];
+    rc = forward_sensor(p, i, (const float*)sp.dev[R_ZERO], 0, I, 0, 1, st);
+    if (!rc)
+      rc = slopes_launch(sp, I, 0, (float*)sp.dev[R_REF], 0, nullptr, 0, nullptr, 1, st, nullptr);
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipStreamSynchronize(plan)");
+  }
+  *out = p;
+  return PWFS_OK;
+}
+
+int pwfs_forward(pwfs_plan_t p, const float* opd, int nf, float* out, void* stream) {
+  if (!p) return fail(PWFS_EINVAL, "plan is NULL");
+  if (!opd || !out) return fail(PWFS_EINVAL, "NULL device pointer");
+  if (nf < 1 || nf > p->max_frames)
+    return fail(PWFS_ESTATE, "n_frames %d outside [1, max_frames=%d]", nf, p->max_frames);
+  hipStream_t st = (hipStream_t)stream;
+  for (size_t i = 0; i < p->s.size(); ++i) {
+    const SensorPlan& sp = p->s[i];
+    const int rc = forward_sensor(p, (int)i, opd + sp.opd_offset, (long long)p->opd_stride,
+                                  out + sp.int_offset, (long long)p->int_stride, nf, st);
+    if (rc) return rc;
+  }
+  return PWFS_OK;
+}
+
+int pwfs_slopes(pwfs_plan_t p, const float* in, int nf, float* slopes, float* flux, void* stream) {
+  if (!p) return fail(PWFS_EINVAL, "plan is NULL");
+  if (!in || !slopes) return fail(PWFS_EINVAL, "NULL device pointer");
+  if (nf < 1 || nf > p->max_frames)
+    return fail(PWFS_ESTATE, "n_frames %d outside [1, max_frames=%d]", nf, p->max_frames);
+  hipStream_t st = (hipStream_t)stream;
+  const long long ns = (long long)p->s.size();
+  for (size_t i = 0; i < p->s.size(); ++i) {
+    const SensorPlan& sp = p->s[i];
+    const float* ref = (sp.desc.flags & PWFS_F_REF_SLOPES) ? (const float*)sp.dev[R_REF] : nullptr;
+    const int rc = slopes_launch(sp, in + sp.int_offset, (long long)p->int_stride, slopes + sp.slope_offset,
+                                 (long long)p->slope_stride, flux ? flux + i : nullptr, ns, ref, nf, st, &p->prof);
+    if (rc) return rc;
+  }
+  return PWFS_OK;
+}
+
+int pwfs_query(pwfs_plan_t p, int sensor, pwfs_sensor_info* info) {
+  if (!p || !info) return fail(PWFS_EINVAL, "NULL argument");
+  if (sensor < 0 || sensor >= (int)p->s.size()) return fail(PWFS_EINVAL, "sensor index out of range");
+  const SensorPlan& sp = p->s[sensor];
+  info->n_pupil = sp.g.D;
+  info->n_fft = sp.g.N;
+  info->n_subap = sp.g.n;
+  info->n_valid = sp.n_valid;
+  info->opd_offset = sp.opd_offset;
+  info->intensity_offset = sp.int_offset;
+  info->slope_offset = sp.slope_offset;
+  info->opd_stride = p->opd_stride;
+  info->intensity_stride = p->int_stride;
+  info->slope_stride = p->slope_stride;
+  return PWFS_OK;
+}
+
+int pwfs_valid_map(pwfs_plan_t p, int sensor, uint8_t* host_out) {
+  if (!p || !host_out) return fail(PWFS_EINVAL, "NULL argument");
+  if (sensor < 0 || sensor >= (int)p->s.size()) return fail(PWFS_EINVAL, "sensor index out of range");
+  const std::vector<uint8_t>& v = p->s[sensor].valid_host;
+  std::memcpy(host_out, v.data(), v.size());
+  return PWFS_OK;
+}
+
+static void prof_release(Prof& pr) {
+  for (hipEvent_t e : pr.ev) (void)hipEventDestroy(e);
+  pr.ev.clear();
+  pr.kid.clear();
+  pr.used = 0;
+  pr.on = false;
+}
+
+int pwfs_profile(pwfs_plan_t p, int max_launches) {
+  if (!p) return fail(PWFS_EINVAL, "plan is NULL");
+  prof_release(p->prof);
+  if (max_launches <= 0) return PWFS_OK;
+  if (max_launches > (1 << 20)) return fail(PWFS_EINVAL, "max_launches too large");
+  p->prof.ev.resize(2 * (size_t)max_launches);
+  p->prof.kid.assign((size_t)max_launches, -1);
+  for (auto& e : p->prof.ev) {
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) {
+      e = nullptr;
+      prof_release(p->prof);
+      return hip_fail(err, "hipEventCreate");
+    }
+  }
+  p->prof.on = true;
+  return PWFS_OK;
+}
+
+int pwfs_profile_read(pwfs_plan_t p, int kernel, double* total_ms, int* launches) {
+  if (!p || !total_ms || !launches) return fail(PWFS_EINVAL, "NULL argument");
+  double t = 0.0;
+  int n = 0;
+  for (int i = 0; i < p->prof.used; ++i) {
+    if (p->prof.kid[i] != kernel) continue;
+    HIP_TRY(hipEventSynchronize(p->prof.ev[2 * i + 1]), "hipEventSynchronize");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->prof.ev[2 * i], p->prof.ev[2 * i + 1]), "hipEventElapsedTime");
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *launches = n;
+  return PWFS_OK;
+}
+
+void pwfs_destroy(pwfs_plan_t p) {
+  if (!p) return;
+  prof_release(p->prof);
+  delete p;
+}
+
+}  // extern "C"
+
+namespace pwfs {
+
+int forward_sensor(pwfs_plan_s* p, int i, const float* opd, long long opd_stride, float* out,
+                   long long out_stride, int nf, hipStream_t st) {
+  const SensorPlan& sp = p->s[i];
+  for (int f0 = 0; f0 < nf; f0 += p->chunk) {
+    const int n = std::min(p->chunk, nf - f0);
+    const float* o = opd + (long long)f0 * opd_stride;
+    float* r = out + (long long)f0 * out_stride;
+    int rc;
+    if (sp.desc.precision == PWFS_FP32)
+      rc = forward_fp32(sp, o, opd_stride, r, out_stride, n, p->rbuf, st, &p->prof);
+    else
+      rc = forward_mfma(sp, o, opd_stride, r, out_stride, n, p->rbuf, st, &p->prof);
+    if (rc) return rc;
+  }
+  return PWFS_OK;
+}
+
+}  // namespace pwfs

@@ -1,0 +1,281 @@
+"""Python binding of ``libpwfs.so`` (argument marshalling only).
+
+Every step of the sensor path runs in the library's HIP kernels; this module
+only turns torch tensors and streams into the plain pointers and sizes of the
+C ABI in ``include/pwfs.h``.  There is no fallback: if the library is not
+built, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpwfs.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pwfs.h")
+
+PWFS_OK = 0
+PWFS_EINVAL = -1
+PWFS_EUNSUPPORTED = -2
+PWFS_EWORKSPACE = -3
+PWFS_EHIP = -4
+PWFS_ESTATE = -5
+
+F_REF_SLOPES = 1
+F_FULL_PLANE = 2
+F_LOCAL_NORM = 4
+
+FP32, BF16, BF16X3, FP16X3 = 0, 1, 2, 3
+MAX_LAMBDA = 4
+
+
+class PwfsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pwfs error {code}: {msg}")
+        self.code = code
+
+
+class CSensorDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_pupil", ctypes.c_int32), ("n_fft", ctypes.c_int32), ("n_subap", ctypes.c_int32),
+        ("n_mod", ctypes.c_int32), ("n_lambda", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+        ("diameter_m", ctypes.c_double), ("obstruction", ctypes.c_double),
+        ("pupil_sep_px", ctypes.c_double), ("mod_radius_lod", ctypes.c_double),
+        ("lambda_ref_nm", ctypes.c_double),
+        ("lambda_nm", ctypes.c_double * MAX_LAMBDA), ("lambda_weight", ctypes.c_double * MAX_LAMBDA),
+    ]
+
+
+class CSensorInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_pupil", ctypes.c_int32), ("n_fft", ctypes.c_int32), ("n_subap", ctypes.c_int32),
+        ("n_valid", ctypes.c_int32),
+        ("opd_offset", ctypes.c_size_t), ("intensity_offset", ctypes.c_size_t),
+        ("slope_offset", ctypes.c_size_t), ("opd_stride", ctypes.c_size_t),
+        ("intensity_stride", ctypes.c_size_t), ("slope_stride", ctypes.c_size_t),
+    ]
+
+
+_lib = None
+
+
+def header_symbols() -> list:
+    """Function names declared by include/pwfs.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pwfs_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib() -> ctypes.CDLL:
+    """Loads the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2602_06688_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    i32 = ctypes.c_int
+    L.pwfs_validate.argtypes = [P(CSensorDesc), i32]
+    L.pwfs_workspace_size.argtypes = [P(CSensorDesc), i32, i32, P(ctypes.c_size_t)]
+    L.pwfs_plan.argtypes = [P(CSensorDesc), i32, i32, vp, ctypes.c_size_t, vp, P(vp)]
+    L.pwfs_forward.argtypes = [vp, vp, i32, vp, vp]
+    L.pwfs_slopes.argtypes = [vp, vp, i32, vp, vp, vp]
+    L.pwfs_query.argtypes = [vp, i32, P(CSensorInfo)]
+    L.pwfs_valid_map.argtypes = [vp, i32, P(ctypes.c_uint8)]
+    L.pwfs_last_error.restype = ctypes.c_char_p
+    L.pwfs_last_error.argtypes = []
+    L.pwfs_profile.argtypes = [vp, i32]
+    L.pwfs_profile_read.argtypes = [vp, i32, P(ctypes.c_double), P(ctypes.c_int)]
+    L.pwfs_destroy.argtypes = [vp]
+    L.pwfs_destroy.restype = None
+    for name in ("pwfs_validate", "pwfs_workspace_size", "pwfs_plan", "pwfs_forward", "pwfs_slopes",
+                 "pwfs_query", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def check(rc: int) -> None:
+    if rc != PWFS_OK:
+        raise PwfsError(rc, lib().pwfs_last_error().decode())
+
+
+def to_c(s) -> CSensorDesc:
+    """A C description from any object with the SensorDesc attributes."""
+    d = CSensorDesc()
+    d.n_pupil = int(s.n_pupil)
+    d.n_fft = int(s.n_fft)
+    d.n_subap = int(s.n_subap)
+    d.n_mod = int(s.n_mod)
+    lams = tuple(s.lambdas_nm)
+    ws = tuple(s.lambda_weights)
+    d.n_lambda = len(lams)
+    d.precision = int(getattr(s, "precision", FP32))
+    d.flags = int(getattr(s, "flags", F_REF_SLOPES))
+    d.reserved = 0
+    d.diameter_m = float(getattr(s, "diameter_m", 8.0))
+    d.obstruction = float(s.obstruction)
+    d.pupil_sep_px = float(s.pupil_sep_px)
+    d.mod_radius_lod = float(s.mod_radius_lod)
+    d.lambda_ref_nm = float(s.lambda_ref_nm)
+    for i in range(min(len(lams), MAX_LAMBDA)):
+        d.lambda_nm[i] = float(lams[i])
+        d.lambda_weight[i] = float(ws[i])
+    return d
+
+
+def _descs(sensors) -> ctypes.Array:
+    sensors = list(sensors)
+    arr = (CSensorDesc * len(sensors))()
+    for i, s in enumerate(sensors):
+        arr[i] = s if isinstance(s, CSensorDesc) else to_c(s)
+    return arr
+
+
+def validate(sensors) -> int:
+    """Return code of pwfs_validate (host only)."""
+    arr = _descs(sensors)
+    return lib().pwfs_validate(arr, len(arr))
+
+
+def workspace_size(sensors, max_frames: int) -> int:
+    arr = _descs(sensors)
+    n = ctypes.c_size_t()
+    check(lib().pwfs_workspace_size(arr, len(arr), int(max_frames), ctypes.byref(n)))
+    return n.value
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _dev_ptr(t, name, dtype=None, min_numel=None):
+    import torch
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {min_numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan over one or more sensors; owns its device workspace tensor."""
+
+    def __init__(self, sensors: Sequence, max_frames: int, device=None, stream=None):
+        import torch
+        self.sensors = list(sensors)
+        self._descs = _descs(self.sensors)
+        self.max_frames = int(max_frames)
+        self.device = torch.device(device if device is not None else "cuda")
+        nbytes = workspace_size(self._descs, self.max_frames)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        h = ctypes.c_void_p()
+        check(lib().pwfs_plan(self._descs, len(self._descs), self.max_frames, ctypes.c_void_p(self._ws_ptr),
+                              nbytes, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.info = [self.query(i) for i in range(len(self.sensors))]
+        i0 = self.info[0]
+        self.opd_stride = i0.opd_stride
+        self.intensity_stride = i0.intensity_stride
+        self.slope_stride = i0.slope_stride
+
+    def query(self, sensor: int) -> CSensorInfo:
+        info = CSensorInfo()
+        check(lib().pwfs_query(self._h, int(sensor), ctypes.byref(info)))
+        return info
+
+    def valid_map(self, sensor: int = 0):
+        import numpy as np
+        n = self.info[sensor].n_subap if hasattr(self, "info") else int(self.sensors[sensor].n_subap)
+        buf = (ctypes.c_uint8 * (n * n))()
+        check(lib().pwfs_valid_map(self._h, int(sensor), buf))
+        return np.frombuffer(bytes(buf), dtype=np.uint8).reshape(n, n).astype(bool)
+
+    # -- shapes of a single-sensor plan; multi-sensor plans use packed [F][stride]
+    def _single(self) -> bool:
+        return len(self.sensors) == 1
+
+    def new_intensity(self, n_frames: int):
+        import torch
+        if self._single():
+            N = self.info[0].n_fft
+            return torch.zeros((n_frames, N, N), dtype=torch.float32, device=self.device)
+        return torch.zeros((n_frames, self.intensity_stride), dtype=torch.float32, device=self.device)
+
+    def new_slopes(self, n_frames: int):
+        import torch
+        if self._single():
+            n = self.info[0].n_subap
+            return torch.zeros((n_frames, 2, n, n), dtype=torch.float32, device=self.device)
+        return torch.zeros((n_frames, self.slope_stride), dtype=torch.float32, device=self.device)
+
+    def forward(self, opd, out=None, stream=None):
+        """OPD [F, D, D] (or packed [F, opd_stride]) float32 nm -> intensity."""
+        import torch
+        F = int(opd.shape[0])
+        if out is None:
+            out = self.new_intensity(F)
+        po = _dev_ptr(opd, "opd", torch.float32, F * self.opd_stride)
+        pi = _dev_ptr(out, "intensity", torch.float32, F * self.intensity_stride)
+        check(lib().pwfs_forward(self._h, po, F, pi, _stream_ptr(stream)))
+        return out
+
+    def slopes(self, intensity, out=None, flux=None, stream=None):
+        """intensity -> (slopes, flux [F, n_sensors])."""
+        import torch
+        F = int(intensity.shape[0])
+        if out is None:
+            out = self.new_slopes(F)
+        if flux is None:
+            flux = torch.zeros((F, len(self.sensors)), dtype=torch.float32, device=self.device)
+        pi = _dev_ptr(intensity, "intensity", torch.float32, F * self.intensity_stride)
+        ps = _dev_ptr(out, "slopes", torch.float32, F * self.slope_stride)
+        pf = _dev_ptr(flux, "flux", torch.float32, F * len(self.sensors))
+        check(lib().pwfs_slopes(self._h, pi, F, ps, pf, _stream_ptr(stream)))
+        return out, flux
+
+    def step(self, opd, intensity=None, slopes=None, flux=None, stream=None):
+        """One pass of the whole path: forward then slopes."""
+        I = self.forward(opd, intensity, stream)
+        s, fl = self.slopes(I, slopes, flux, stream)
+        return I, s, fl
+
+    KERNELS = {"rows": 0, "cols": 1, "slopes": 2, "mfma": 3}
+
+    def profile(self, max_launches: int) -> None:
+        """Time the next ``max_launches`` kernel launches with HIP events (0 = off)."""
+        check(lib().pwfs_profile(self._h, int(max_launches)))
+
+    def profile_read(self, kernel: str):
+        """(total ms, launches) of one kernel kind since ``profile`` was called."""
+        t = ctypes.c_double()
+        n = ctypes.c_int()
+        check(lib().pwfs_profile_read(self._h, self.KERNELS[kernel], ctypes.byref(t), ctypes.byref(n)))
+        return t.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pwfs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

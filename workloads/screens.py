@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import math
 import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import scipy.fft
@@ -55,17 +56,19 @@ def von_karman_opd(frames, n_pupil: int, diameter_m: float, r0_m: float, L0_m: f
     o = (M - n_pupil) // 2
     to_nm = r0_lambda_nm / (2.0 * math.pi)
     out = np.empty((len(frames), n_pupil, n_pupil), np.float32)
-    cache = {}
+
+    def draw(pair):
+        rng = np.random.default_rng([int(seed), pair])
+        c = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+        scr = scipy.fft.ifft2(c * amp, workers=1) * (M * M)
+        return scr[o:o + n_pupil, o:o + n_pupil].copy()
+
+    pairs = sorted({int(fr) // 2 for fr in frames})
+    with ThreadPoolExecutor(max_workers=_workers()) as ex:
+        crops = dict(zip(pairs, ex.map(draw, pairs)))
     for i, fr in enumerate(frames):
-        pair, part = divmod(int(fr), 2)
-        if pair not in cache:
-            cache.clear()
-            rng = np.random.default_rng([int(seed), pair])
-            c = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
-            scr = scipy.fft.ifft2(c * amp, workers=_workers()) * (M * M)
-            cache[pair] = scr[o:o + n_pupil, o:o + n_pupil]
-        crop = cache[pair]
-        out[i] = (crop.imag if part else crop.real) * to_nm
+        crop = crops[int(fr) // 2]
+        out[i] = (crop.imag if int(fr) % 2 else crop.real) * to_nm
     return out
 
 
