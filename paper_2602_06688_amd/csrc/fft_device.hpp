@@ -154,8 +154,8 @@ __device__ __forceinline__ void dftp(float2* a) {
 // T lanes per transform; radices of the forward transform in stage order.
 template <int N> struct FftPlan;
 template <> struct FftPlan<64>  { static constexpr int T = 8;  static constexpr int NS = 2; static constexpr int r[2] = {8, 8}; };
-template <> struct FftPlan<128> { static constexpr int T = 16; static constexpr int NS = 3; static constexpr int r[3] = {8, 8, 2}; };
-template <> struct FftPlan<256> { static constexpr int T = 32; static constexpr int NS = 3; static constexpr int r[3] = {8, 8, 4}; };
+template <> struct FftPlan<128> { static constexpr int T = 16; static constexpr int NS = 3; static constexpr int r[3] = {8, 2, 8}; };
+template <> struct FftPlan<256> { static constexpr int T = 32; static constexpr int NS = 3; static constexpr int r[3] = {8, 4, 8}; };
 template <> struct FftPlan<384> { static constexpr int T = 16; static constexpr int NS = 4; static constexpr int r[4] = {8, 8, 2, 3}; };
 template <> struct FftPlan<512> { static constexpr int T = 64; static constexpr int NS = 3; static constexpr int r[3] = {8, 8, 8}; };
 template <> struct FftPlan<768> { static constexpr int T = 32; static constexpr int NS = 4; static constexpr int r[4] = {8, 8, 4, 3}; };
@@ -252,6 +252,124 @@ __device__ __forceinline__ int space_index(int t, int slot) {
   constexpr int R = P::r[0];
   const int i = slot / R, q = slot % R;
   return t + P::T * i + q * (N / R);
+}
+
+// ------------------------------------------- register-twiddle variant ----
+// For plans whose radix list reads the same forwards and backwards, stage s
+// of the inverse transform has the same radix and the same L as stage s of
+// the forward one, so its twiddles are the conjugates of the forward ones.
+// Each lane then keeps the twiddles of all its butterflies in registers for
+// the whole kernel, and the LDS exchange buffer is padded by one float2
+// every 8 to spread the strided Stockham stores over the banks.
+
+template <int N>
+struct Palindromic {
+  static constexpr bool check() {
+    using P = FftPlan<N>;
+    for (int s = 0; s < P::NS; ++s)
+      if (P::r[s] != P::r[P::NS - 1 - s]) return false;
+    return P::NS <= 3;
+  }
+  static constexpr bool value = check();
+};
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
+template <int N> struct PaddedLen { static constexpr int value = N + N / 8; };
+
+template <int N, int S>
+struct StageTw {
+  using SI = StageInfo<N, S, false>;
+  static constexpr int T = FftPlan<N>::T;
+  static constexpr int R = SI::R, L = SI::L, NB = (N / T) / SI::R;
+  float2 w[NB][R - 1];
+  __device__ __forceinline__ void load(int t, const float2* tw) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int k = (t + T * i) % L;
+#pragma unroll
+      for (int q = 1; q < R; ++q) w[i][q - 1] = tw[k * q * (N / (L * R))];
+    }
+  }
+};
+
+template <int N>
+struct TwSet {
+  static constexpr int NS = FftPlan<N>::NS;
+  StageTw<N, 1> s1;
+  StageTw<N, (NS > 2 ? 2 : 1)> s2;
+  __device__ __forceinline__ void load(int t, const float2* tw) {
+    s1.load(t, tw);
+    if constexpr (NS > 2) s2.load(t, tw);
+  }
+};
+
+// conj(w) * a when INV, w * a otherwise
+template <bool INV>
+__device__ __forceinline__ float2 twmul(float2 a, float2 w) {
+  return INV ? make_float2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y) : cmul(a, w);
+}
+
+template <int N, int S, int NZ, bool INV, class TW>
+__device__ __forceinline__ void stage_compute_reg(float2* v, const TW& tw) {
+  constexpr int T = FftPlan<N>::T, V = N / T;
+  using SI = StageInfo<N, S, INV>;
+  constexpr int R = SI::R, NB = V / R;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if constexpr (S > 0) {
+#pragma unroll
+      for (int q = 1; q < R; ++q) v[i * R + q] = twmul<INV>(v[i * R + q], tw.w[i][q - 1]);
+    }
+    dftp<R, NZ, INV>(&v[i * R]);
+  }
+}
+
+template <int N, int R>
+__device__ __forceinline__ void stage_load_pad(float2* v, int t, const float2* buf) {
+  constexpr int T = FftPlan<N>::T, V = N / T, NB = V / R;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[i * R + q] = buf[lds_pad(t + T * i + q * (N / R))];
+}
+
+template <int N, int R, int L>
+__device__ __forceinline__ void stage_store_pad(const float2* v, int t, float2* buf) {
+  constexpr int T = FftPlan<N>::T, V = N / T, NB = V / R;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + T * i;
+    const int base = (j / L) * L * R + (j % L);
+#pragma unroll
+    for (int q = 0; q < R; ++q) buf[lds_pad(base + q * L)] = v[i * R + q];
+  }
+}
+
+template <int N, int S>
+__device__ __forceinline__ const auto& tw_of(const TwSet<N>& tw) {
+  if constexpr (S == 1) return tw.s1;
+  else return tw.s2;
+}
+
+// Same contract as fft_from, for palindromic plans, with register twiddles
+// and a padded buffer of PaddedLen<N> float2.
+template <int N, bool INV, int S, int NZ0>
+__device__ __forceinline__ void fft_reg(float2* v, int t, float2* buf, const TwSet<N>& tw) {
+  using P = FftPlan<N>;
+  using SI = StageInfo<N, S, INV>;
+  static_assert(Palindromic<N>::value, "plan must be palindromic");
+  if constexpr (S > 0) {
+    wave_sync();
+    stage_load_pad<N, SI::R>(v, t, buf);
+    wave_sync();
+    stage_compute_reg<N, S, SI::R, INV>(v, tw_of<N, S>(tw));
+  } else {
+    stage_compute_reg<N, 0, NZ0, INV>(v, tw.s1);
+  }
+  if constexpr (S + 1 < P::NS) {
+    stage_store_pad<N, SI::R, SI::L>(v, t, buf);
+    fft_reg<N, INV, S + 1, NZ0>(v, t, buf, tw);
+  }
 }
 
 }  // namespace pwfs

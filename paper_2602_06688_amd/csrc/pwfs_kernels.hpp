@@ -47,7 +47,7 @@ struct ColArgs {
   const float2* ry;        // [n_lam][n_mod][D] column tilt
   const float2* mcol;      // [n_lam][N] column mask, offset phase, 1/N, sqrt(weight)
   const float2* tw;        // [N]
-  const int* ak;           // [n_mod] distinct-cosine index of each point
+  const int2* kord;        // [n_mod] (point k, distinct-cosine index a), k and n_mod-k adjacent
   float* out;              // sensor's first frame of the chunk; frame stride out_stride
   long long out_stride;
   int D, Dp, Nc, n_a, n_lam, n_mod, colblocks;
@@ -75,24 +75,71 @@ __device__ __forceinline__ int window_coord(int xc, int D, int lo, int hi) {
   return xc < D ? lo + xc : hi + xc - D;
 }
 
+// ------------------------------------------------------ FFT pair core ----
+// One lane-group's "transform, mask, inverse transform" on a row or column
+// held in registers.  Palindromic plans keep twiddles and the mask in
+// registers and exchange through a padded buffer; the others read the LDS
+// twiddle table and use an unpadded buffer.
+template <int N>
+struct BufLen {
+  static constexpr int value = Palindromic<N>::value ? PaddedLen<N>::value : N;
+};
+
+template <int N, int QM>
+struct FftPair {
+  static constexpr bool PAL = Palindromic<N>::value;
+  static constexpr int T = FftPlan<N>::T, V = N / T;
+  static constexpr int RLAST = FftPlan<N>::r[FftPlan<N>::NS - 1];
+  TwSet<N> tw;
+  float2 m[V];
+  const float2* s_tw;
+  float2* buf;
+  int t;
+
+  __device__ __forceinline__ void init(int lane, float2* group_buf, const float2* twiddles) {
+    t = lane;
+    buf = group_buf;
+    s_tw = twiddles;
+    if constexpr (PAL) tw.load(t, twiddles);
+  }
+  // mask values of this lane's frequency slots (mask table in LDS)
+  __device__ __forceinline__ void set_mask(const float2* mask) {
+#pragma unroll
+    for (int s = 0; s < V; ++s) m[s] = mask[freq_index<N>(t, s)];
+  }
+  __device__ __forceinline__ void run(float2* v) {
+    if constexpr (PAL) {
+      fft_reg<N, false, 0, QM>(v, t, buf, tw);
+#pragma unroll
+      for (int s = 0; s < V; ++s) v[s] = cmul(v[s], m[s]);
+      fft_reg<N, true, 0, RLAST>(v, t, buf, tw);
+    } else {
+      fft_from<N, false, 0, QM>(v, t, buf, s_tw);
+#pragma unroll
+      for (int s = 0; s < V; ++s) v[s] = cmul(v[s], m[s]);
+      fft_from<N, true, 0, RLAST>(v, t, buf, s_tw);
+    }
+  }
+};
+
 // ---------------------------------------------------------------- rows ----
 template <int N, int QM>
 __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
   using P = FftPlan<N>;
   constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
-  constexpr int RW = RowTile<N>::RW, RPG = RW / G;
+  constexpr int RW = RowTile<N>::RW, RPG = RW / G, BL = BufLen<N>::value;
   static_assert(RPG >= 1 && RW % G == 0, "row tile");
-  constexpr int RLAST = P::r[P::NS - 1];
 
   extern __shared__ float2 smem[];
   float2* s_tw = smem;
   float2* s_m = s_tw + N;
   float2* s_buf = s_m + N;
-  float2* s_tile = s_buf + G * N;
+  float2* s_tile = s_buf + G * BL;
 
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
   int bid = blockIdx.x;
-  const int agi = bid % p.n_agroups; bid /= p.n_agroups;
+  const int agi = bid % p.n_agroups;
+  bid /= p.n_agroups;
   const int rb = bid % p.rowblocks;
   const int f = bid / p.rowblocks;
   const int y0 = rb * RW;
@@ -103,13 +150,15 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
     s_tw[i] = p.tw[i];
     s_m[i] = p.mrow[i];
   }
-  float2* buf = s_buf + g * N;
   const float* opd = p.opd + (long long)f * p.opd_stride;
+  __syncthreads();
+
+  FftPair<N, QM> fp;
+  fp.init(t, s_buf + g * BL, s_tw);
+  fp.set_mask(s_m);
 
   float2 e0[RPG][NB0][QM];
   int cur_lam = -1;
-  __syncthreads();
-
   for (int la = la0; la < la1; ++la) {
     const int lam = la / p.n_a, a = la % p.n_a;
     if (lam != cur_lam) {
@@ -118,25 +167,22 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
 #pragma unroll
       for (int rr = 0; rr < RPG; ++rr) {
         const int y = y0 + g * RPG + rr;
+        const int yy = min(y, p.D - 1);
 #pragma unroll
         for (int i = 0; i < NB0; ++i)
 #pragma unroll
           for (int q = 0; q < QM; ++q) {
             const int x = t + T * i + q * (N / R0);
-            float2 e = czero();
-            if (y < p.D && x < p.D) {
-              const float amp = p.amp[y * p.D + x];
-              if (amp != 0.f) {
-                // phase in float64, reduced to [-pi, pi] before float32 sincos
-                const double ph = (double)opd[y * p.D + x] * k2p;
-                const double n = rint(ph * 0.15915494309189533577);
-                const float r = (float)fma(-n, 6.283185307179586477, ph);
-                float s, c;
-                sincosf(r, &s, &c);
-                e = make_float2(amp * c, amp * s);
-              }
-            }
-            e0[rr][i][q] = e;
+            const int xx = min(x, p.D - 1);
+            const bool in = (y < p.D) && (x < p.D);
+            const float amp = in ? p.amp[yy * p.D + xx] : 0.f;
+            // phase in float64, reduced to [-pi, pi] before float32 sincos
+            const double ph = (double)opd[yy * p.D + xx] * k2p;
+            const double n = rint(ph * 0.15915494309189533577);
+            const float r = (float)fma(-n, 6.283185307179586477, ph);
+            float sn, cs;
+            sincosf(r, &sn, &cs);
+            e0[rr][i][q] = make_float2(amp * cs, amp * sn);
           }
       }
     }
@@ -151,15 +197,12 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
         for (int q = 0; q < R0; ++q) {
           if (q < QM) {
             const int x = t + T * i + q * (N / R0);
-            v[i * R0 + q] = (x < p.D) ? cmul(e0[rr][i][q], rx[x]) : czero();
+            v[i * R0 + q] = cmul(e0[rr][i][q], rx[min(x, p.D - 1)]);
           } else {
             v[i * R0 + q] = czero();
           }
         }
-      fft_from<N, false, 0, QM>(v, t, buf, s_tw);
-#pragma unroll
-      for (int s = 0; s < V; ++s) v[s] = cmul(v[s], s_m[freq_index<N>(t, s)]);
-      fft_from<N, true, 0, RLAST>(v, t, buf, s_tw);
+      fp.run(v);
 #pragma unroll
       for (int s = 0; s < V; ++s) {
         const int X = space_index<N>(t, s);
@@ -183,7 +226,7 @@ template <int N, int QM>
 __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
   using P = FftPlan<N>;
   constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
-  constexpr int RLAST = P::r[P::NS - 1];
+  constexpr int BL = BufLen<N>::value, NL = NB0 * QM;
 
   extern __shared__ float2 smem[];
   float2* s_tw = smem;
@@ -195,38 +238,71 @@ __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
   const int f = blockIdx.x / p.colblocks;
   const int xc = cb * G + g;
   const bool live = xc < p.Nc;
+  const int xcl = live ? xc : 0;
 
   for (int i = tid; i < N; i += kBlock) s_tw[i] = p.tw[i];
   for (int i = tid; i < p.n_lam * N; i += kBlock) s_m[i] = p.mcol[i];
-  float2* buf = s_buf + g * N;
   __syncthreads();
+
+  FftPair<N, QM> fp;
+  fp.init(t, s_buf + g * BL, s_tw);
+
+  // this lane's input rows and whether they hold pupil data
+  int yy[NL];
+  bool yin[NL];
+#pragma unroll
+  for (int i = 0; i < NB0; ++i)
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      const int y = t + T * i + q * (N / R0);
+      yy[i * QM + q] = min(y, p.D - 1);
+      yin[i * QM + q] = live && (y < p.D);
+    }
 
   float acc[V];
 #pragma unroll
   for (int s = 0; s < V; ++s) acc[s] = 0.f;
 
+  const size_t frame_base = (size_t)f * p.n_lam * p.n_a;
   for (int lam = 0; lam < p.n_lam; ++lam) {
-    const float2* mc = s_m + lam * N;
-    for (int k = 0; k < p.n_mod; ++k) {
-      const int a = p.ak[k];
-      const float2* col = p.rbuf + (((((size_t)f * p.n_lam + lam) * p.n_a + a) * p.Nc) + (live ? xc : 0)) * p.Dp;
-      const float2* ry = p.ry + ((size_t)lam * p.n_mod + k) * p.D;
+    fp.set_mask(s_m + lam * N);
+    const float2* rbl = p.rbuf + ((frame_base + (size_t)lam * p.n_a) * p.Nc + xcl) * p.Dp;
+    const float2* ryl = p.ry + (size_t)lam * p.n_mod * p.D;
+    float2 cn[NL], rn[NL];
+    {
+      const int2 ka = p.kord[0];
+      const float2* col = rbl + (size_t)ka.y * p.Nc * p.Dp;
+      const float2* ry = ryl + (size_t)ka.x * p.D;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        cn[l] = col[yy[l]];
+        rn[l] = ry[yy[l]];
+      }
+    }
+    for (int it = 0; it < p.n_mod; ++it) {
       float2 v[V];
 #pragma unroll
       for (int i = 0; i < NB0; ++i)
 #pragma unroll
         for (int q = 0; q < R0; ++q) {
           if (q < QM) {
-            const int y = t + T * i + q * (N / R0);
-            v[i * R0 + q] = (live && y < p.D) ? cmul(col[y], ry[y]) : czero();
+            const int l = i * QM + q;
+            v[i * R0 + q] = yin[l] ? cmul(cn[l], rn[l]) : czero();
           } else {
             v[i * R0 + q] = czero();
           }
         }
-      fft_from<N, false, 0, QM>(v, t, buf, s_tw);
+      if (it + 1 < p.n_mod) {   // prefetch the next point's column and tilt
+        const int2 ka = p.kord[it + 1];
+        const float2* col = rbl + (size_t)ka.y * p.Nc * p.Dp;
+        const float2* ry = ryl + (size_t)ka.x * p.D;
 #pragma unroll
-      for (int s = 0; s < V; ++s) v[s] = cmul(v[s], mc[freq_index<N>(t, s)]);
-      fft_from<N, true, 0, RLAST>(v, t, buf, s_tw);
+        for (int l = 0; l < NL; ++l) {
+          cn[l] = col[yy[l]];
+          rn[l] = ry[yy[l]];
+        }
+      }
+      fp.run(v);
 #pragma unroll
       for (int s = 0; s < V; ++s) acc[s] += cabs2(v[s]);
     }

@@ -146,7 +146,7 @@ static void sensor_regions(const pwfs_sensor_desc& d, size_t out[kRegions]) {
   out[R_AMP] = sizeof(float) * g.D * g.D;
   out[R_RX] = sizeof(float2) * g.n_lam * g.n_a * g.D;
   out[R_RY] = sizeof(float2) * g.n_lam * g.n_mod * g.D;
-  out[R_AK] = sizeof(int) * g.n_mod;
+  out[R_AK] = sizeof(int) * 2 * g.n_mod;
   out[R_MROW] = sizeof(float2) * g.N;
   out[R_MCOL] = sizeof(float2) * g.n_lam * g.N;
   out[R_TW] = sizeof(float2) * g.N;
@@ -279,8 +279,18 @@ int upload_tables(const pwfs_sensor_desc& d, char* ws, const size_t* off, hipStr
       }
     }
   }
-  std::vector<int> ak(g.n_mod);
-  for (int k = 0; k < g.n_mod; ++k) ak[k] = std::min(k, d.n_mod - k);
+  // visiting order of the modulation points: k and n_mod - k (same cosine,
+  // same row-pass result) back to back; entries are (k, a)
+  std::vector<int> ak;
+  for (int a = 0; a < g.n_a; ++a) {
+    ak.push_back(a);
+    ak.push_back(a);
+    const int k2 = d.n_mod - a;
+    if (a > 0 && k2 != a && k2 < d.n_mod) {
+      ak.push_back(k2);
+      ak.push_back(a);
+    }
+  }
   std::vector<float> mrow(2 * (size_t)g.N), mcol(2 * (size_t)g.n_lam * g.N), tw(2 * (size_t)g.N);
   {
     const std::vector<double> m = mask_table(g, 1.0);
@@ -349,7 +359,7 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
   ra.win_hi = g.win_hi;
   ra.full = g.full;
   for (int l = 0; l < g.n_lam; ++l) ra.two_pi_over_lam[l] = 2.0 * kPi / sp.desc.lambda_nm[l];
-  const size_t lds_rows = sizeof(float2) * (2 * N + G * N + (size_t)g.Nc * (RW + 1));
+  const size_t lds_rows = sizeof(float2) * (2 * N + G * BufLen<N>::value + (size_t)g.Nc * (RW + 1));
   const unsigned grid_rows = (unsigned)((long long)nf * ra.rowblocks * ra.n_agroups);
   int slot = prof->begin(st);
   hipLaunchKernelGGL((k_rows<N, QM>), dim3(grid_rows), dim3(kBlock), lds_rows, st, ra);
@@ -361,7 +371,7 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
   ca.ry = (const float2*)sp.dev[R_RY];
   ca.mcol = (const float2*)sp.dev[R_MCOL];
   ca.tw = (const float2*)sp.dev[R_TW];
-  ca.ak = (const int*)sp.dev[R_AK];
+  ca.kord = (const int2*)sp.dev[R_AK];
   ca.out = out;
   ca.out_stride = out_stride;
   ca.D = g.D;
@@ -374,7 +384,7 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
   ca.win_lo = g.win_lo;
   ca.win_hi = g.win_hi;
   ca.full = g.full;
-  const size_t lds_cols = sizeof(float2) * ((size_t)N + (size_t)g.n_lam * N + (size_t)G * N);
+  const size_t lds_cols = sizeof(float2) * ((size_t)N + (size_t)g.n_lam * N + (size_t)G * BufLen<N>::value);
   slot = prof->begin(st);
   hipLaunchKernelGGL((k_cols<N, QM>), dim3((unsigned)(nf * ca.colblocks)), dim3(kBlock), lds_cols, st, ca);
   HIP_TRY(hipGetLastError(), "launch k_cols");
