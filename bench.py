@@ -40,6 +40,25 @@ def nominal_flops(s) -> dict:
     return {"path": path, "cols": cols}
 
 
+def measured_traffic(kernel: str, frames_per_launch: float):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)[kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for p in rec["sources"]:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sha256"]:
+        return None
+    return rec["hbm_bytes_per_frame"] * frames_per_launch
+
+
 def _oracle_frame(args):
     import numpy as np
     from oracle import pwfs as O
@@ -71,6 +90,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-frames", type=int, default=32)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed region, run one plain device copy of this many MiB "
+                         "(calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the sensor path is measured at its single-GPU shape "
@@ -116,8 +138,16 @@ def main() -> int:
         plan.step(x, I, S, Fl, stream=stream)
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t0
-    kern = {k: plan.profile_read(k) for k in ("rows", "cols", "slopes")}
+    kern = {k: plan.profile_read(k) for k in ("field", "rows", "cols", "slopes")}
     plan.profile(0)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize(dev)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        del src, dst
 
     frames = w.n_frames * args.steps
     value = frames / dt
@@ -149,7 +179,8 @@ def main() -> int:
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic("k_cols", frames_per_launch),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "launches": cols_n,
             "avg_launch_ms": round(cols_ms / max(1, cols_n), 4),
             "frames_per_launch": frames_per_launch,

@@ -164,7 +164,8 @@ int pwfs_valid_map(pwfs_plan_t plan, int sensor, uint8_t* host_out);
  * of this plan (launches beyond n are not timed).  Calling it again resets
  * the pool.  Not for use under graph capture.
  * pwfs_profile_read waits for the recorded events of one kernel kind
- * (0 = row pass, 1 = column pass, 2 = slope stage, 3 = matrix-core forward)
+ * (0 = row pass, 1 = column pass, 2 = slope stage, 3 = matrix-core forward,
+ * 4 = pupil-field pass)
  * and returns their summed duration in ms and their number.
  */
 int pwfs_profile(pwfs_plan_t plan, int max_launches);

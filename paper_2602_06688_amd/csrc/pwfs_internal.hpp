@@ -44,7 +44,7 @@ struct Layout {
 Geometry geometry(const pwfs_sensor_desc& d);
 void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vector<uint8_t>& V);
 int fft_lanes(int N);
-int row_tile(int N);
+size_t rbuf_field_offset(const pwfs_sensor_desc& d, int nf);
 
 // MFMA (split-precision DFT-as-GEMM) form
 bool mfma_supported(const pwfs_sensor_desc& d);
@@ -58,7 +58,7 @@ int forward_mfma(const SensorPlan& sp, const float* opd, long long opd_stride, f
 
 // Optional per-kernel timing: HIP events recorded on the launch stream
 // around each kernel (pool created when profiling is switched on).
-enum KernelId { K_ROWS = 0, K_COLS = 1, K_SLOPES = 2, K_MFMA = 3, kKernelIds = 8 };
+enum KernelId { K_ROWS = 0, K_COLS = 1, K_SLOPES = 2, K_MFMA = 3, K_FIELD = 4, kKernelIds = 8 };
 
 struct Prof {
   bool on = false;

@@ -25,21 +25,28 @@ namespace pwfs {
 constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
 
 // rows of one row-pass workgroup tile
-template <int N> struct RowTile { static constexpr int RW = 16; };
+template <int N> struct RowTile { static constexpr int RW = 8; };
 template <> struct RowTile<64> { static constexpr int RW = 32; };
-template <> struct RowTile<768> { static constexpr int RW = 8; };
+template <> struct RowTile<128> { static constexpr int RW = 16; };
+template <> struct RowTile<384> { static constexpr int RW = 16; };
 
-struct RowArgs {
+struct FieldArgs {
   const float* opd;        // sensor's first frame of the chunk; frame stride opd_stride
   const float* amp;        // [D][D] pupil amplitude
+  float2* field;           // [frames][n_lam][D][D]
+  long long opd_stride;
+  int D, n_lam;
+  double two_pi_over_lam[4];
+};
+
+struct RowArgs {
+  const float2* field;     // [frames][n_lam][D][D] pupil field A exp(i phi)
   const float2* rx;        // [n_lam][n_a][D] row tilt (modulation x-part, half-pixel tilt)
   const float2* mrow;      // [N] row mask with pupil-offset phase and 1/N
   const float2* tw;        // [N] exp(-2 pi i n / N)
   float2* rbuf;            // [frames][n_lam][n_a][Nc][Dp]
-  long long opd_stride;
   int D, Dp, Nc, n_a, n_lam, n_la, ag, n_agroups, rowblocks;
   int win_lo, win_hi, full;
-  double two_pi_over_lam[4];
 };
 
 struct ColArgs {
@@ -122,12 +129,32 @@ struct FftPair {
   }
 };
 
+// --------------------------------------------------------------- field ----
+// E0 = A exp(i 2 pi OPD / lambda): phase formed and reduced to [-pi, pi] in
+// float64, then float32 sincos.
+__global__ __launch_bounds__(kBlock) void k_field(FieldArgs p) {
+  const int DD = p.D * p.D;
+  const int blocks = (DD + kBlock - 1) / kBlock;
+  const int b = blockIdx.x % blocks;
+  const int fl = blockIdx.x / blocks;     // frame * n_lam + lam
+  const int lam = fl % p.n_lam, f = fl / p.n_lam;
+  const int i = b * kBlock + threadIdx.x;
+  if (i >= DD) return;
+  const double ph = (double)p.opd[(long long)f * p.opd_stride + i] * p.two_pi_over_lam[lam];
+  const double n = rint(ph * 0.15915494309189533577);
+  const float r = (float)fma(-n, 6.283185307179586477, ph);
+  float sn, cs;
+  sincosf(r, &sn, &cs);
+  const float a = p.amp[i];
+  p.field[(size_t)fl * DD + i] = make_float2(a * cs, a * sn);
+}
+
 // ---------------------------------------------------------------- rows ----
 template <int N, int QM>
 __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
   using P = FftPlan<N>;
   constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
-  constexpr int RW = RowTile<N>::RW, RPG = RW / G, BL = BufLen<N>::value;
+  constexpr int RW = RowTile<N>::RW, RPG = RW / G, BL = BufLen<N>::value, NL = NB0 * QM;
   static_assert(RPG >= 1 && RW % G == 0, "row tile");
 
   extern __shared__ float2 smem[];
@@ -150,58 +177,58 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
     s_tw[i] = p.tw[i];
     s_m[i] = p.mrow[i];
   }
-  const float* opd = p.opd + (long long)f * p.opd_stride;
   __syncthreads();
 
   FftPair<N, QM> fp;
   fp.init(t, s_buf + g * BL, s_tw);
   fp.set_mask(s_m);
 
-  float2 e0[RPG][NB0][QM];
-  int cur_lam = -1;
+  // this lane's input columns
+  int xx[NL];
+  bool xin[NL];
+#pragma unroll
+  for (int i = 0; i < NB0; ++i)
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      const int x = t + T * i + q * (N / R0);
+      xx[i * QM + q] = min(x, p.D - 1);
+      xin[i * QM + q] = x < p.D;
+    }
+
   for (int la = la0; la < la1; ++la) {
     const int lam = la / p.n_a, a = la % p.n_a;
-    if (lam != cur_lam) {
-      cur_lam = lam;
-      const double k2p = p.two_pi_over_lam[lam];
-#pragma unroll
-      for (int rr = 0; rr < RPG; ++rr) {
-        const int y = y0 + g * RPG + rr;
-        const int yy = min(y, p.D - 1);
-#pragma unroll
-        for (int i = 0; i < NB0; ++i)
-#pragma unroll
-          for (int q = 0; q < QM; ++q) {
-            const int x = t + T * i + q * (N / R0);
-            const int xx = min(x, p.D - 1);
-            const bool in = (y < p.D) && (x < p.D);
-            const float amp = in ? p.amp[yy * p.D + xx] : 0.f;
-            // phase in float64, reduced to [-pi, pi] before float32 sincos
-            const double ph = (double)opd[yy * p.D + xx] * k2p;
-            const double n = rint(ph * 0.15915494309189533577);
-            const float r = (float)fma(-n, 6.283185307179586477, ph);
-            float sn, cs;
-            sincosf(r, &sn, &cs);
-            e0[rr][i][q] = make_float2(amp * cs, amp * sn);
-          }
-      }
-    }
+    const float2* e0 = p.field + ((size_t)f * p.n_lam + lam) * p.D * p.D;
     const float2* rx = p.rx + (size_t)la * p.D;
+    float2 rxv[NL];
 #pragma unroll
+    for (int l = 0; l < NL; ++l) rxv[l] = xin[l] ? rx[xx[l]] : czero();
+    float2 en[NL];
+    {
+      const int yy = min(y0 + g * RPG, p.D - 1);
+#pragma unroll
+      for (int l = 0; l < NL; ++l) en[l] = e0[(size_t)yy * p.D + xx[l]];
+    }
+#pragma unroll 1
     for (int rr = 0; rr < RPG; ++rr) {
       const int yl = g * RPG + rr;
+      const bool yin = y0 + yl < p.D;
       float2 v[V];
 #pragma unroll
       for (int i = 0; i < NB0; ++i)
 #pragma unroll
         for (int q = 0; q < R0; ++q) {
           if (q < QM) {
-            const int x = t + T * i + q * (N / R0);
-            v[i * R0 + q] = cmul(e0[rr][i][q], rx[min(x, p.D - 1)]);
+            const int l = i * QM + q;
+            v[i * R0 + q] = yin ? cmul(en[l], rxv[l]) : czero();
           } else {
             v[i * R0 + q] = czero();
           }
         }
+      if (rr + 1 < RPG) {   // prefetch the next row of the field
+        const int yy = min(y0 + yl + 1, p.D - 1);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) en[l] = e0[(size_t)yy * p.D + xx[l]];
+      }
       fp.run(v);
 #pragma unroll
       for (int s = 0; s < V; ++s) {

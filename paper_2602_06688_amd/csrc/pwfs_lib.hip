@@ -157,10 +157,18 @@ static void sensor_regions(const pwfs_sensor_desc& d, size_t out[kRegions]) {
   out[R_MFMA] = mfma_table_bytes(d);
 }
 
+// per frame: the row-pass output [n_lam][n_a][Nc][Dp], then the pupil field
+// [n_lam][D][D] (the field block of a pass sits after all frames' R blocks)
 size_t rbuf_frame_bytes(const pwfs_sensor_desc& d) {
   const Geometry g = geometry(d);
   if (d.precision != PWFS_FP32) return mfma_scratch_frame_bytes(d);
-  return sizeof(float2) * (size_t)g.n_lam * g.n_a * g.Nc * g.Dp;
+  return sizeof(float2) * ((size_t)g.n_lam * g.n_a * g.Nc * g.Dp + (size_t)g.n_lam * g.D * g.D);
+}
+
+// float2 offset of the field block of a pass of nf frames
+size_t rbuf_field_offset(const pwfs_sensor_desc& d, int nf) {
+  const Geometry g = geometry(d);
+  return (size_t)nf * g.n_lam * g.n_a * g.Nc * g.Dp;
 }
 
 int choose_chunk(const pwfs_sensor_desc* s, int n, int max_frames) {
@@ -189,14 +197,6 @@ int fft_lanes(int N) {
     case 384: return FftPlan<384>::T;
     case 512: return FftPlan<512>::T;
     default: return FftPlan<768>::T;
-  }
-}
-
-int row_tile(int N) {
-  switch (N) {
-    case 64: return RowTile<64>::RW;
-    case 768: return RowTile<768>::RW;
-    default: return 16;
   }
 }
 
@@ -333,14 +333,30 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
                        long long out_stride, int nf, float2* rbuf, hipStream_t st, Prof* prof) {
   constexpr int T = FftPlan<N>::T, G = kBlock / T, RW = RowTile<N>::RW;
   const Geometry& g = sp.g;
+  const size_t field_elems = (size_t)nf * g.n_lam * g.D * g.D;
+  float2* field = rbuf + rbuf_field_offset(sp.desc, nf);
+  {
+    FieldArgs fa{};
+    fa.opd = opd;
+    fa.amp = (const float*)sp.dev[R_AMP];
+    fa.field = field;
+    fa.opd_stride = opd_stride;
+    fa.D = g.D;
+    fa.n_lam = g.n_lam;
+    for (int l = 0; l < g.n_lam; ++l) fa.two_pi_over_lam[l] = 2.0 * kPi / sp.desc.lambda_nm[l];
+    const int blocks = (g.D * g.D + kBlock - 1) / kBlock;
+    const int fslot = prof->begin(st);
+    hipLaunchKernelGGL(k_field, dim3((unsigned)(nf * g.n_lam * blocks)), dim3(kBlock), 0, st, fa);
+    HIP_TRY(hipGetLastError(), "launch k_field");
+    prof->end(fslot, st, K_FIELD);
+  }
+  (void)field_elems;
   RowArgs ra{};
-  ra.opd = opd;
-  ra.amp = (const float*)sp.dev[R_AMP];
+  ra.field = field;
   ra.rx = (const float2*)sp.dev[R_RX];
   ra.mrow = (const float2*)sp.dev[R_MROW];
   ra.tw = (const float2*)sp.dev[R_TW];
   ra.rbuf = rbuf;
-  ra.opd_stride = opd_stride;
   ra.D = g.D;
   ra.Dp = g.Dp;
   ra.Nc = g.Nc;
@@ -358,7 +374,6 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
   ra.win_lo = g.win_lo;
   ra.win_hi = g.win_hi;
   ra.full = g.full;
-  for (int l = 0; l < g.n_lam; ++l) ra.two_pi_over_lam[l] = 2.0 * kPi / sp.desc.lambda_nm[l];
   const size_t lds_rows = sizeof(float2) * (2 * N + G * BufLen<N>::value + (size_t)g.Nc * (RW + 1));
   const unsigned grid_rows = (unsigned)((long long)nf * ra.rowblocks * ra.n_agroups);
   int slot = prof->begin(st);

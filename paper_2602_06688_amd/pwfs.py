@@ -256,7 +256,7 @@ class Plan:
         s, fl = self.slopes(I, slopes, flux, stream)
         return I, s, fl
 
-    KERNELS = {"rows": 0, "cols": 1, "slopes": 2, "mfma": 3}
+    KERNELS = {"rows": 0, "cols": 1, "slopes": 2, "mfma": 3, "field": 4}
 
     def profile(self, max_launches: int) -> None:
         """Time the next ``max_launches`` kernel launches with HIP events (0 = off)."""
