@@ -23,6 +23,7 @@ if ROOT not in sys.path:
 
 METRIC = "PWFS frames/s @160px pupil,48 mod pts: plain vs MFMA/surrogate at stated error"
 FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0}   # MI355X dense matrix peaks
 
 
 def nominal_flops(s) -> dict:
@@ -38,6 +39,69 @@ def nominal_flops(s) -> dict:
     path = K * (2 * fft2d + 9.0 * N * N + 6.0 * D * D)
     cols = K * (2 * 5.0 * N * N * math.log2(N) + 9.0 * N * N)
     return {"path": path, "cols": cols}
+
+
+def mfma_flops(s, terms: int) -> dict:
+    """Executed matrix-core flops per frame of the DFT-as-GEMM form: stage 1
+    (2 Nc x D x Kp per distinct cosine) and stage 2 (2 Nc x Nc x Kp per point),
+    2 flops per MAC, times the number of split products."""
+    D, N = s.n_pupil, s.n_fft
+    Nc = N if (s.flags & 2) else 2 * D
+    Kp = (2 * D + 31) // 32 * 32
+    L = len(s.lambdas_nm)
+    n_a = min(s.n_mod // 2 + 1, s.n_mod)
+    g1 = L * n_a * 2 * Nc * D * Kp * 2.0 * terms
+    g2 = L * s.n_mod * 2 * Nc * Nc * Kp * 2.0 * terms
+    return {"stage1": g1, "stage2": g2}
+
+
+def time_form(P, torch, s, x, n_frames, steps, warmup, ref_I, ref_S, dev, stream, label, terms, dtype):
+    """frames/s of one precision form, its error against the FP32 path's
+    outputs (ref_I, ref_S) on the same frames, and its matrix-core roofline."""
+    plan = P.Plan([s], max_frames=n_frames, device=dev, stream=stream)
+    I = plan.new_intensity(n_frames)
+    S = plan.new_slopes(n_frames)
+    Fl = torch.zeros((n_frames, 1), dtype=torch.float32, device=dev)
+    for _ in range(warmup):
+        plan.step(x, I, S, Fl, stream=stream)
+    torch.cuda.synchronize(dev)
+    plan.profile(4096)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.step(x, I, S, Fl, stream=stream)
+    torch.cuda.synchronize(dev)
+    dt = time.perf_counter() - t0
+    g2_ms, g2_n = plan.profile_read("mfma")
+    g1_ms, g1_n = plan.profile_read("rows")
+    plan.profile(0)
+    valid = torch.from_numpy(plan.valid_map(0)).to(dev)
+    D = s.n_pupil
+    win = [(r, c) for r in (s.n_fft // 2 - int(s.pupil_sep_px) // 2 - D // 2,
+                            s.n_fft // 2 + int(s.pupil_sep_px) // 2 - D // 2)
+           for c in (s.n_fft // 2 - int(s.pupil_sep_px) // 2 - D // 2,
+                     s.n_fft // 2 + int(s.pupil_sep_px) // 2 - D // 2)]
+    a = torch.stack([I[:, r:r + D, c:c + D] for r, c in win], 1).reshape(n_frames, -1).double()
+    b = torch.stack([ref_I[:, r:r + D, c:c + D] for r, c in win], 1).reshape(n_frames, -1).double()
+    ie = ((a - b).norm(dim=1) / b.norm(dim=1)).max().item()
+    sa = S.double()[:, :, valid]
+    sb = ref_S.double()[:, :, valid]
+    se = ((sa - sb).norm() / sb.norm()).item()
+    fl = mfma_flops(s, terms)
+    frames = n_frames * steps
+    ach = fl["stage2"] * frames / (g2_ms / 1e3) / 1e12 if g2_ms > 0 else None
+    peak = MFMA_PEAK_TFLOPS[dtype]
+    out = {"value": round(frames / dt, 2), "unit": "frames/s", "ms_per_step": round(dt / steps * 1e3, 4),
+           "intensity_rel_err_max_vs_fp32": ie, "slope_rel_rms_vs_fp32": se,
+           "roofline": {"kernel": "k_mfma_cols (stage 2: e_k = Qy_k T, |e|^2 accumulate)", "bound": "mfma",
+                        "achieved": round(ach, 2) if ach else None, "peak": peak, "unit": "TFLOP/s",
+                        "frac": round(ach / peak, 4) if ach else None, "traffic": None,
+                        "avg_launch_ms": round(g2_ms / max(1, g2_n), 4), "flops_per_frame": fl["stage2"]},
+           "stage1_ms_per_step": round(g1_ms / steps, 3), "stage2_ms_per_step": round(g2_ms / steps, 3)}
+    plan.close()
+    print(f"# {label}: {out['value']:.0f} frames/s, intensity err {ie:.2e}, slope err {se:.2e}",
+          file=sys.stderr, flush=True)
+    return out
 
 
 def measured_traffic(kernel: str, frames_per_launch: float):
@@ -90,6 +154,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-frames", type=int, default=32)
+    ap.add_argument("--no-forms", action="store_true", help="time only the plain FP32 path")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -149,6 +214,15 @@ def main() -> int:
         torch.cuda.synchronize(dev)
         del src, dst
 
+    forms = {}
+    if not args.no_forms:
+        from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16X3
+        for label, prec, terms, dt_name in (("mfma_bf16x3", PREC_BF16X3, 3, "bf16"),
+                                            ("mfma_fp16x3", PREC_FP16X3, 3, "fp16"),
+                                            ("mfma_bf16", PREC_BF16, 1, "bf16")):
+            forms[label] = time_form(P, torch, s.with_(precision=prec), x, w.n_frames, max(2, args.steps // 2),
+                                     1, I, S, dev, stream, label, terms, dt_name)
+
     frames = w.n_frames * args.steps
     value = frames / dt
     flops = nominal_flops(s)
@@ -193,6 +267,7 @@ def main() -> int:
             "flops_per_frame": flops["path"],
             "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
         },
+        "forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include "fft_device.hpp"
+#include "pwfs_geom.hpp"
 
 namespace pwfs {
 
@@ -71,16 +72,6 @@ struct SlopeArgs {
   int N, n, b, n_valid, local_norm;
   int org_r[4], org_c[4];  // image origins
 };
-
-// compact index of plane coordinate X in window mode, -1 if outside
-__device__ __forceinline__ int window_index(int X, int D, int lo, int hi) {
-  if (X >= lo && X < lo + D) return X - lo;
-  if (X >= hi && X < hi + D) return X - hi + D;
-  return -1;
-}
-__device__ __forceinline__ int window_coord(int xc, int D, int lo, int hi) {
-  return xc < D ? lo + xc : hi + xc - D;
-}
 
 // ------------------------------------------------------ FFT pair core ----
 // One lane-group's "transform, mask, inverse transform" on a row or column

@@ -179,8 +179,13 @@ int choose_chunk(const pwfs_sensor_desc* s, int n, int max_frames) {
   for (int i = 0; i < n; ++i) {
     const Geometry g = geometry(s[i]);
     per = std::max(per, rbuf_frame_bytes(s[i]));
-    const int G = kBlock / fft_lanes(g.N);
-    const int colwg = (g.Nc + G - 1) / G;
+    int colwg;
+    if (s[i].precision == PWFS_FP32) {
+      const int G = kBlock / fft_lanes(g.N);
+      colwg = (g.Nc + G - 1) / G;
+    } else {   // matrix-core form: one 128 x 128 tile grid of stage 2 per frame
+      colwg = ((2 * g.Nc + 127) / 128) * ((g.Nc + 127) / 128);
+    }
     want = std::max(want, (2048 + colwg - 1) / colwg);
   }
   const size_t cap = (size_t)1 << 30;

@@ -1,18 +1,498 @@
-// pwfs_mfma.hip -- split-precision DFT-as-GEMM form of the forward model.
+// pwfs_mfma.hip -- the forward model as dense complex matrix products on the
+// gfx950 matrix cores, in bf16 (one term) or bf16/fp16 hi/lo split (three
+// terms) with fp32 accumulation.
+//
+// Because the mask and the tilts are separable, the padded 2-D chain of one
+// modulation point is e_k = Qy_k E0 Qx_a^T with
+//   P[Y][x]   = h[o + x] p[(Y - o - x) mod N],  p = IDFT(m)  (N_out x D),
+//   Qx_a[X][x] = P[X][x] exp(i 2 pi r x_c cos t_a / D),
+//   Qy_k[Y][y] = P[Y][y] exp(i 2 pi r y_c sin t_k / D),
+// built in float64 on the host.  Stage 1 forms T_a = E0 Qx_a^T once per
+// distinct cosine a (shared by k and n_mod - k) for all frames at once; stage
+// 2 forms e_k = Qy_k T_a(k) and accumulates c_lambda |e_k|^2 over k and
+// wavelength in registers (c_lambda = w_lambda / (n_mod sum A^2)).
+//
+// Complex products run as real products on an interleaved block form: the
+// left operand's rows come in pairs (Re Q[X][.], -Im Q[X][.]) and
+// (Im Q[X][.], Re Q[X][.]) over K = (real parts, imaginary parts) of the
+// right operand, so output rows 2X and 2X + 1 hold Re and Im of one element,
+// in the same lane of the accumulator layout.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "mfma_gemm.hpp"
+#include "pwfs_geom.hpp"
 #include "pwfs_internal.hpp"
 
 namespace pwfs {
 
-bool mfma_supported(const pwfs_sensor_desc&) { return false; }
-size_t mfma_table_bytes(const pwfs_sensor_desc&) { return 0; }
-size_t mfma_scratch_frame_bytes(const pwfs_sensor_desc&) { return 0; }
-int upload_mfma_tables(const pwfs_sensor_desc&, char*, hipStream_t, std::vector<std::vector<char>>&, double) {
-  return PWFS_EUNSUPPORTED;
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+struct MGeom {
+  int D, N, Nc, Kp, M, n_a, n_lam, n_mod, planes;
+  bool f16;
+};
+
+MGeom mgeom(const pwfs_sensor_desc& d) {
+  const Geometry g = geometry(d);
+  MGeom m;
+  m.D = g.D;
+  m.N = g.N;
+  m.Nc = g.Nc;
+  m.Kp = (2 * g.D + kGemmBK - 1) / kGemmBK * kGemmBK;
+  m.M = 2 * g.Nc;
+  m.n_a = g.n_a;
+  m.n_lam = g.n_lam;
+  m.n_mod = g.n_mod;
+  m.planes = d.precision == PWFS_BF16 ? 1 : 2;
+  m.f16 = d.precision == PWFS_FP16X3;
+  return m;
 }
-int forward_mfma(const SensorPlan&, const float*, long long, float*, long long, int, void*, hipStream_t, Prof*) {
-  return PWFS_EUNSUPPORTED;
+
+// host-side conversions (round to nearest even)
+uint16_t h_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float h_bf16_f(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+uint16_t h_f16(float xf) {
+  // IEEE binary16, round to nearest even, with subnormals; |x| < 65504 here
+  const double x = xf;
+  const uint16_t sign = std::signbit(x) ? 0x8000 : 0;
+  const double a = std::fabs(x);
+  if (a == 0.0) return sign;
+  int e;
+  std::frexp(a, &e);            // a = f 2^e, f in [0.5, 1)
+  int ex = e - 1;               // a = 1.m 2^ex
+  if (ex < -14) ex = -14;       // subnormal range shares the exponent of 2^-14
+  const double q = std::ldexp(a, 10 - ex);   // mantissa units
+  double r = std::nearbyint(q);             // ties to even (default rounding mode)
+  uint32_t mant = (uint32_t)r;
+  int bexp = ex + 15;
+  if (mant >= 2048u) {          // rounding carried into the next binade
+    mant >>= 1;
+    ++bexp;
+  }
+  if (mant < 1024u) return (uint16_t)(sign | mant);   // subnormal
+  if (bexp >= 31) return (uint16_t)(sign | 0x7C00);
+  return (uint16_t)(sign | (bexp << 10) | (mant & 0x3FFu));
+}
+float h_f16_f(uint16_t h) {
+  const int e = (h >> 10) & 31, m = h & 1023;
+  const double s = (h & 0x8000) ? -1.0 : 1.0;
+  if (e == 0) return (float)(s * std::ldexp((double)m, -24));
+  return (float)(s * std::ldexp(1.0 + m / 1024.0, e - 15));
+}
+
+void host_split(float x, bool f16, uint16_t& hi, uint16_t& lo) {
+  if (f16) {
+    hi = h_f16(x);
+    lo = h_f16((x - h_f16_f(hi)) * 2048.f);
+  } else {
+    hi = h_bf16(x);
+    lo = h_bf16(x - h_bf16_f(hi));
+  }
+}
+
+// ---------------------------------------------------------------- kernels --
+struct SplitFieldArgs {
+  const float* opd;       // first frame of the pass, frame stride opd_stride
+  const float* amp;       // [D][D]
+  uint16_t* out;          // plane 0 [n_lam][F][D][Kp], plane 1 follows at +plane
+  long long opd_stride, plane;
+  int D, Kp, F, n_lam, planes;
+  double two_pi_over_lam[4];
+};
+
+template <bool F16>
+__global__ __launch_bounds__(256) void k_field_split(SplitFieldArgs p) {
+  const long long total = (long long)p.n_lam * p.F * p.D * p.Kp;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int kk = (int)(i % p.Kp);
+  long long r = i / p.Kp;
+  const int y = (int)(r % p.D);
+  r /= p.D;
+  const int f = (int)(r % p.F);
+  const int lam = (int)(r / p.F);
+  float v = 0.f;
+  if (kk < 2 * p.D) {
+    const int x = kk % p.D;
+    const double ph = (double)p.opd[(long long)f * p.opd_stride + y * p.D + x] * p.two_pi_over_lam[lam];
+    const double n = rint(ph * 0.15915494309189533577);
+    const float red = (float)fma(-n, 6.283185307179586477, ph);
+    float sn, cs;
+    sincosf(red, &sn, &cs);
+    v = p.amp[y * p.D + x] * (kk < p.D ? cs : sn);
+  }
+  uint16_t hi, lo;
+  if (p.planes == 2) {
+    split16<F16>(v, hi, lo);
+    p.out[i] = hi;
+    p.out[p.plane + i] = lo;
+  } else {
+    p.out[i] = F16 ? f32_to_f16_rne(v) : f32_to_bf16_rne(v);
+  }
+}
+
+struct G1Args {
+  const uint16_t* a;      // Qx'' plane 0 [n_lam][n_a][M][Kp]; plane 1 at +a_plane
+  const uint16_t* b;      // split field plane 0 [n_lam][F][D][Kp]; plane 1 at +b_plane
+  uint16_t* t;            // T plane 0 [F][n_lam][n_a][Nc][Kp]; plane 1 at +t_plane
+  long long a_plane, b_plane, t_plane;
+  int M, F, D, Kp, Nc, n_a, n_lam, mtiles, ntiles;
+};
+
+template <int NPL, bool F16>
+__global__ __launch_bounds__(256) void k_mfma_rows(G1Args p) {
+  extern __shared__ uint4 lds_raw[];
+  uint16_t* lds = (uint16_t*)lds_raw;
+  using E = MfmaTile<NPL, F16>;
+  const int tid = threadIdx.x;
+  int bid = blockIdx.x;
+  const int nt = bid % p.ntiles;
+  bid /= p.ntiles;
+  const int mt = bid % p.mtiles;
+  const int la = bid / p.mtiles;          // lam * n_a + a
+  const int lam = la / p.n_a, a = la % p.n_a;
+  const int m0 = mt * kGemmTile, n0 = nt * kGemmTile;
+  const int NF = p.F * p.D;
+  typename E::Ops ops;
+#pragma unroll
+  for (int pl = 0; pl < NPL; ++pl) {
+    ops.a[pl] = p.a + pl * p.a_plane + ((long long)la * p.M + m0) * p.Kp;
+    ops.b[pl] = p.b + pl * p.b_plane + ((long long)lam * NF + n0) * p.Kp;
+  }
+  E eng;
+  eng.zero();
+  eng.run(ops, p.Kp, p.M - m0, p.Kp, NF - n0, p.Kp, lds, tid);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int row, col;
+        E::coord(tid, i, j, e, row, col);
+        const int m = m0 + row, n = n0 + col;
+        if (m >= p.M || n >= NF) continue;
+        const int X = m >> 1, c = m & 1;
+        const int f = n / p.D, y = n - f * p.D;
+        const long long o = ((((long long)f * p.n_lam + lam) * p.n_a + a) * p.Nc + X) * p.Kp + c * p.D + y;
+        const float v = eng.value(i, j, e);
+        if constexpr (NPL == 2) {
+          uint16_t hi, lo;
+          split16<F16>(v, hi, lo);
+          p.t[o] = hi;
+          p.t[p.t_plane + o] = lo;
+        } else {
+          p.t[o] = F16 ? f32_to_f16_rne(v) : f32_to_bf16_rne(v);
+        }
+        // the K padding [2D, Kp) of this row must hold zeros for stage 2
+        if (c == 1)
+          for (int z = y; z < p.Kp - 2 * p.D; z += p.D) {
+            p.t[o + p.D + z - y] = 0;
+            if constexpr (NPL == 2) p.t[p.t_plane + o + p.D + z - y] = 0;
+          }
+      }
+}
+
+struct G2Args {
+  const uint16_t* a;      // Qy'' plane 0 [n_lam][n_mod][M][Kp]; plane 1 at +a_plane
+  const uint16_t* t;      // T as written by stage 1
+  const int2* kord;       // [n_mod] (k, a)
+  float* out;             // first frame of the pass, frame stride out_stride
+  long long a_plane, t_plane, out_stride;
+  int M, Nc, N, D, Kp, n_a, n_lam, n_mod, mtiles, ntiles, win_lo, win_hi, full;
+  float scale[4];
+};
+
+template <int NPL, bool F16>
+__global__ __launch_bounds__(256) void k_mfma_cols(G2Args p) {
+  extern __shared__ uint4 lds_raw[];
+  uint16_t* lds = (uint16_t*)lds_raw;
+  using E = MfmaTile<NPL, F16>;
+  const int tid = threadIdx.x;
+  int bid = blockIdx.x;
+  const int nt = bid % p.ntiles;
+  bid /= p.ntiles;
+  const int mt = bid % p.mtiles;
+  const int f = bid / p.mtiles;
+  const int m0 = mt * kGemmTile, n0 = nt * kGemmTile;
+
+  float inten[2][2][8];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) inten[i][j][e] = 0.f;
+
+  E eng;
+  for (int lam = 0; lam < p.n_lam; ++lam) {
+    const float sc = p.scale[lam];
+    for (int it = 0; it < p.n_mod; ++it) {
+      const int2 ka = p.kord[it];
+      typename E::Ops ops;
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl) {
+        ops.a[pl] = p.a + pl * p.a_plane + (((long long)lam * p.n_mod + ka.x) * p.M + m0) * p.Kp;
+        ops.b[pl] = p.t + pl * p.t_plane + ((((long long)f * p.n_lam + lam) * p.n_a + ka.y) * p.Nc + n0) * p.Kp;
+      }
+      eng.zero();
+      eng.run(ops, p.Kp, p.M - m0, p.Kp, p.Nc - n0, p.Kp, lds, tid);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int e = 0; e < 16; e += 2) {
+            const float re = eng.value(i, j, e), im = eng.value(i, j, e + 1);
+            inten[i][j][e >> 1] += sc * (re * re + im * im);
+          }
+    }
+  }
+  float* out = p.out + (long long)f * p.out_stride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; e += 2) {
+        int row, col;
+        E::coord(tid, i, j, e, row, col);
+        const int Yc = (m0 + row) >> 1, Xc = n0 + col;
+        if (Yc >= p.Nc || Xc >= p.Nc) continue;
+        const int Y = p.full ? Yc : window_coord(Yc, p.D, p.win_lo, p.win_hi);
+        const int X = p.full ? Xc : window_coord(Xc, p.D, p.win_lo, p.win_hi);
+        out[(long long)Y * p.N + X] = inten[i][j][e >> 1];
+      }
+}
+
+template <int NPL, bool F16>
+int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os, float* out, long long ost, int nf,
+           void* scratch, hipStream_t st, Prof* prof) {
+  const Geometry& g = sp.g;
+  uint16_t* field = (uint16_t*)scratch;
+  const long long field_plane = (long long)m.n_lam * nf * m.D * m.Kp;
+  uint16_t* T = field + field_plane * m.planes;
+  const long long t_plane = (long long)nf * m.n_lam * m.n_a * m.Nc * m.Kp;
+  const uint16_t* tab = (const uint16_t*)sp.dev[R_MFMA];
+  const long long qx_plane = (long long)m.n_lam * m.n_a * m.M * m.Kp;
+  const long long qy_plane = (long long)m.n_lam * m.n_mod * m.M * m.Kp;
+  const uint16_t* qx = tab;
+  const uint16_t* qy = tab + qx_plane * m.planes;
+
+  SplitFieldArgs fa{};
+  fa.opd = opd;
+  fa.amp = (const float*)sp.dev[R_AMP];
+  fa.out = field;
+  fa.opd_stride = os;
+  fa.plane = field_plane;
+  fa.D = m.D;
+  fa.Kp = m.Kp;
+  fa.F = nf;
+  fa.n_lam = m.n_lam;
+  fa.planes = m.planes;
+  for (int l = 0; l < m.n_lam; ++l) fa.two_pi_over_lam[l] = 2.0 * kPi / sp.desc.lambda_nm[l];
+  const unsigned fblocks = (unsigned)((field_plane + 255) / 256);
+  int slot = prof->begin(st);
+  hipLaunchKernelGGL((k_field_split<F16>), dim3(fblocks), dim3(256), 0, st, fa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return PWFS_EHIP;
+  prof->end(slot, st, K_FIELD);
+
+  const size_t lds = MfmaTile<NPL, F16>::lds_bytes();
+  G1Args a1{};
+  a1.a = qx;
+  a1.b = field;
+  a1.t = T;
+  a1.a_plane = qx_plane;
+  a1.b_plane = field_plane;
+  a1.t_plane = t_plane;
+  a1.M = m.M;
+  a1.F = nf;
+  a1.D = m.D;
+  a1.Kp = m.Kp;
+  a1.Nc = m.Nc;
+  a1.n_a = m.n_a;
+  a1.n_lam = m.n_lam;
+  a1.mtiles = (m.M + kGemmTile - 1) / kGemmTile;
+  a1.ntiles = (nf * m.D + kGemmTile - 1) / kGemmTile;
+  const unsigned g1 = (unsigned)(m.n_lam * m.n_a * a1.mtiles * a1.ntiles);
+  slot = prof->begin(st);
+  hipLaunchKernelGGL((k_mfma_rows<NPL, F16>), dim3(g1), dim3(256), lds, st, a1);
+  if ((e = hipGetLastError()) != hipSuccess) return PWFS_EHIP;
+  prof->end(slot, st, K_ROWS);
+
+  G2Args a2{};
+  a2.a = qy;
+  a2.t = T;
+  a2.kord = (const int2*)sp.dev[R_AK];
+  a2.out = out;
+  a2.a_plane = qy_plane;
+  a2.t_plane = t_plane;
+  a2.out_stride = ost;
+  a2.M = m.M;
+  a2.Nc = m.Nc;
+  a2.N = m.N;
+  a2.D = m.D;
+  a2.Kp = m.Kp;
+  a2.n_a = m.n_a;
+  a2.n_lam = m.n_lam;
+  a2.n_mod = m.n_mod;
+  a2.mtiles = (m.M + kGemmTile - 1) / kGemmTile;
+  a2.ntiles = (m.Nc + kGemmTile - 1) / kGemmTile;
+  a2.win_lo = g.win_lo;
+  a2.win_hi = g.win_hi;
+  a2.full = g.full;
+  for (int l = 0; l < m.n_lam; ++l)
+    a2.scale[l] = (float)(sp.desc.lambda_weight[l] / ((double)sp.desc.n_mod * sp.sumA2));
+  const unsigned g2 = (unsigned)(nf * a2.mtiles * a2.ntiles);
+  slot = prof->begin(st);
+  hipLaunchKernelGGL((k_mfma_cols<NPL, F16>), dim3(g2), dim3(256), lds, st, a2);
+  if ((e = hipGetLastError()) != hipSuccess) return PWFS_EHIP;
+  prof->end(slot, st, K_MFMA);
+  return PWFS_OK;
+}
+
+template <int NPL, bool F16>
+void set_lds() {
+  const int lds = (int)MfmaTile<NPL, F16>::lds_bytes();
+  if (hipFuncSetAttribute((const void*)k_mfma_rows<NPL, F16>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+      hipSuccess)
+    (void)hipGetLastError();
+  if (hipFuncSetAttribute((const void*)k_mfma_cols<NPL, F16>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+      hipSuccess)
+    (void)hipGetLastError();
+}
+
+}  // namespace
+
+bool mfma_supported(const pwfs_sensor_desc& d) {
+  return d.precision == PWFS_BF16 || d.precision == PWFS_BF16X3 || d.precision == PWFS_FP16X3;
+}
+
+size_t mfma_table_bytes(const pwfs_sensor_desc& d) {
+  if (d.precision == PWFS_FP32) return 0;
+  const MGeom m = mgeom(d);
+  return sizeof(uint16_t) * (size_t)m.planes * m.n_lam * ((size_t)m.n_a + m.n_mod) * m.M * m.Kp;
+}
+
+size_t mfma_scratch_frame_bytes(const pwfs_sensor_desc& d) {
+  const MGeom m = mgeom(d);
+  return sizeof(uint16_t) * (size_t)m.planes * m.n_lam * ((size_t)m.D * m.Kp + (size_t)m.n_a * m.Nc * m.Kp);
+}
+
+int upload_mfma_tables(const pwfs_sensor_desc& d, char* dst, hipStream_t st, std::vector<std::vector<char>>& keep,
+                       double) {
+  const MGeom m = mgeom(d);
+  const Geometry g = geometry(d);
+  const int N = m.N, D = m.D;
+  // circulant kernel p = IDFT(m) of the pyramid mask (phases reduced exactly)
+  std::vector<std::complex<double>> mk(N), pk(N);
+  for (int u = 0; u < N; ++u) {
+    const long long twice = (u < N / 2) ? (2LL * u + 1) : (2LL * N - 2LL * u - 1);
+    const long long ph = ((long long)g.S * twice) % (4LL * N);
+    mk[u] = std::polar(1.0, 2.0 * kPi * (double)ph / (4.0 * N));
+  }
+  for (int dd = 0; dd < N; ++dd) {
+    std::complex<double> s = 0.0;
+    for (int u = 0; u < N; ++u) s += mk[u] * std::polar(1.0, 2.0 * kPi * (double)(((long long)u * dd) % N) / N);
+    pk[dd] = s / (double)N;
+  }
+  // P[Yc][x] over the kept rows (windows or full plane)
+  std::vector<std::complex<double>> P((size_t)m.Nc * D);
+  for (int yc = 0; yc < m.Nc; ++yc) {
+    const int Y = g.full ? yc : (yc < D ? g.win_lo + yc : g.win_hi + yc - D);
+    for (int x = 0; x < D; ++x) {
+      const int Xp = g.o + x;
+      const std::complex<double> h = std::polar(1.0, -kPi * (double)Xp / N);
+      P[(size_t)yc * D + x] = h * pk[(((Y - Xp) % N) + N) % N];
+    }
+  }
+  const size_t blk = (size_t)m.M * m.Kp;               // one operator, one plane
+  const size_t nblk = (size_t)m.n_lam * (m.n_a + m.n_mod);
+  std::vector<uint16_t> tab((size_t)m.planes * nblk * blk, 0);
+  auto put = [&](size_t b, const std::vector<std::complex<double>>& ramp) {
+    // interleaved real block form of Q[Xc][x] = P[Xc][x] ramp[x]
+    for (int xc = 0; xc < m.Nc; ++xc)
+      for (int x = 0; x < D; ++x) {
+        const std::complex<double> q = P[(size_t)xc * D + x] * ramp[x];
+        const float vals[4] = {(float)q.real(), (float)-q.imag(), (float)q.imag(), (float)q.real()};
+        const size_t idx[4] = {(size_t)(2 * xc) * m.Kp + x, (size_t)(2 * xc) * m.Kp + D + x,
+                               (size_t)(2 * xc + 1) * m.Kp + x, (size_t)(2 * xc + 1) * m.Kp + D + x};
+        for (int t = 0; t < 4; ++t) {
+          uint16_t hi, lo;
+          if (m.planes == 2) {
+            host_split(vals[t], m.f16, hi, lo);
+            tab[b * blk + idx[t]] = hi;
+            tab[(nblk + b) * blk + idx[t]] = lo;
+          } else {
+            tab[b * blk + idx[t]] = m.f16 ? h_f16(vals[t]) : h_bf16(vals[t]);
+          }
+        }
+      }
+  };
+  std::vector<std::complex<double>> ramp(D);
+  for (int l = 0; l < m.n_lam; ++l) {
+    const double r = d.mod_radius_lod * d.lambda_ref_nm / d.lambda_nm[l];
+    for (int a = 0; a < m.n_a; ++a) {
+      const double th = 2.0 * kPi * a / d.n_mod;
+      for (int x = 0; x < D; ++x) ramp[x] = std::polar(1.0, 2.0 * kPi * r * (x - (D - 1) / 2.0) * std::cos(th) / D);
+      put((size_t)l * m.n_a + a, ramp);
+    }
+  }
+  // the two planes are laid out [plane][qx blocks ... qy blocks], so qy
+  // blocks of plane 0 start after all qx blocks of plane 0
+  for (int l = 0; l < m.n_lam; ++l) {
+    const double r = d.mod_radius_lod * d.lambda_ref_nm / d.lambda_nm[l];
+    for (int k = 0; k < m.n_mod; ++k) {
+      const double th = 2.0 * kPi * k / d.n_mod;
+      for (int y = 0; y < D; ++y) ramp[y] = std::polar(1.0, 2.0 * kPi * r * (y - (D - 1) / 2.0) * std::sin(th) / D);
+      put((size_t)m.n_lam * m.n_a + (size_t)l * m.n_mod + k, ramp);
+    }
+  }
+  // reorder to [qx plane0][qx plane1][qy plane0][qy plane1] (what the launch expects)
+  std::vector<uint16_t> out(tab.size());
+  const size_t nqx = (size_t)m.n_lam * m.n_a * blk, nqy = (size_t)m.n_lam * m.n_mod * blk;
+  for (int pl = 0; pl < m.planes; ++pl) {
+    std::memcpy(&out[pl * nqx], &tab[(size_t)pl * nblk * blk], nqx * 2);
+    std::memcpy(&out[m.planes * nqx + pl * nqy], &tab[(size_t)pl * nblk * blk + nqx], nqy * 2);
+  }
+  keep.emplace_back((const char*)out.data(), (const char*)out.data() + out.size() * 2);
+  if (hipMemcpyAsync(dst, keep.back().data(), out.size() * 2, hipMemcpyHostToDevice, st) != hipSuccess)
+    return PWFS_EHIP;
+  static bool lds_set = false;
+  if (!lds_set) {
+    set_lds<1, false>();
+    set_lds<2, false>();
+    set_lds<2, true>();
+    lds_set = true;
+  }
+  return PWFS_OK;
+}
+
+int forward_mfma(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost, int nf,
+                 void* scratch, hipStream_t st, Prof* prof) {
+  const MGeom m = mgeom(sp.desc);
+  if (sp.desc.precision == PWFS_BF16) return launch<1, false>(sp, m, opd, os, out, ost, nf, scratch, st, prof);
+  if (sp.desc.precision == PWFS_BF16X3) return launch<2, false>(sp, m, opd, os, out, ost, nf, scratch, st, prof);
+  return launch<2, true>(sp, m, opd, os, out, ost, nf, scratch, st, prof);
 }
 
 }  // namespace pwfs
