@@ -171,6 +171,60 @@ int pwfs_valid_map(pwfs_plan_t plan, int sensor, uint8_t* host_out);
 int pwfs_profile(pwfs_plan_t plan, int max_launches);
 int pwfs_profile_read(pwfs_plan_t plan, int kernel, double* total_ms, int* launches);
 
+/* ------------------------------------------------------------------------
+ * Matrix-core products.  The learned-surrogate form and its data pipeline
+ * (modal coefficients -> OPD, the linear interaction-matrix baseline) need
+ * dense products; they run on the same split-precision MFMA tiles as the
+ * matrix-core forward model.  precision: PWFS_BF16 (bf16 operands, fp32
+ * accumulation) or PWFS_BF16X3 (bf16 hi/lo split, three products, ~fp32).
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes of pwfs_gemm for these sizes. */
+int pwfs_gemm_workspace_size(int M, int N, int K, int precision, size_t* bytes);
+
+/*
+ * C[M][N] = alpha * sum_k A[M][k] B[N][k]: all float32 device arrays,
+ * row-major with leading dimensions lda >= K, ldb >= K, ldc >= N.  The
+ * operands are converted into 16-bit planes in d_workspace (256-byte
+ * aligned, >= pwfs_gemm_workspace_size bytes).  Asynchronous on hip_stream.
+ */
+int pwfs_gemm(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc, int M, int N,
+              int K, float alpha, int precision, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* out[r] = sqrt(mean_c x[r][c]^2) for r < rows (float32 device arrays). */
+int pwfs_row_rms(const float* x, long long ld, int rows, int cols, float* out, void* hip_stream);
+
+/*
+ * Surrogate network: n_layers fully connected layers sizes[0] -> ... ->
+ * sizes[n_layers], exact-erf GELU after every layer but the last, mean
+ * squared error loss, Adam.  Weights are kept as float32 masters plus
+ * 16-bit copies used by the products.  All device memory is the caller's
+ * workspace (>= pwfs_mlp_workspace_size bytes, 256-byte aligned), cleared
+ * by pwfs_mlp_create on hip_stream.  Parameters are exchanged packed and
+ * unpadded: for each layer W [out][in] row-major, then b [out].
+ */
+typedef struct pwfs_mlp_s* pwfs_mlp_t;
+int pwfs_mlp_workspace_size(int n_layers, const int32_t* sizes, int max_batch, int precision, size_t* bytes);
+int pwfs_mlp_create(int n_layers, const int32_t* sizes, int max_batch, int precision, void* d_workspace,
+                    size_t ws_bytes, void* hip_stream, pwfs_mlp_t* out);
+int pwfs_mlp_param_count(pwfs_mlp_t mlp, size_t* count);
+/* Loads parameters (device, packed) and clears the Adam state and step. */
+int pwfs_mlp_set_params(pwfs_mlp_t mlp, const float* d_params, void* hip_stream);
+int pwfs_mlp_get_params(pwfs_mlp_t mlp, float* d_params, void* hip_stream);
+/* d_y [batch][sizes[n]] = out_scale * network(d_x [batch][sizes[0]]), 1 <= batch <= max_batch. */
+int pwfs_mlp_forward(pwfs_mlp_t mlp, const float* d_x, int batch, float* d_y, float out_scale, void* hip_stream);
+/*
+ * Loss and gradients of mean((y - target_scale * t)^2) over the batch
+ * (batch a multiple of 32, <= max_batch): d_loss (1 float, nullable),
+ * d_grads (packed like the parameters, nullable; the gradients are also
+ * kept for pwfs_mlp_adam).
+ */
+int pwfs_mlp_grad(pwfs_mlp_t mlp, const float* d_x, const float* d_t, int batch, float target_scale, float* d_loss,
+                  float* d_grads, void* hip_stream);
+/* One Adam step (bias-corrected) with the last gradients. */
+int pwfs_mlp_adam(pwfs_mlp_t mlp, float lr, float beta1, float beta2, float eps, void* hip_stream);
+void pwfs_mlp_destroy(pwfs_mlp_t mlp);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* pwfs_last_error(void);
 

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpwfs.so")
 
-SOURCES = ["pwfs_lib.hip", "pwfs_mfma.hip"]
+SOURCES = ["pwfs_lib.hip", "pwfs_mfma.hip", "pwfs_mlp.hip"]
 
 # packed fp32 instructions are kept out of every kernel
 HIP_FLAGS = [

@@ -42,6 +42,7 @@ struct Layout {
 };
 
 Geometry geometry(const pwfs_sensor_desc& d);
+void set_last_error(const char* msg);   // message returned by pwfs_last_error
 void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vector<uint8_t>& V);
 int fft_lanes(int N);
 size_t rbuf_field_offset(const pwfs_sensor_desc& d, int nf);

@@ -53,6 +53,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 namespace pwfs {
 
+void set_last_error(const char* msg) { g_err = msg; }
+
 int validate_one(const pwfs_sensor_desc& d, int idx) {
   auto bad = [&](const char* why) { return fail(PWFS_EINVAL, "sensor %d: %s", idx, why); };
   if (d.reserved != 0) return bad("reserved field must be 0");

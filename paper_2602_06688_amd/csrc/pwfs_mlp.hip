@@ -1,0 +1,701 @@
+// pwfs_mlp.hip -- matrix-core GEMM entry point and the surrogate network
+// (fully connected layers with exact GELU, MSE loss, Adam) for gfx950.
+//
+// Every product is the "NT" tile engine of mfma_gemm.hpp on bf16 operands
+// (one plane: bf16 weights and activations, fp32 accumulation) or on bf16
+// hi/lo pairs (three products, ~fp32 accuracy).  Layer l maps P_l -> P_{l+1}
+// features (sizes rounded up to 32, padding kept at zero).  Per layer the
+// network keeps: fp32 master W [P_{l+1}][P_l] and b, Adam moments, fp32
+// gradients, and 16-bit copies of W (rows = outputs) and W^T (rows =
+// inputs) so that both the forward product (A W^T) and the backward data
+// product (dZ W) read K-contiguous operands.  Activations are stored twice
+// by the epilogue that produces them: [batch][features] for the next
+// forward product and [features][batch] for the weight-gradient product
+// dW = dZ^T A, whose K is the batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mfma_gemm.hpp"
+#include "pwfs.h"
+#include "pwfs_internal.hpp"
+
+namespace pwfs {
+namespace {
+
+int mfail(int code, const char* fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  set_last_error(msg);
+  return code;
+}
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+int up32(int x) { return (x + 31) / 32 * 32; }
+
+enum Epi { E_STORE = 0, E_HIDDEN = 1, E_OUTPUT = 2, E_DHIDDEN = 3 };
+
+struct GemmArgs {
+  const uint16_t* a;
+  const uint16_t* b;
+  long long a_plane, b_plane, lda, ldb;
+  int M, N, K, mtiles, ntiles;
+  float alpha;
+  float* c;               // fp32 output [M][ldc] (E_STORE, E_OUTPUT)
+  long long ldc;
+  const float* bias;      // [N]
+  float* z;               // fp32 pre-activation (E_HIDDEN) or gradient (E_OUTPUT, E_DHIDDEN) [M][ldz]
+  long long ldz;
+  uint16_t* h;            // 16-bit planes [M][ldh]
+  long long h_plane, ldh;
+  uint16_t* ht;           // 16-bit planes [N][ldht]
+  long long ht_plane, ldht;
+  const float* target;    // [M][ldt] (E_OUTPUT with loss)
+  long long ldt;
+  float tscale, gscale;
+  const float* zprev;     // [M][ldzp] (E_DHIDDEN)
+  long long ldzp;
+  double* loss_part;      // [grid] (E_OUTPUT with loss)
+  int planes_out;
+};
+
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
+}
+
+__device__ __forceinline__ void put16(uint16_t* base, long long plane, long long off, float v, int planes) {
+  if (planes == 2) {
+    uint16_t hi, lo;
+    split16<false>(v, hi, lo);
+    base[off] = hi;
+    base[plane + off] = lo;
+  } else {
+    base[off] = f32_to_bf16_rne(v);
+  }
+}
+
+template <int NPL, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
+  extern __shared__ u32x4_t lds_raw[];
+  uint16_t* lds = (uint16_t*)lds_raw;
+  using E = MfmaTile<NPL, false>;
+  const int tid = threadIdx.x;
+  const int nt = blockIdx.x % p.ntiles;
+  const int mt = blockIdx.x / p.ntiles;
+  const int m0 = mt * kGemmTile, n0 = nt * kGemmTile;
+  typename E::Ops ops;
+#pragma unroll
+  for (int pl = 0; pl < NPL; ++pl) {
+    ops.a[pl] = p.a + pl * p.a_plane + (long long)m0 * p.lda;
+    ops.b[pl] = p.b + pl * p.b_plane + (long long)n0 * p.ldb;
+  }
+  E eng;
+  eng.zero();
+  eng.run(ops, p.lda, p.M - m0, p.ldb, p.N - n0, p.K, lds, tid);
+  double lsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int row, col;
+        E::coord(tid, i, j, e, row, col);
+        const int m = m0 + row, n = n0 + col;
+        if (m >= p.M || n >= p.N) continue;
+        const float v = eng.value(i, j, e);
+        if constexpr (EPI == E_STORE) {
+          p.c[(long long)m * p.ldc + n] = p.alpha * v;
+        } else if constexpr (EPI == E_HIDDEN) {
+          const float zz = v + p.bias[n];
+          p.z[(long long)m * p.ldz + n] = zz;
+          const float hv = gelu_f(zz);
+          put16(p.h, p.h_plane, (long long)m * p.ldh + n, hv, p.planes_out);
+          put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, hv, p.planes_out);
+        } else if constexpr (EPI == E_OUTPUT) {
+          const float y = v + p.bias[n];
+          if (p.c) p.c[(long long)m * p.ldc + n] = p.alpha * y;
+          if (p.target) {
+            const float d = y - p.target[(long long)m * p.ldt + n] * p.tscale;
+            lsum += (double)d * d;
+            const float g = p.gscale * d;
+            p.z[(long long)m * p.ldz + n] = g;
+            put16(p.h, p.h_plane, (long long)m * p.ldh + n, g, p.planes_out);
+            put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, g, p.planes_out);
+          }
+        } else {  // E_DHIDDEN
+          const float g = v * gelu_grad_f(p.zprev[(long long)m * p.ldzp + n]);
+          p.z[(long long)m * p.ldz + n] = g;
+          put16(p.h, p.h_plane, (long long)m * p.ldh + n, g, p.planes_out);
+          put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, g, p.planes_out);
+        }
+      }
+  if constexpr (EPI == E_OUTPUT) {
+    if (p.loss_part) {
+      __shared__ double red[256];
+      red[tid] = lsum;
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+      }
+      if (tid == 0) p.loss_part[blockIdx.x] = red[0];
+    }
+  }
+}
+
+// fp32 [rows][cols] (row stride ld) -> 16-bit planes [rows][Kp], zero padding;
+// with `transpose`, planes [cols][ldo] hold the transpose (row index = col)
+struct SplitArgs {
+  const float* src;
+  long long ld;
+  uint16_t* dst;
+  long long plane, ldo;
+  int rows, cols, Kp, planes, transpose;
+  float scale;
+};
+
+__global__ __launch_bounds__(256) void k_split(SplitArgs p) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long total = (long long)p.rows * p.Kp;
+  if (i >= total) return;
+  const int r = (int)(i / p.Kp), k = (int)(i % p.Kp);
+  const float v = (k < p.cols) ? p.src[(long long)r * p.ld + k] * p.scale : 0.f;
+  const long long off = p.transpose ? (long long)k * p.ldo + r : (long long)r * p.ldo + k;
+  put16(p.dst, p.plane, off, v, p.planes);
+}
+
+// column sums of an fp32 [rows][ld] matrix over its first `rows` rows
+__global__ __launch_bounds__(256) void k_colsum(const float* x, long long ld, int rows, int cols, float* out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += x[(long long)r * ld + c];
+  out[c] = s;
+}
+
+__global__ void k_loss_reduce(const double* part, int n, float scale, float* loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  *loss = (float)(s * scale);
+}
+
+struct AdamArgs {
+  float* w;        // fp32 master [rows][cols]
+  float* m;
+  float* v;
+  const float* g;
+  uint16_t* wq;    // 16-bit planes [rows][cols]    (nullptr for biases)
+  uint16_t* wqt;   // 16-bit planes [cols][rows]
+  long long plane, plane_t;
+  int rows, cols, planes;
+  float lr, b1, b2, eps, c1, c2;   // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
+};
+
+__global__ __launch_bounds__(256) void k_adam(AdamArgs p) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long total = (long long)p.rows * p.cols;
+  if (i >= total) return;
+  const float g = p.g[i];
+  const float m = p.b1 * p.m[i] + (1.f - p.b1) * g;
+  const float v = p.b2 * p.v[i] + (1.f - p.b2) * g * g;
+  p.m[i] = m;
+  p.v[i] = v;
+  const float w = p.w[i] - p.lr * (m * p.c1) / (sqrtf(v * p.c2) + p.eps);
+  p.w[i] = w;
+  if (p.wq) {
+    const int r = (int)(i / p.cols), c = (int)(i % p.cols);
+    put16(p.wq, p.plane, i, w, p.planes);
+    put16(p.wqt, p.plane_t, (long long)c * p.rows + r, w, p.planes);
+  }
+}
+
+// params (packed, unpadded, W as [out][in]) <-> padded master copies
+struct ParamCopyArgs {
+  const float* src;
+  float* dst;
+  int rows, cols, src_ld, dst_ld;
+};
+__global__ __launch_bounds__(256) void k_copy2d(ParamCopyArgs p) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (long long)p.rows * p.cols) return;
+  const int r = (int)(i / p.cols), c = (int)(i % p.cols);
+  p.dst[(long long)r * p.dst_ld + c] = p.src[(long long)r * p.src_ld + c];
+}
+
+__global__ __launch_bounds__(256) void k_row_rms(const float* x, long long ld, int rows, int cols, float* out) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  double s = 0.0;
+  for (int c = 0; c < cols; ++c) {
+    const double v = x[(long long)r * ld + c];
+    s += v * v;
+  }
+  out[r] = (float)sqrt(s / cols);
+}
+
+template <int NPL, int EPI>
+int gemm_launch(const GemmArgs& a0, hipStream_t st) {
+  GemmArgs a = a0;
+  a.mtiles = (a.M + kGemmTile - 1) / kGemmTile;
+  a.ntiles = (a.N + kGemmTile - 1) / kGemmTile;
+  static bool lds_set = false;
+  if (!lds_set) {
+    if (hipFuncSetAttribute((const void*)k_gemm<NPL, EPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)MfmaTile<NPL, false>::lds_bytes()) != hipSuccess)
+      (void)hipGetLastError();
+    lds_set = true;
+  }
+  const size_t lds = MfmaTile<NPL, false>::lds_bytes();
+  hipLaunchKernelGGL((k_gemm<NPL, EPI>), dim3((unsigned)(a.mtiles * a.ntiles)), dim3(256), lds, st, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return mfail(PWFS_EHIP, "launch k_gemm: %s", hipGetErrorString(e));
+  return PWFS_OK;
+}
+
+template <int EPI>
+int gemm_dispatch(int planes, const GemmArgs& a, hipStream_t st) {
+  return planes == 2 ? gemm_launch<2, EPI>(a, st) : gemm_launch<1, EPI>(a, st);
+}
+
+int split_launch(const float* src, long long ld, int rows, int cols, int Kp, uint16_t* dst, long long plane,
+                 long long ldo, int planes, int transpose, float scale, hipStream_t st) {
+  SplitArgs s{src, ld, dst, plane, ldo, rows, cols, Kp, planes, transpose, scale};
+  const long long total = (long long)rows * Kp;
+  hipLaunchKernelGGL(k_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, s);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return mfail(PWFS_EHIP, "launch k_split: %s", hipGetErrorString(e));
+  return PWFS_OK;
+}
+
+int planes_of(int precision) { return precision == PWFS_BF16X3 ? 2 : 1; }
+
+}  // namespace
+}  // namespace pwfs
+
+using namespace pwfs;
+
+// ================================================================ GEMM ABI ==
+extern "C" int pwfs_gemm_workspace_size(int M, int N, int K, int precision, size_t* bytes) {
+  if (!bytes || M < 1 || N < 1 || K < 1) return mfail(PWFS_EINVAL, "bad GEMM sizes");
+  if (precision != PWFS_BF16 && precision != PWFS_BF16X3) return mfail(PWFS_EUNSUPPORTED, "precision");
+  const size_t Kp = up32(K), pl = planes_of(precision);
+  *bytes = a256(2 * pl * (size_t)M * Kp) + a256(2 * pl * (size_t)N * Kp);
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_gemm(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc,
+                         int M, int N, int K, float alpha, int precision, void* ws, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  int rc = pwfs_gemm_workspace_size(M, N, K, precision, &need);
+  if (rc) return rc;
+  if (!A || !B || !C) return mfail(PWFS_EINVAL, "NULL device pointer");
+  if (lda < K || ldb < K || ldc < N) return mfail(PWFS_EINVAL, "leading dimension too small");
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return mfail(PWFS_EWORKSPACE, "workspace");
+  hipStream_t st = (hipStream_t)stream;
+  const int Kp = up32(K), pl = planes_of(precision);
+  uint16_t* a16 = (uint16_t*)ws;
+  uint16_t* b16 = (uint16_t*)((char*)ws + a256(2 * pl * (size_t)M * Kp));
+  const long long ap = (long long)M * Kp, bp = (long long)N * Kp;
+  if ((rc = split_launch(A, lda, M, K, Kp, a16, ap, Kp, pl, 0, 1.f, st))) return rc;
+  if ((rc = split_launch(B, ldb, N, K, Kp, b16, bp, Kp, pl, 0, 1.f, st))) return rc;
+  GemmArgs g{};
+  g.a = a16;
+  g.b = b16;
+  g.a_plane = ap;
+  g.b_plane = bp;
+  g.lda = Kp;
+  g.ldb = Kp;
+  g.M = M;
+  g.N = N;
+  g.K = Kp;
+  g.alpha = alpha;
+  g.c = C;
+  g.ldc = ldc;
+  return gemm_dispatch<E_STORE>(pl, g, st);
+}
+
+extern "C" int pwfs_row_rms(const float* x, long long ld, int rows, int cols, float* out, void* stream) {
+  if (!x || !out || rows < 1 || cols < 1 || ld < cols) return mfail(PWFS_EINVAL, "bad arguments");
+  hipLaunchKernelGGL(k_row_rms, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, (hipStream_t)stream, x, ld,
+                     rows, cols, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return mfail(PWFS_EHIP, "launch k_row_rms: %s", hipGetErrorString(e));
+  return PWFS_OK;
+}
+
+// ================================================================= MLP ABI ==
+struct pwfs_mlp_s {
+  int L = 0, Bm = 0, precision = 0, planes = 1, step = 0;
+  std::vector<int> n, P;                     // true and padded sizes, L + 1 each
+  // per layer l (0..L-1)
+  std::vector<float*> W, b, mW, vW, mb, vb, gW, gb;
+  std::vector<uint16_t*> Wq, Wqt;            // planes [P_{l+1}][P_l], [P_l][P_{l+1}]
+  // per layer boundary j (0..L): activation planes and transposes; z, dz fp32
+  std::vector<uint16_t*> H, Ht, G, Gt;
+  std::vector<float*> Z, dZ;
+  float* Y = nullptr;
+  double* loss_part = nullptr;
+  int loss_parts = 0;
+  bool have_grad = false;
+};
+
+namespace {
+
+struct MlpLayout {
+  size_t total = 0;
+  std::vector<size_t> off;
+};
+
+// sizes of every region, in order; `cb` is called with each region's bytes
+template <class CB>
+void mlp_regions(int L, const std::vector<int>& P, int Bm, int planes, CB cb) {
+  for (int l = 0; l < L; ++l) {
+    const size_t w = (size_t)P[l + 1] * P[l], bb = (size_t)P[l + 1];
+    for (int r = 0; r < 4; ++r) cb(4 * w);     // W, mW, vW, gW
+    for (int r = 0; r < 4; ++r) cb(4 * bb);    // b, mb, vb, gb
+    cb(2 * planes * w);                        // Wq
+    cb(2 * planes * w);                        // Wqt
+  }
+  for (int j = 0; j <= L; ++j) {
+    const size_t a = (size_t)Bm * P[j];
+    cb(2 * planes * a);  // H
+    cb(2 * planes * a);  // Ht
+    cb(2 * planes * a);  // G
+    cb(2 * planes * a);  // Gt
+    cb(4 * a);           // Z
+    cb(4 * a);           // dZ
+  }
+  cb(4 * (size_t)Bm * P[L]);                   // Y
+  const int tiles = ((Bm + 127) / 128) * ((P[L] + 127) / 128);
+  cb(8 * (size_t)tiles);                       // loss partials
+}
+
+int mlp_check(int L, const int32_t* sizes, int Bm, int precision, std::vector<int>& n, std::vector<int>& P) {
+  if (L < 1 || L > 8 || !sizes) return mfail(PWFS_EINVAL, "n_layers must be in [1, 8]");
+  if (Bm < 32 || Bm % 32) return mfail(PWFS_EINVAL, "max_batch must be a positive multiple of 32");
+  if (precision != PWFS_BF16 && precision != PWFS_BF16X3) return mfail(PWFS_EUNSUPPORTED, "precision");
+  n.assign(sizes, sizes + L + 1);
+  P.resize(L + 1);
+  for (int j = 0; j <= L; ++j) {
+    if (n[j] < 1 || n[j] > 65536) return mfail(PWFS_EINVAL, "layer size out of range");
+    P[j] = up32(n[j]);
+  }
+  return PWFS_OK;
+}
+
+}  // namespace
+
+extern "C" int pwfs_mlp_workspace_size(int L, const int32_t* sizes, int max_batch, int precision, size_t* bytes) {
+  std::vector<int> n, P;
+  int rc = mlp_check(L, sizes, max_batch, precision, n, P);
+  if (rc) return rc;
+  if (!bytes) return mfail(PWFS_EINVAL, "bytes is NULL");
+  size_t tot = 0;
+  mlp_regions(L, P, max_batch, planes_of(precision), [&](size_t b) { tot += a256(b); });
+  *bytes = tot;
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_mlp_create(int L, const int32_t* sizes, int max_batch, int precision, void* ws, size_t ws_bytes,
+                               void* stream, pwfs_mlp_t* out) {
+  size_t need = 0;
+  int rc = pwfs_mlp_workspace_size(L, sizes, max_batch, precision, &need);
+  if (rc) return rc;
+  if (!out) return mfail(PWFS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return mfail(PWFS_EWORKSPACE, "workspace missing, small or misaligned");
+  pwfs_mlp_s* m = new (std::nothrow) pwfs_mlp_s();
+  if (!m) return mfail(PWFS_EINVAL, "out of host memory");
+  mlp_check(L, sizes, max_batch, precision, m->n, m->P);
+  m->L = L;
+  m->Bm = max_batch;
+  m->precision = precision;
+  m->planes = planes_of(precision);
+  std::vector<char*> reg;
+  size_t off = 0;
+  mlp_regions(L, m->P, max_batch, m->planes, [&](size_t b) {
+    reg.push_back((char*)ws + off);
+    off += a256(b);
+  });
+  size_t r = 0;
+  for (int l = 0; l < L; ++l) {
+    m->W.push_back((float*)reg[r++]);
+    m->mW.push_back((float*)reg[r++]);
+    m->vW.push_back((float*)reg[r++]);
+    m->gW.push_back((float*)reg[r++]);
+    m->b.push_back((float*)reg[r++]);
+    m->mb.push_back((float*)reg[r++]);
+    m->vb.push_back((float*)reg[r++]);
+    m->gb.push_back((float*)reg[r++]);
+    m->Wq.push_back((uint16_t*)reg[r++]);
+    m->Wqt.push_back((uint16_t*)reg[r++]);
+  }
+  for (int j = 0; j <= L; ++j) {
+    m->H.push_back((uint16_t*)reg[r++]);
+    m->Ht.push_back((uint16_t*)reg[r++]);
+    m->G.push_back((uint16_t*)reg[r++]);
+    m->Gt.push_back((uint16_t*)reg[r++]);
+    m->Z.push_back((float*)reg[r++]);
+    m->dZ.push_back((float*)reg[r++]);
+  }
+  m->Y = (float*)reg[r++];
+  m->loss_part = (double*)reg[r++];
+  m->loss_parts = ((max_batch + 127) / 128) * ((m->P[L] + 127) / 128);
+  // everything starts at zero: padding of every buffer must stay zero
+  const hipError_t e = hipMemsetAsync(ws, 0, need, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    delete m;
+    return mfail(PWFS_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+  }
+  *out = m;
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_mlp_param_count(pwfs_mlp_t m, size_t* count) {
+  if (!m || !count) return mfail(PWFS_EINVAL, "NULL argument");
+  size_t c = 0;
+  for (int l = 0; l < m->L; ++l) c += (size_t)m->n[l + 1] * m->n[l] + m->n[l + 1];
+  *count = c;
+  return PWFS_OK;
+}
+
+namespace {
+
+int copy2d(const float* src, int src_ld, float* dst, int dst_ld, int rows, int cols, hipStream_t st) {
+  ParamCopyArgs a{src, dst, rows, cols, src_ld, dst_ld};
+  const long long total = (long long)rows * cols;
+  hipLaunchKernelGGL(k_copy2d, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return mfail(PWFS_EHIP, "launch k_copy2d: %s", hipGetErrorString(e));
+  return PWFS_OK;
+}
+
+// refresh the 16-bit weight copies from the fp32 masters (Adam with lr = 0
+// on zero moments would do the same; this is explicit)
+int refresh_q(pwfs_mlp_t m, int l, hipStream_t st) {
+  const int rows = m->P[l + 1], cols = m->P[l];
+  int rc = split_launch(m->W[l], cols, rows, cols, cols, m->Wq[l], (long long)rows * cols, cols, m->planes, 0, 1.f, st);
+  if (rc) return rc;
+  return split_launch(m->W[l], cols, rows, cols, cols, m->Wqt[l], (long long)rows * cols, rows, m->planes, 1, 1.f, st);
+}
+
+}  // namespace
+
+extern "C" int pwfs_mlp_set_params(pwfs_mlp_t m, const float* params, void* stream) {
+  if (!m || !params) return mfail(PWFS_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  size_t off = 0;
+  int rc;
+  for (int l = 0; l < m->L; ++l) {
+    const int no = m->n[l + 1], ni = m->n[l];
+    if ((rc = copy2d(params + off, ni, m->W[l], m->P[l], no, ni, st))) return rc;
+    off += (size_t)no * ni;
+    if ((rc = copy2d(params + off, no, m->b[l], no, 1, no, st))) return rc;
+    off += no;
+    const size_t w = (size_t)m->P[l + 1] * m->P[l];
+    if (hipMemsetAsync(m->mW[l], 0, 4 * w, st) != hipSuccess || hipMemsetAsync(m->vW[l], 0, 4 * w, st) != hipSuccess ||
+        hipMemsetAsync(m->mb[l], 0, 4 * (size_t)m->P[l + 1], st) != hipSuccess ||
+        hipMemsetAsync(m->vb[l], 0, 4 * (size_t)m->P[l + 1], st) != hipSuccess)
+      return mfail(PWFS_EHIP, "hipMemsetAsync");
+    if ((rc = refresh_q(m, l, st))) return rc;
+  }
+  m->step = 0;
+  m->have_grad = false;
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_mlp_get_params(pwfs_mlp_t m, float* params, void* stream) {
+  if (!m || !params) return mfail(PWFS_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  size_t off = 0;
+  int rc;
+  for (int l = 0; l < m->L; ++l) {
+    const int no = m->n[l + 1], ni = m->n[l];
+    if ((rc = copy2d(m->W[l], m->P[l], params + off, ni, no, ni, st))) return rc;
+    off += (size_t)no * ni;
+    if ((rc = copy2d(m->b[l], no, params + off, no, 1, no, st))) return rc;
+    off += no;
+  }
+  return PWFS_OK;
+}
+
+namespace {
+
+// forward through all layers; the output epilogue optionally forms the loss
+// gradient against `target`
+int mlp_forward(pwfs_mlp_t m, const float* x, int batch, float* y, float out_scale, const float* target,
+                float tscale, hipStream_t st) {
+  const int L = m->L, pl = m->planes;
+  int rc;
+  // input activations (and their transpose, used by dW of layer 0)
+  const long long a0 = (long long)m->Bm * m->P[0];
+  if ((rc = split_launch(x, m->n[0], batch, m->n[0], m->P[0], m->H[0], a0, m->P[0], pl, 0, 1.f, st))) return rc;
+  if (target)
+    if ((rc = split_launch(x, m->n[0], batch, m->n[0], m->P[0], m->Ht[0], a0, m->Bm, pl, 1, 1.f, st))) return rc;
+  for (int l = 0; l < L; ++l) {
+    GemmArgs g{};
+    g.a = m->H[l];
+    g.a_plane = (long long)m->Bm * m->P[l];
+    g.lda = m->P[l];
+    g.b = m->Wq[l];
+    g.b_plane = (long long)m->P[l + 1] * m->P[l];
+    g.ldb = m->P[l];
+    g.M = batch;
+    g.N = m->n[l + 1];
+    g.K = m->P[l];
+    g.bias = m->b[l];
+    g.planes_out = pl;
+    const long long ap = (long long)m->Bm * m->P[l + 1];
+    if (l + 1 < L) {
+      g.z = m->Z[l + 1];
+      g.ldz = m->P[l + 1];
+      g.h = m->H[l + 1];
+      g.h_plane = ap;
+      g.ldh = m->P[l + 1];
+      g.ht = m->Ht[l + 1];
+      g.ht_plane = ap;
+      g.ldht = m->Bm;
+      if ((rc = gemm_dispatch<E_HIDDEN>(pl, g, st))) return rc;
+    } else {
+      g.alpha = out_scale;
+      g.c = y;
+      g.ldc = m->n[L];
+      if (target) {
+        g.target = target;
+        g.ldt = m->n[L];
+        g.tscale = tscale;
+        g.gscale = 2.f / ((float)batch * (float)m->n[L]);
+        g.z = m->dZ[L];
+        g.ldz = m->P[L];
+        g.h = m->G[L];
+        g.h_plane = ap;
+        g.ldh = m->P[L];
+        g.ht = m->Gt[L];
+        g.ht_plane = ap;
+        g.ldht = m->Bm;
+        g.loss_part = m->loss_part;
+      }
+      if ((rc = gemm_dispatch<E_OUTPUT>(pl, g, st))) return rc;
+    }
+  }
+  return PWFS_OK;
+}
+
+}  // namespace
+
+extern "C" int pwfs_mlp_forward(pwfs_mlp_t m, const float* x, int batch, float* y, float out_scale, void* stream) {
+  if (!m || !x || !y) return mfail(PWFS_EINVAL, "NULL argument");
+  if (batch < 1 || batch > m->Bm) return mfail(PWFS_ESTATE, "batch outside [1, max_batch]");
+  return mlp_forward(m, x, batch, y, out_scale, nullptr, 1.f, (hipStream_t)stream);
+}
+
+extern "C" int pwfs_mlp_grad(pwfs_mlp_t m, const float* x, const float* t, int batch, float tscale, float* loss,
+                             float* grads, void* stream) {
+  if (!m || !x || !t) return mfail(PWFS_EINVAL, "NULL argument");
+  if (batch < 32 || batch > m->Bm || batch % 32)
+    return mfail(PWFS_ESTATE, "training batch must be a multiple of 32 in [32, max_batch]");
+  hipStream_t st = (hipStream_t)stream;
+  const int L = m->L, pl = m->planes;
+  int rc = mlp_forward(m, x, batch, m->Y, 1.f, t, tscale, st);
+  if (rc) return rc;
+  const int tiles = ((batch + 127) / 128) * ((m->n[L] + 127) / 128);
+  if (loss) {
+    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(64), 0, st, m->loss_part, tiles,
+                       1.f / ((float)batch * (float)m->n[L]), loss);
+    if (hipGetLastError() != hipSuccess) return mfail(PWFS_EHIP, "launch k_loss_reduce");
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    // dW_l = G_{l+1}^T H_l : A = Gt_{l+1} [n_{l+1}][batch], B = Ht_l [P_l][batch], K = batch
+    GemmArgs g{};
+    g.a = m->Gt[l + 1];
+    g.a_plane = (long long)m->Bm * m->P[l + 1];
+    g.lda = m->Bm;
+    g.b = m->Ht[l];
+    g.b_plane = (long long)m->Bm * m->P[l];
+    g.ldb = m->Bm;
+    g.M = m->n[l + 1];
+    g.N = m->P[l];
+    g.K = batch;
+    g.alpha = 1.f;
+    g.c = m->gW[l];
+    g.ldc = m->P[l];
+    if ((rc = gemm_dispatch<E_STORE>(pl, g, st))) return rc;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->n[l + 1] + 255) / 256)), dim3(256), 0, st, m->dZ[l + 1],
+                       (long long)m->P[l + 1], batch, m->n[l + 1], m->gb[l]);
+    if (hipGetLastError() != hipSuccess) return mfail(PWFS_EHIP, "launch k_colsum");
+    if (l == 0) break;
+    // G_l = (G_{l+1} W_l) * gelu'(Z_l) : A = G_{l+1} [batch][P_{l+1}], B = Wqt_l [P_l][P_{l+1}]
+    GemmArgs d{};
+    d.a = m->G[l + 1];
+    d.a_plane = (long long)m->Bm * m->P[l + 1];
+    d.lda = m->P[l + 1];
+    d.b = m->Wqt[l];
+    d.b_plane = (long long)m->P[l + 1] * m->P[l];
+    d.ldb = m->P[l + 1];
+    d.M = batch;
+    d.N = m->n[l];
+    d.K = m->P[l + 1];
+    d.zprev = m->Z[l];
+    d.ldzp = m->P[l];
+    d.z = m->dZ[l];
+    d.ldz = m->P[l];
+    d.h = m->G[l];
+    d.h_plane = (long long)m->Bm * m->P[l];
+    d.ldh = m->P[l];
+    d.ht = m->Gt[l];
+    d.ht_plane = (long long)m->Bm * m->P[l];
+    d.ldht = m->Bm;
+    d.planes_out = pl;
+    if ((rc = gemm_dispatch<E_DHIDDEN>(pl, d, st))) return rc;
+  }
+  m->have_grad = true;
+  if (grads) {
+    size_t off = 0;
+    for (int l = 0; l < L; ++l) {
+      const int no = m->n[l + 1], ni = m->n[l];
+      if ((rc = copy2d(m->gW[l], m->P[l], grads + off, ni, no, ni, st))) return rc;
+      off += (size_t)no * ni;
+      if ((rc = copy2d(m->gb[l], no, grads + off, no, 1, no, st))) return rc;
+      off += no;
+    }
+  }
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_mlp_adam(pwfs_mlp_t m, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!m) return mfail(PWFS_EINVAL, "NULL argument");
+  if (!m->have_grad) return mfail(PWFS_ESTATE, "no gradient: call pwfs_mlp_grad first");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return mfail(PWFS_EINVAL, "bad Adam hyper-parameters");
+  hipStream_t st = (hipStream_t)stream;
+  m->step += 1;
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, m->step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, m->step)));
+  for (int l = 0; l < m->L; ++l) {
+    const int rows = m->P[l + 1], cols = m->P[l];
+    AdamArgs a{m->W[l], m->mW[l], m->vW[l], m->gW[l], m->Wq[l], m->Wqt[l], (long long)rows * cols,
+               (long long)rows * cols, rows, cols, m->planes, lr, beta1, beta2, eps, c1, c2};
+    const long long tw = (long long)rows * cols;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((tw + 255) / 256)), dim3(256), 0, st, a);
+    AdamArgs ab{m->b[l], m->mb[l], m->vb[l], m->gb[l], nullptr, nullptr, 0, 0, 1, rows, m->planes,
+                lr, beta1, beta2, eps, c1, c2};
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, ab);
+    if (hipGetLastError() != hipSuccess) return mfail(PWFS_EHIP, "launch k_adam");
+  }
+  return PWFS_OK;
+}
+
+extern "C" void pwfs_mlp_destroy(pwfs_mlp_t m) { delete m; }

@@ -95,8 +95,25 @@ def lib() -> ctypes.CDLL:
     L.pwfs_profile_read.argtypes = [vp, i32, P(ctypes.c_double), P(ctypes.c_int)]
     L.pwfs_destroy.argtypes = [vp]
     L.pwfs_destroy.restype = None
+    ll = ctypes.c_longlong
+    L.pwfs_gemm_workspace_size.argtypes = [i32, i32, i32, i32, P(ctypes.c_size_t)]
+    L.pwfs_gemm.argtypes = [vp, ll, vp, ll, vp, ll, i32, i32, i32, ctypes.c_float, i32, vp, ctypes.c_size_t, vp]
+    L.pwfs_row_rms.argtypes = [vp, ll, i32, i32, vp, vp]
+    L.pwfs_mlp_workspace_size.argtypes = [i32, P(ctypes.c_int32), i32, i32, P(ctypes.c_size_t)]
+    L.pwfs_mlp_create.argtypes = [i32, P(ctypes.c_int32), i32, i32, vp, ctypes.c_size_t, vp, P(vp)]
+    L.pwfs_mlp_param_count.argtypes = [vp, P(ctypes.c_size_t)]
+    L.pwfs_mlp_set_params.argtypes = [vp, vp, vp]
+    L.pwfs_mlp_get_params.argtypes = [vp, vp, vp]
+    L.pwfs_mlp_forward.argtypes = [vp, vp, i32, vp, ctypes.c_float, vp]
+    L.pwfs_mlp_grad.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp]
+    L.pwfs_mlp_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+    L.pwfs_mlp_destroy.argtypes = [vp]
+    L.pwfs_mlp_destroy.restype = None
     for name in ("pwfs_validate", "pwfs_workspace_size", "pwfs_plan", "pwfs_forward", "pwfs_slopes",
-                 "pwfs_query", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read"):
+                 "pwfs_query", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
+                 "pwfs_gemm_workspace_size", "pwfs_gemm", "pwfs_row_rms", "pwfs_mlp_workspace_size",
+                 "pwfs_mlp_create", "pwfs_mlp_param_count", "pwfs_mlp_set_params", "pwfs_mlp_get_params",
+                 "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -272,6 +289,112 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             lib().pwfs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ dense products --
+
+def _aligned_workspace(nbytes: int, device):
+    import torch
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = (buf.data_ptr() + 255) & ~255
+    return buf, ptr
+
+
+def gemm(A, B, out=None, alpha: float = 1.0, precision: int = BF16X3, stream=None):
+    """out [M, N] = alpha * A [M, K] @ B [N, K]^T on the matrix cores."""
+    import torch
+    M, K = A.shape
+    N, K2 = B.shape
+    if K2 != K:
+        raise ValueError("inner dimensions differ")
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    n = ctypes.c_size_t()
+    check(lib().pwfs_gemm_workspace_size(M, N, K, precision, ctypes.byref(n)))
+    ws, ptr = _aligned_workspace(n.value, A.device)
+    check(lib().pwfs_gemm(_dev_ptr(A, "A", torch.float32), A.stride(0), _dev_ptr(B, "B", torch.float32),
+                          B.stride(0), _dev_ptr(out, "out", torch.float32), out.stride(0), M, N, K,
+                          float(alpha), precision, ctypes.c_void_p(ptr), n.value, _stream_ptr(stream)))
+    return out
+
+
+def row_rms(x, out=None, stream=None):
+    import torch
+    rows, cols = x.shape
+    if out is None:
+        out = torch.empty(rows, dtype=torch.float32, device=x.device)
+    check(lib().pwfs_row_rms(_dev_ptr(x, "x", torch.float32), x.stride(0), rows, cols,
+                             _dev_ptr(out, "out", torch.float32), _stream_ptr(stream)))
+    return out
+
+
+class MLP:
+    """The surrogate network on the library's kernels (see include/pwfs.h)."""
+
+    def __init__(self, sizes, max_batch: int, precision: int = BF16, device=None, stream=None):
+        import torch
+        self.sizes = [int(v) for v in sizes]
+        self.max_batch = int(max_batch)
+        self.precision = int(precision)
+        self.device = torch.device(device if device is not None else "cuda")
+        arr = (ctypes.c_int32 * len(self.sizes))(*self.sizes)
+        n = ctypes.c_size_t()
+        L = len(self.sizes) - 1
+        check(lib().pwfs_mlp_workspace_size(L, arr, self.max_batch, self.precision, ctypes.byref(n)))
+        self.workspace, ptr = _aligned_workspace(n.value, self.device)
+        h = ctypes.c_void_p()
+        check(lib().pwfs_mlp_create(L, arr, self.max_batch, self.precision, ctypes.c_void_p(ptr), n.value,
+                                    _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        c = ctypes.c_size_t()
+        check(lib().pwfs_mlp_param_count(self._h, ctypes.byref(c)))
+        self.n_params = c.value
+        self.loss_buf = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    def set_params(self, params, stream=None):
+        import torch
+        check(lib().pwfs_mlp_set_params(self._h, _dev_ptr(params, "params", torch.float32, self.n_params),
+                                        _stream_ptr(stream)))
+
+    def get_params(self, stream=None):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        check(lib().pwfs_mlp_get_params(self._h, _dev_ptr(out, "params", torch.float32), _stream_ptr(stream)))
+        return out
+
+    def forward(self, x, out=None, out_scale: float = 1.0, stream=None):
+        import torch
+        B = int(x.shape[0])
+        if out is None:
+            out = torch.empty((B, self.sizes[-1]), dtype=torch.float32, device=self.device)
+        check(lib().pwfs_mlp_forward(self._h, _dev_ptr(x, "x", torch.float32, B * self.sizes[0]), B,
+                                     _dev_ptr(out, "y", torch.float32, B * self.sizes[-1]), float(out_scale),
+                                     _stream_ptr(stream)))
+        return out
+
+    def grad(self, x, t, target_scale: float = 1.0, grads=None, stream=None):
+        """Loss (device scalar tensor) and, if ``grads`` is given, packed gradients."""
+        import torch
+        B = int(x.shape[0])
+        gp = ctypes.c_void_p(None) if grads is None else _dev_ptr(grads, "grads", torch.float32, self.n_params)
+        check(lib().pwfs_mlp_grad(self._h, _dev_ptr(x, "x", torch.float32, B * self.sizes[0]),
+                                  _dev_ptr(t, "t", torch.float32, B * self.sizes[-1]), B, float(target_scale),
+                                  _dev_ptr(self.loss_buf, "loss", torch.float32), gp, _stream_ptr(stream)))
+        return self.loss_buf
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+        check(lib().pwfs_mlp_adam(self._h, float(lr), float(beta1), float(beta2), float(eps), _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pwfs_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):

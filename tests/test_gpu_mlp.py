@@ -1,0 +1,153 @@
+"""Matrix-core GEMM, surrogate-network kernels and the surrogate pipeline.
+
+Tolerances: bf16 x3 (hi/lo split, ~fp32) products and gradients <= 1e-4
+normwise relative to the FP64 oracle; plain bf16 (8-bit significand
+operands, fp32 accumulation) <= 3e-2.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as MO
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    from paper_2602_06688_amd import pwfs as P
+    return P
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("M,N,K", [(128, 128, 32), (200, 77, 45), (1, 3, 500), (1000, 640, 320)])
+def test_gemm_matches_float64(M, N, K):
+    P = _P()
+    rng = np.random.default_rng(M + N + K)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((N, K)).astype(np.float32)
+    ref = A.astype(np.float64) @ B.astype(np.float64).T * 0.5
+    print(f"[gpu] gemm {M}x{N}x{K}", flush=True)
+    for prec, tol in ((P.BF16X3, 2e-5), (P.BF16, 3e-2)):
+        C = P.gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), alpha=0.5, precision=prec)
+        torch.cuda.synchronize()
+        e = _rel(C.cpu().numpy(), ref)
+        print(f"      precision {prec}: rel err {e:.2e}", flush=True)
+        assert e <= tol
+
+
+def _to_oracle(params, sizes):
+    out, off = [], 0
+    for i, o in zip(sizes[:-1], sizes[1:]):
+        W = params[off:off + o * i].reshape(o, i).T
+        off += o * i
+        b = params[off:off + o]
+        off += o
+        out.append((W.astype(np.float64), b.astype(np.float64)))
+    return out
+
+
+def _flat_grads(g):
+    return np.concatenate([np.concatenate([gw.T.ravel(), gb]) for gw, gb in g])
+
+
+@pytest.mark.parametrize("prec_name,tol", [("bf16x3", 1e-4), ("bf16", 3e-2)])
+def test_mlp_forward_grad_adam_vs_oracle(prec_name, tol):
+    P = _P()
+    from workloads.modes import init_params
+    prec = P.BF16X3 if prec_name == "bf16x3" else P.BF16
+    sizes = [40, 96, 64, 30]
+    B = 64
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((B, sizes[0])).astype(np.float32)
+    t = rng.standard_normal((B, sizes[-1])).astype(np.float32)
+    p0 = init_params(sizes, 11)
+    p0[-sizes[-1]:] = 0.1                      # non-zero output bias
+    print(f"[gpu] mlp {prec_name} sizes {sizes}", flush=True)
+    mlp = P.MLP(sizes, max_batch=128, precision=prec)
+    mlp.set_params(torch.from_numpy(p0).cuda())
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    y = mlp.forward(xd, out_scale=2.0)
+    g = torch.zeros(mlp.n_params, dtype=torch.float32, device="cuda")
+    loss = mlp.grad(xd, td, target_scale=0.5, grads=g)
+    torch.cuda.synchronize()
+    params = _to_oracle(p0, sizes)
+    y_ref, cache = MO.forward(params, x)
+    assert _rel(y.cpu().numpy(), 2.0 * y_ref) <= tol
+    l_ref, dy = MO.mse(y_ref, 0.5 * t.astype(np.float64))
+    g_ref = _flat_grads(MO.backward(params, cache, dy))
+    gl = g.cpu().numpy()
+    e_loss = abs(float(loss.item()) - l_ref) / l_ref
+    e_grad = _rel(gl, g_ref)
+    # per-tensor check too (first-layer weights see the longest chain)
+    off, worst = 0, 0.0
+    for i, o in zip(sizes[:-1], sizes[1:]):
+        worst = max(worst, _rel(gl[off:off + o * i], g_ref[off:off + o * i]))
+        off += o * i
+        worst = max(worst, _rel(gl[off:off + o], g_ref[off:off + o]))
+        off += o
+    print(f"      loss {e_loss:.2e}, grads {e_grad:.2e} (worst tensor {worst:.2e})", flush=True)
+    assert e_loss <= tol and worst <= (tol if prec == P.BF16X3 else 5e-2)
+    # two Adam steps against the oracle's update of the GPU's own gradients
+    w = p0.astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    for step in (1, 2):
+        if step == 2:
+            mlp.grad(xd, td, target_scale=0.5, grads=g)
+            torch.cuda.synchronize()
+            gl = g.cpu().numpy()
+        mlp.adam(1e-3)
+        w, m, v = MO.adam_step(w, gl, m, v, step, 1e-3)
+        torch.cuda.synchronize()
+        got = mlp.get_params().cpu().numpy()
+        err = np.abs(got - w).max() / np.abs(w).max()
+        print(f"      adam step {step}: max rel err {err:.2e}", flush=True)
+        assert err <= 1e-6
+
+
+def test_training_loss_decreases():
+    """A small teacher-student regression: 300 Adam steps cut the loss at least 4x."""
+    P = _P()
+    from workloads.modes import init_params
+    sizes = [64, 128, 128, 48]
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((4096, 64)).astype(np.float32)
+    teacher = _to_oracle(init_params(sizes, 99), sizes)
+    T = MO.forward(teacher, X)[0].astype(np.float32)
+    mlp = P.MLP(sizes, max_batch=256, precision=P.BF16)
+    mlp.set_params(torch.from_numpy(init_params(sizes, 1)).cuda())
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    print("[gpu] mlp training", flush=True)
+    first = None
+    for step in range(300):
+        i0 = (step * 256) % 4096
+        l = mlp.grad(Xd[i0:i0 + 256], Td[i0:i0 + 256])
+        if first is None:
+            torch.cuda.synchronize()
+            first = float(l.item())
+        mlp.adam(2e-3)
+    torch.cuda.synchronize()
+    last = float(l.item())
+    print(f"      loss {first:.3e} -> {last:.3e}", flush=True)
+    assert last < 0.25 * first
+
+
+def test_errors_and_limits():
+    P = _P()
+    mlp = P.MLP([40, 64, 30], max_batch=64, precision=P.BF16)
+    x = torch.zeros((65, 40), dtype=torch.float32, device="cuda")
+    with pytest.raises(P.PwfsError):
+        mlp.forward(x)                      # batch above max_batch
+    with pytest.raises(P.PwfsError):
+        mlp.adam(1e-3)                      # no gradient yet
+    t = torch.zeros((48, 30), dtype=torch.float32, device="cuda")
+    with pytest.raises(P.PwfsError):
+        mlp.grad(x[:48], t)                 # batch not a multiple of 32

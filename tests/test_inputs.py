@@ -50,3 +50,23 @@ def test_workload_shapes():
     assert o.shape == (2, 160, 160) and o.dtype == np.float32
     w4 = workload("cfg4")
     assert [s.n_fft for s in w4.sensors] == [256, 384, 512, 512, 768, 768]
+
+
+def test_kl_modes_orthonormal_ordered_and_scaled():
+    from workloads.modes import coefficient_sigmas, kl_modes
+    Z, ev = kl_modes(64, 0.12, 8.0, 25.0, 60)
+    pup = Z[0] != 0
+    m = Z[:, pup]
+    G = m @ m.T / m.shape[1]
+    assert np.abs(G - np.eye(60)).max() < 1e-10          # unit RMS, orthogonal
+    assert np.abs(m.mean(axis=1)).max() < 1e-10          # piston-free
+    assert (np.diff(ev) <= 1e-12).all()                  # decreasing variance
+    s = coefficient_sigmas(ev, 100.0, 750.0)
+    assert abs((s ** 2).sum() - (2 * math.pi * 100 / 750) ** 2) < 1e-12
+    # tip and tilt dominate a von Karman spectrum: the first two modes are
+    # (nearly) linear ramps
+    c = np.arange(64) - 31.5
+    ramp = np.broadcast_to(c[None, :], (64, 64)).ravel()[pup]
+    ramp = ramp / np.sqrt((ramp ** 2).mean())
+    proj = (m[:2] @ ramp / m.shape[1])
+    assert np.hypot(*proj) > 0.95
