@@ -104,6 +104,111 @@ def time_form(P, torch, s, x, n_frames, steps, warmup, ref_I, ref_S, dev, stream
     return out
 
 
+def surrogate_form(torch, dev, n_train, n_test, epochs, reps):
+    """Learned surrogate of the 160 px sensor: trained on n_train samples of
+    the plain kernels, timed on n_test held-out samples; errors are against
+    the plain path (the judge), next to the linear interaction-matrix method."""
+    from paper_2602_06688_amd.surrogate import SurrogatePipeline
+    from workloads import workload
+    from workloads.modes import coefficient_sigmas, kl_modes
+    w = workload("cfg5")
+    s = w.sensors[0]
+    ex = w.extra
+    t0 = time.perf_counter()
+    modes, ev = kl_modes(s.n_pupil, s.obstruction, s.diameter_m, w.L0_m, ex["n_modes"])
+    sig = coefficient_sigmas(ev, ex["residual_rms_nm"], s.lambdas_nm[0])
+    pipe = SurrogatePipeline(s, modes, sig, device=dev)
+    z, S = pipe.generate(n_train, seed=w.seeds[0])
+    zt, St = pipe.generate(n_test, seed=ex["test_seed"])
+    torch.cuda.synchronize(dev)
+    t_data = time.perf_counter() - t0
+    pipe.interaction_matrix()
+    e_lin = pipe.rel_error(pipe.linear_predict(zt), St)
+    rep = pipe.train(z, S, hidden=(ex["hidden"], ex["hidden"]), epochs=epochs, batch=1024, lr=1e-3)
+    out = torch.empty_like(St)
+    pipe.predict(zt, out=out)
+    e_nn = pipe.rel_error(out, St)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pipe.predict(zt, out=out)
+    torch.cuda.synchronize(dev)
+    dt = (time.perf_counter() - t0) / reps
+    sizes = [ex["n_modes"], ex["hidden"], ex["hidden"], 2 * s.n_subap ** 2]
+    fl = 2.0 * sum(a * b for a, b in zip(sizes[:-1], sizes[1:]))
+    ach = fl * n_test / dt / 1e12
+    print(f"# surrogate: {n_test / dt:.0f} frames/s, error {e_nn:.3e} (linear IM {e_lin:.3e}), "
+          f"train {rep.seconds:.1f} s", file=sys.stderr, flush=True)
+    return {"value": round(n_test / dt, 1), "unit": "frames/s",
+            "slope_rel_rms_vs_plain": e_nn, "linear_im_slope_rel_rms_vs_plain": e_lin,
+            "train_samples": n_train, "test_samples": n_test, "epochs": epochs,
+            "train_seconds": round(rep.seconds, 2), "data_seconds": round(t_data, 2),
+            "loss_first_last": [rep.losses[0], rep.losses[-1]],
+            "roofline": {"kernel": "k_gemm (MLP forward, bf16 weights, fp32 accumulation)", "bound": "mfma",
+                         "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                         "frac": round(ach / MFMA_PEAK_TFLOPS["bf16"], 4), "flops_per_frame": fl,
+                         "traffic": None}}
+
+
+def hetero_form(P, torch, dev, stream, steps: int, graph_reps: int = 200):
+    """Six sensors (80-240 px pupils, FFT 256-768, 16-96 points, 3 wavelengths)
+    in one plan: autotuned execution, timesteps/s over the 500-frame batch, and
+    the per-timestep latency of a HIP graph holding one timestep."""
+    import numpy as np
+    from paper_2602_06688_amd.autotune import autotune
+    from workloads import workload, workload_opd
+    w = workload("cfg4")
+    F = w.n_frames
+    opds = [workload_opd(w, i) for i in range(len(w.sensors))]
+    x = torch.from_numpy(np.concatenate([o.reshape(F, -1) for o in opds], axis=1)).to(dev)
+    plan = P.Plan(list(w.sensors), max_frames=F, device=dev, stream=stream)
+    I = plan.new_intensity(F)
+    S = plan.new_slopes(F)
+    Fl = torch.zeros((F, len(w.sensors)), dtype=torch.float32, device=dev)
+    tune = autotune(plan, lambda: plan.forward(x, I, stream=stream), F, reps=2)
+    for _ in range(1):
+        plan.step(x, I, S, Fl, stream=stream)
+    torch.cuda.synchronize(dev)
+    plan.profile(8192)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.step(x, I, S, Fl, stream=stream)
+    torch.cuda.synchronize(dev)
+    dt = time.perf_counter() - t0
+    kms = {k: plan.profile_read(k) for k in ("field", "rows", "cols", "slopes", "hetero")}
+    plan.profile(0)
+    gpu_ms = sum(v[0] for v in kms.values())
+    path = sum(nominal_flops(s)["path"] for s in w.sensors)
+    ach = path * F * steps / (gpu_ms / 1e3) / 1e12
+    # one timestep (frame 0 of every sensor) captured in a graph, replayed
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(device=dev)
+    x1, I1, S1, F1 = x[:1], I[:1], S[:1], Fl[:1]
+    with torch.cuda.stream(side):
+        plan.step(x1, I1, S1, F1, stream=side)
+    side.synchronize()
+    ref = S1.clone()
+    with torch.cuda.graph(g, stream=side):
+        plan.step(x1, I1, S1, F1, stream=side)
+    g.replay()
+    torch.cuda.synchronize(dev)
+    same = bool(torch.equal(S1, ref))
+    t0 = time.perf_counter()
+    for _ in range(graph_reps):
+        g.replay()
+    torch.cuda.synchronize(dev)
+    lat = (time.perf_counter() - t0) / graph_reps * 1e3
+    print(f"# hetero: {F * steps / dt:.1f} timesteps/s ({tune.get('mode')}, chunk {tune.get('chunk')}), "
+          f"graph timestep {lat:.3f} ms", file=sys.stderr, flush=True)
+    return {"value": round(F * steps / dt, 2), "unit": "timesteps/s",
+            "workload": w.name, "frames": F, "ms_per_step": round(dt / steps * 1e3, 3),
+            "tuning": {k: tune[k] for k in ("mode", "chunk", "wg_per_cu", "row_groups") if k in tune},
+            "graph_timestep_ms": round(lat, 4), "graph_replay_matches_eager": same,
+            "roofline": {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(ach / FP32_PEAK_TFLOPS, 4), "flops_per_timestep": path, "traffic": None,
+                         "kernel_ms": {k: round(v[0], 3) for k, v in kms.items() if v[1]}}}
+
+
 def measured_traffic(kernel: str, frames_per_launch: float):
     """HBM bytes per launch from the committed counter summary, or None when
     the kernel sources have changed since the counters were taken."""
@@ -155,6 +260,10 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-frames", type=int, default=32)
     ap.add_argument("--no-forms", action="store_true", help="time only the plain FP32 path")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate form")
+    ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous six-sensor batch")
+    ap.add_argument("--surrogate-train", type=int, default=200_000)
+    ap.add_argument("--surrogate-epochs", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -222,6 +331,10 @@ def main() -> int:
                                             ("mfma_bf16", PREC_BF16, 1, "bf16")):
             forms[label] = time_form(P, torch, s.with_(precision=prec), x, w.n_frames, max(2, args.steps // 2),
                                      1, I, S, dev, stream, label, terms, dt_name)
+    if not args.no_surrogate:
+        forms["surrogate"] = surrogate_form(torch, dev, args.surrogate_train, 20_000, args.surrogate_epochs, 5)
+    if not args.no_hetero:
+        forms["hetero6_poly3"] = hetero_form(P, torch, dev, stream, max(2, args.steps // 5))
 
     frames = w.n_frames * args.steps
     value = frames / dt

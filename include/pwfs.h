@@ -151,6 +151,27 @@ int pwfs_forward(pwfs_plan_t plan, const float* d_opd_nm, int n_frames, float* d
 int pwfs_slopes(pwfs_plan_t plan, const float* d_intensity, int n_frames, float* d_slopes,
                 float* d_flux, void* hip_stream);
 
+/*
+ * Execution tuning of a plan (chosen by the autotuner, see autotune.py).
+ *  mode       PWFS_MODE_LAUNCHES: per sensor, a field, a row and a column
+ *             launch per pass; PWFS_MODE_PERSISTENT: one persistent launch per
+ *             pass for all sensors, whose workgroups claim field, row and
+ *             column work items from a device counter (a sensor's row items
+ *             wait for its field items, its column items for its row items).
+ *             Both modes give bit-identical results.
+ *  chunk      frames per pass, 1 .. max_chunk (set by the workspace size)
+ *  wg_per_cu  persistent workgroups per compute unit, 1 .. 8
+ *  row_groups minimum number of row-pass work items per pass
+ */
+enum { PWFS_MODE_LAUNCHES = 0, PWFS_MODE_PERSISTENT = 1 };
+typedef struct {
+  int32_t mode, chunk, wg_per_cu, row_groups, max_chunk, reserved[3];
+} pwfs_tuning;
+int pwfs_get_tuning(pwfs_plan_t plan, pwfs_tuning* out);
+/* PWFS_EUNSUPPORTED for the persistent mode unless every sensor is FP32 with
+ * N >= 256 and at most 3 non-zero inputs per first-stage butterfly. */
+int pwfs_set_tuning(pwfs_plan_t plan, const pwfs_tuning* tuning);
+
 /* Geometry and packing of sensor `sensor` of the plan. */
 int pwfs_query(pwfs_plan_t plan, int sensor, pwfs_sensor_info* info);
 
@@ -165,7 +186,7 @@ int pwfs_valid_map(pwfs_plan_t plan, int sensor, uint8_t* host_out);
  * the pool.  Not for use under graph capture.
  * pwfs_profile_read waits for the recorded events of one kernel kind
  * (0 = row pass, 1 = column pass, 2 = slope stage, 3 = matrix-core forward,
- * 4 = pupil-field pass)
+ * 4 = pupil-field pass, 5 = persistent heterogeneous pass)
  * and returns their summed duration in ms and their number.
  */
 int pwfs_profile(pwfs_plan_t plan, int max_launches);

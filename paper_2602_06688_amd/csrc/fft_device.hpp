@@ -156,9 +156,9 @@ template <int N> struct FftPlan;
 template <> struct FftPlan<64>  { static constexpr int T = 8;  static constexpr int NS = 2; static constexpr int r[2] = {8, 8}; };
 template <> struct FftPlan<128> { static constexpr int T = 16; static constexpr int NS = 3; static constexpr int r[3] = {8, 2, 8}; };
 template <> struct FftPlan<256> { static constexpr int T = 32; static constexpr int NS = 3; static constexpr int r[3] = {8, 4, 8}; };
-template <> struct FftPlan<384> { static constexpr int T = 16; static constexpr int NS = 4; static constexpr int r[4] = {8, 8, 2, 3}; };
+template <> struct FftPlan<384> { static constexpr int T = 32; static constexpr int NS = 5; static constexpr int r[5] = {4, 4, 4, 2, 3}; };
 template <> struct FftPlan<512> { static constexpr int T = 64; static constexpr int NS = 3; static constexpr int r[3] = {8, 8, 8}; };
-template <> struct FftPlan<768> { static constexpr int T = 32; static constexpr int NS = 4; static constexpr int r[4] = {8, 8, 4, 3}; };
+template <> struct FftPlan<768> { static constexpr int T = 64; static constexpr int NS = 5; static constexpr int r[5] = {4, 4, 4, 4, 3}; };
 
 template <int N, int S, bool INV>
 struct StageInfo {

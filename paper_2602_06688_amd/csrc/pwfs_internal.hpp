@@ -33,11 +33,13 @@ struct SensorPlan {
   double sumA2;
   std::vector<uint8_t> valid_host;
   size_t opd_offset, int_offset, slope_offset;
+  float2* rbuf = nullptr;   // this sensor's pass scratch
 };
 
 struct Layout {
   std::vector<size_t> offsets;  // [sensor][region]
-  size_t rbuf_offset = 0, rbuf_bytes = 0, total = 0;
+  std::vector<size_t> sensor_rbuf;
+  size_t rbuf_offset = 0, rbuf_bytes = 0, counters_offset = 0, total = 0;
   int chunk = 1;
 };
 
@@ -45,6 +47,7 @@ Geometry geometry(const pwfs_sensor_desc& d);
 void set_last_error(const char* msg);   // message returned by pwfs_last_error
 void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vector<uint8_t>& V);
 int fft_lanes(int N);
+int fft_r0(int N);
 size_t rbuf_field_offset(const pwfs_sensor_desc& d, int nf);
 
 // MFMA (split-precision DFT-as-GEMM) form
@@ -59,7 +62,7 @@ int forward_mfma(const SensorPlan& sp, const float* opd, long long opd_stride, f
 
 // Optional per-kernel timing: HIP events recorded on the launch stream
 // around each kernel (pool created when profiling is switched on).
-enum KernelId { K_ROWS = 0, K_COLS = 1, K_SLOPES = 2, K_MFMA = 3, K_FIELD = 4, kKernelIds = 8 };
+enum KernelId { K_ROWS = 0, K_COLS = 1, K_SLOPES = 2, K_MFMA = 3, K_FIELD = 4, K_HETERO = 5, kKernelIds = 8 };
 
 struct Prof {
   bool on = false;
@@ -82,7 +85,9 @@ struct Prof {
 
 struct pwfs_plan_s {
   std::vector<pwfs::SensorPlan> s;
-  int max_frames = 0, chunk = 1;
+  int max_frames = 0, chunk = 1, max_chunk = 1, n_cu = 256;
+  pwfs_tuning tune{};
+  int* counters = nullptr;      // persistent-pass claim and dependency counters
   size_t opd_stride = 0, int_stride = 0, slope_stride = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;

@@ -123,11 +123,11 @@ struct FftPair {
 // --------------------------------------------------------------- field ----
 // E0 = A exp(i 2 pi OPD / lambda): phase formed and reduced to [-pi, pi] in
 // float64, then float32 sincos.
-__global__ __launch_bounds__(kBlock) void k_field(FieldArgs p) {
+__device__ __forceinline__ void field_body(const FieldArgs& p, int bid) {
   const int DD = p.D * p.D;
   const int blocks = (DD + kBlock - 1) / kBlock;
-  const int b = blockIdx.x % blocks;
-  const int fl = blockIdx.x / blocks;     // frame * n_lam + lam
+  const int b = bid % blocks;
+  const int fl = bid / blocks;            // frame * n_lam + lam
   const int lam = fl % p.n_lam, f = fl / p.n_lam;
   const int i = b * kBlock + threadIdx.x;
   if (i >= DD) return;
@@ -140,22 +140,23 @@ __global__ __launch_bounds__(kBlock) void k_field(FieldArgs p) {
   p.field[(size_t)fl * DD + i] = make_float2(a * cs, a * sn);
 }
 
+__global__ __launch_bounds__(kBlock) void k_field(FieldArgs p) { field_body(p, blockIdx.x); }
+
 // ---------------------------------------------------------------- rows ----
-template <int N, int QM>
-__global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
+template <int N, int QM_>
+__device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* smem) {
   using P = FftPlan<N>;
   constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
+  constexpr int QM = QM_ < R0 ? QM_ : R0;
   constexpr int RW = RowTile<N>::RW, RPG = RW / G, BL = BufLen<N>::value, NL = NB0 * QM;
   static_assert(RPG >= 1 && RW % G == 0, "row tile");
 
-  extern __shared__ float2 smem[];
   float2* s_tw = smem;
   float2* s_m = s_tw + N;
   float2* s_buf = s_m + N;
   float2* s_tile = s_buf + G * BL;
 
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
-  int bid = blockIdx.x;
   const int agi = bid % p.n_agroups;
   bid /= p.n_agroups;
   const int rb = bid % p.rowblocks;
@@ -239,21 +240,27 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
   }
 }
 
-// ------------------------------------------------------------- columns ----
 template <int N, int QM>
-__global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
+__global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
+  extern __shared__ float2 smem[];
+  rows_body<N, QM>(p, blockIdx.x, smem);
+}
+
+// ------------------------------------------------------------- columns ----
+template <int N, int QM_>
+__device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* smem) {
   using P = FftPlan<N>;
   constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
+  constexpr int QM = QM_ < R0 ? QM_ : R0;
   constexpr int BL = BufLen<N>::value, NL = NB0 * QM;
 
-  extern __shared__ float2 smem[];
   float2* s_tw = smem;
   float2* s_m = s_tw + N;               // [n_lam][N]
   float2* s_buf = s_m + p.n_lam * N;
 
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
-  const int cb = blockIdx.x % p.colblocks;
-  const int f = blockIdx.x / p.colblocks;
+  const int cb = bid % p.colblocks;
+  const int f = bid / p.colblocks;
   const int xc = cb * G + g;
   const bool live = xc < p.Nc;
   const int xcl = live ? xc : 0;
@@ -336,6 +343,12 @@ __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
   }
 }
 
+template <int N, int QM>
+__global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
+  extern __shared__ float2 smem[];
+  cols_body<N, QM>(p, blockIdx.x, smem);
+}
+
 // -------------------------------------------------------------- slopes ----
 __global__ __launch_bounds__(kBlock) void k_slopes(SlopeArgs p) {
   extern __shared__ float s_q[];        // [4][n*n]
@@ -384,6 +397,109 @@ __global__ __launch_bounds__(kBlock) void k_slopes(SlopeArgs p) {
     out[nn + s] = sy;
   }
   if (p.flux && tid == 0) p.flux[(long long)f * p.flux_stride] = (float)flux;
+}
+
+}  // namespace pwfs
+
+// ============================================ persistent heterogeneous pass ==
+// One launch runs the field, row and column passes of every sensor of a
+// plan.  Work items are numbered kind-major (all field items, then all row
+// items, then all column items; within a kind, sensors in `order`, largest
+// first); each workgroup claims the next item from counters[0].  A sensor's
+// row items wait until all its field items are done, its column items until
+// all its row items are done (counters[1 + 2 s + 0 / 1]).  Completion is
+// published with an agent-scope release after a workgroup barrier, waits use
+// agent-scope acquire loads, so data written on one XCD is read coherently
+// on another.  Items are claimed in increasing order and only wait for
+// smaller items that running workgroups already own, so every wait ends; a
+// spin limit turns a broken schedule into an error flag instead of a hang.
+namespace pwfs {
+
+constexpr int kMaxHetero = 8;
+
+struct HeteroArgs {
+  FieldArgs field[kMaxHetero];
+  RowArgs rows[kMaxHetero];
+  ColArgs cols[kMaxHetero];
+  int nfft[kMaxHetero];
+  int n_items[3][kMaxHetero];
+  int order[kMaxHetero];
+  int n_sensors, total, spin_limit;
+  int* counters;   // [0] claim, [1 + 2 s] field done, [2 + 2 s] rows done, [1 + 2 kMaxHetero] error flag
+};
+
+__global__ void k_counter_reset(int* c, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
+}
+
+template <int N>
+__device__ __forceinline__ void hetero_rows(const RowArgs& a, int bid, float2* smem) {
+  rows_body<N, 3>(a, bid, smem);
+}
+template <int N>
+__device__ __forceinline__ void hetero_cols(const ColArgs& a, int bid, float2* smem) {
+  cols_body<N, 3>(a, bid, smem);
+}
+
+__global__ __launch_bounds__(kBlock, 1) void k_hetero(HeteroArgs p) {
+  extern __shared__ float2 smem[];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&p.counters[0], 1);
+    __syncthreads();
+    int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: selects kernel arguments
+    __syncthreads();
+    if (item >= p.total) break;
+    int kind = 0, s = 0;
+    for (kind = 0; kind < 3; ++kind) {
+      bool found = false;
+      for (int o = 0; o < p.n_sensors; ++o) {
+        const int c = p.n_items[kind][p.order[o]];
+        if (item < c) {
+          s = p.order[o];
+          found = true;
+          break;
+        }
+        item -= c;
+      }
+      if (found) break;
+    }
+    if (kind > 0) {
+      if (threadIdx.x == 0) {
+        int* dep = &p.counters[1 + 2 * s + (kind - 1)];
+        const int need = p.n_items[kind - 1][s];
+        int spins = 0;
+        while (__hip_atomic_load(dep, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > p.spin_limit) {
+            atomicExch(&p.counters[1 + 2 * kMaxHetero], 1);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (kind == 0) {
+      field_body(p.field[s], item);
+    } else if (kind == 1) {
+      switch (p.nfft[s]) {
+        case 256: hetero_rows<256>(p.rows[s], item, smem); break;
+        case 384: hetero_rows<384>(p.rows[s], item, smem); break;
+        case 512: hetero_rows<512>(p.rows[s], item, smem); break;
+        default: hetero_rows<768>(p.rows[s], item, smem); break;
+      }
+    } else {
+      switch (p.nfft[s]) {
+        case 256: hetero_cols<256>(p.cols[s], item, smem); break;
+        case 384: hetero_cols<384>(p.cols[s], item, smem); break;
+        case 512: hetero_cols<512>(p.cols[s], item, smem); break;
+        default: hetero_cols<768>(p.cols[s], item, smem); break;
+      }
+    }
+    __syncthreads();   // every lane's stores of this item are issued and the LDS is free
+    if (threadIdx.x == 0 && kind < 2)
+      __hip_atomic_fetch_add(&p.counters[1 + 2 * s + kind], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 }  // namespace pwfs

@@ -137,7 +137,8 @@ Geometry geometry(const pwfs_sensor_desc& d) {
   g.n_lam = d.n_lambda;
   g.n_a = d.n_mod / 2 + 1;
   if (g.n_a > d.n_mod) g.n_a = d.n_mod;
-  g.qmax = (g.D + (g.N / 8) - 1) / (g.N / 8);
+  const int stride0 = g.N / fft_r0(g.N);   // distance between the inputs of a first-stage butterfly
+  g.qmax = (g.D + stride0 - 1) / stride0;
   return g;
 }
 
@@ -175,12 +176,12 @@ size_t rbuf_field_offset(const pwfs_sensor_desc& d, int nf) {
 
 int choose_chunk(const pwfs_sensor_desc* s, int n, int max_frames) {
   // enough frames per pass that the column pass launches >= ~2048 workgroups,
-  // with the scratch of one pass capped at 1 GiB
+  // with the scratch of one pass (all sensors) capped at 2 GiB
   size_t per = 0;
   int want = 1;
   for (int i = 0; i < n; ++i) {
     const Geometry g = geometry(s[i]);
-    per = std::max(per, rbuf_frame_bytes(s[i]));
+    per += rbuf_frame_bytes(s[i]);
     int colwg;
     if (s[i].precision == PWFS_FP32) {
       const int G = kBlock / fft_lanes(g.N);
@@ -190,10 +191,21 @@ int choose_chunk(const pwfs_sensor_desc* s, int n, int max_frames) {
     }
     want = std::max(want, (2048 + colwg - 1) / colwg);
   }
-  const size_t cap = (size_t)1 << 30;
+  const size_t cap = (size_t)2 << 30;
   int c = std::min(want, max_frames);
   if (per > 0) c = (int)std::min<size_t>((size_t)c, std::max<size_t>(1, cap / per));
   return std::max(1, c);
+}
+
+int fft_r0(int N) {
+  switch (N) {
+    case 64: return FftPlan<64>::r[0];
+    case 128: return FftPlan<128>::r[0];
+    case 256: return FftPlan<256>::r[0];
+    case 384: return FftPlan<384>::r[0];
+    case 512: return FftPlan<512>::r[0];
+    default: return FftPlan<768>::r[0];
+  }
 }
 
 int fft_lanes(int N) {
@@ -219,11 +231,16 @@ int layout(const pwfs_sensor_desc* s, int n, int max_frames, Layout* L) {
     }
   }
   L->chunk = choose_chunk(s, n, max_frames);
-  size_t per = 0;
-  for (int i = 0; i < n; ++i) per = std::max(per, rbuf_frame_bytes(s[i]));
+  // one scratch region per sensor (sensors of a persistent pass run together)
   L->rbuf_offset = off;
-  L->rbuf_bytes = per * (size_t)L->chunk;
-  off += align256(L->rbuf_bytes);
+  L->sensor_rbuf.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    L->sensor_rbuf[i] = off;
+    off += align256(rbuf_frame_bytes(s[i]) * (size_t)L->chunk);
+  }
+  L->counters_offset = off;
+  off += align256(sizeof(int) * 64);
+  L->rbuf_bytes = off - L->rbuf_offset;
   L->total = off;
   return PWFS_OK;
 }
@@ -335,30 +352,33 @@ int upload_tables(const pwfs_sensor_desc& d, char* ws, const size_t* off, hipStr
 }
 
 // ---------------------------------------------------- kernel launches ----
-template <int N, int QM>
-static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_stride, float* out,
-                       long long out_stride, int nf, float2* rbuf, hipStream_t st, Prof* prof) {
+// Arguments of the three passes of one sensor over `nf` frames.
+struct PassArgs {
+  FieldArgs fa;
+  RowArgs ra;
+  ColArgs ca;
+  unsigned grid_field, grid_rows, grid_cols;
+  size_t lds_rows, lds_cols;
+};
+
+template <int N>
+static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd_stride, float* out,
+                           long long out_stride, int nf, float2* rbuf, int row_group_target) {
   constexpr int T = FftPlan<N>::T, G = kBlock / T, RW = RowTile<N>::RW;
   const Geometry& g = sp.g;
-  const size_t field_elems = (size_t)nf * g.n_lam * g.D * g.D;
+  PassArgs pa{};
   float2* field = rbuf + rbuf_field_offset(sp.desc, nf);
-  {
-    FieldArgs fa{};
-    fa.opd = opd;
-    fa.amp = (const float*)sp.dev[R_AMP];
-    fa.field = field;
-    fa.opd_stride = opd_stride;
-    fa.D = g.D;
-    fa.n_lam = g.n_lam;
-    for (int l = 0; l < g.n_lam; ++l) fa.two_pi_over_lam[l] = 2.0 * kPi / sp.desc.lambda_nm[l];
-    const int blocks = (g.D * g.D + kBlock - 1) / kBlock;
-    const int fslot = prof->begin(st);
-    hipLaunchKernelGGL(k_field, dim3((unsigned)(nf * g.n_lam * blocks)), dim3(kBlock), 0, st, fa);
-    HIP_TRY(hipGetLastError(), "launch k_field");
-    prof->end(fslot, st, K_FIELD);
-  }
-  (void)field_elems;
-  RowArgs ra{};
+  FieldArgs& fa = pa.fa;
+  fa.opd = opd;
+  fa.amp = (const float*)sp.dev[R_AMP];
+  fa.field = field;
+  fa.opd_stride = opd_stride;
+  fa.D = g.D;
+  fa.n_lam = g.n_lam;
+  for (int l = 0; l < g.n_lam; ++l) fa.two_pi_over_lam[l] = 2.0 * kPi / sp.desc.lambda_nm[l];
+  pa.grid_field = (unsigned)(nf * g.n_lam * ((g.D * g.D + kBlock - 1) / kBlock));
+
+  RowArgs& ra = pa.ra;
   ra.field = field;
   ra.rx = (const float2*)sp.dev[R_RX];
   ra.mrow = (const float2*)sp.dev[R_MROW];
@@ -371,24 +391,21 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
   ra.n_lam = g.n_lam;
   ra.n_la = g.n_lam * g.n_a;
   ra.rowblocks = (g.D + RW - 1) / RW;
-  // split the (wavelength, cosine) pairs so a pass launches >= ~2048 groups
+  // split the (wavelength, cosine) pairs so a pass has >= row_group_target row groups
   {
     const long long base = (long long)ra.rowblocks * nf;
-    int groups = (int)std::min<long long>(ra.n_la, std::max<long long>(1, (2048 + base - 1) / base));
+    const long long want = std::max<long long>(1, (row_group_target + base - 1) / base);
+    const int groups = (int)std::min<long long>(ra.n_la, want);
     ra.ag = (ra.n_la + groups - 1) / groups;
     ra.n_agroups = (ra.n_la + ra.ag - 1) / ra.ag;
   }
   ra.win_lo = g.win_lo;
   ra.win_hi = g.win_hi;
   ra.full = g.full;
-  const size_t lds_rows = sizeof(float2) * (2 * N + G * BufLen<N>::value + (size_t)g.Nc * (RW + 1));
-  const unsigned grid_rows = (unsigned)((long long)nf * ra.rowblocks * ra.n_agroups);
-  int slot = prof->begin(st);
-  hipLaunchKernelGGL((k_rows<N, QM>), dim3(grid_rows), dim3(kBlock), lds_rows, st, ra);
-  HIP_TRY(hipGetLastError(), "launch k_rows");
-  prof->end(slot, st, K_ROWS);
+  pa.lds_rows = sizeof(float2) * (2 * N + G * BufLen<N>::value + (size_t)g.Nc * (RW + 1));
+  pa.grid_rows = (unsigned)((long long)nf * ra.rowblocks * ra.n_agroups);
 
-  ColArgs ca{};
+  ColArgs& ca = pa.ca;
   ca.rbuf = rbuf;
   ca.ry = (const float2*)sp.dev[R_RY];
   ca.mcol = (const float2*)sp.dev[R_MCOL];
@@ -406,11 +423,84 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
   ca.win_lo = g.win_lo;
   ca.win_hi = g.win_hi;
   ca.full = g.full;
-  const size_t lds_cols = sizeof(float2) * ((size_t)N + (size_t)g.n_lam * N + (size_t)G * BufLen<N>::value);
+  pa.lds_cols = sizeof(float2) * ((size_t)N + (size_t)g.n_lam * N + (size_t)G * BufLen<N>::value);
+  pa.grid_cols = (unsigned)(nf * ca.colblocks);
+  return pa;
+}
+
+static PassArgs build_pass_any(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost,
+                               int nf, float2* rbuf, int target) {
+  switch (sp.g.N) {
+    case 64: return build_pass<64>(sp, opd, os, out, ost, nf, rbuf, target);
+    case 128: return build_pass<128>(sp, opd, os, out, ost, nf, rbuf, target);
+    case 256: return build_pass<256>(sp, opd, os, out, ost, nf, rbuf, target);
+    case 384: return build_pass<384>(sp, opd, os, out, ost, nf, rbuf, target);
+    case 512: return build_pass<512>(sp, opd, os, out, ost, nf, rbuf, target);
+    default: return build_pass<768>(sp, opd, os, out, ost, nf, rbuf, target);
+  }
+}
+
+template <int N, int QM>
+static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_stride, float* out,
+                       long long out_stride, int nf, float2* rbuf, hipStream_t st, Prof* prof) {
+  const PassArgs pa = build_pass<N>(sp, opd, opd_stride, out, out_stride, nf, rbuf, 2048);
+  int slot = prof->begin(st);
+  hipLaunchKernelGGL(k_field, dim3(pa.grid_field), dim3(kBlock), 0, st, pa.fa);
+  HIP_TRY(hipGetLastError(), "launch k_field");
+  prof->end(slot, st, K_FIELD);
   slot = prof->begin(st);
-  hipLaunchKernelGGL((k_cols<N, QM>), dim3((unsigned)(nf * ca.colblocks)), dim3(kBlock), lds_cols, st, ca);
+  hipLaunchKernelGGL((k_rows<N, QM>), dim3(pa.grid_rows), dim3(kBlock), pa.lds_rows, st, pa.ra);
+  HIP_TRY(hipGetLastError(), "launch k_rows");
+  prof->end(slot, st, K_ROWS);
+  slot = prof->begin(st);
+  hipLaunchKernelGGL((k_cols<N, QM>), dim3(pa.grid_cols), dim3(kBlock), pa.lds_cols, st, pa.ca);
   HIP_TRY(hipGetLastError(), "launch k_cols");
   prof->end(slot, st, K_COLS);
+  return PWFS_OK;
+}
+
+// ------------------------------------------- persistent heterogeneous pass --
+bool hetero_eligible(const SensorPlan& sp) {
+  return sp.desc.precision == PWFS_FP32 && sp.g.qmax <= 3 && sp.g.N >= 256;
+}
+
+int forward_hetero(pwfs_plan_s* p, const float* opd, int f0, int nf, float* out, hipStream_t st) {
+  HeteroArgs ha{};
+  const int ns = (int)p->s.size();
+  if (ns > kMaxHetero) return fail(PWFS_EUNSUPPORTED, "persistent mode takes at most %d sensors", kMaxHetero);
+  size_t lds = 0;
+  std::vector<std::pair<double, int>> cost;
+  for (int i = 0; i < ns; ++i) {
+    const SensorPlan& sp = p->s[i];
+    const PassArgs pa = build_pass_any(sp, opd + sp.opd_offset + (long long)f0 * p->opd_stride,
+                                       (long long)p->opd_stride, out + sp.int_offset + (long long)f0 * p->int_stride,
+                                       (long long)p->int_stride, nf, sp.rbuf, p->tune.row_groups);
+    ha.field[i] = pa.fa;
+    ha.rows[i] = pa.ra;
+    ha.cols[i] = pa.ca;
+    ha.nfft[i] = sp.g.N;
+    ha.n_items[0][i] = (int)pa.grid_field;
+    ha.n_items[1][i] = (int)pa.grid_rows;
+    ha.n_items[2][i] = (int)pa.grid_cols;
+    lds = std::max(lds, std::max(pa.lds_rows, pa.lds_cols));
+    cost.push_back({-(double)sp.g.n_mod * sp.g.n_lam * sp.g.N * sp.g.N, i});
+  }
+  std::sort(cost.begin(), cost.end());
+  ha.n_sensors = ns;
+  int total = 0;
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < ns; ++i) total += ha.n_items[k][i];
+  for (int i = 0; i < ns; ++i) ha.order[i] = cost[i].second;   // largest sensors claim first
+  ha.total = total;
+  ha.counters = p->counters;
+  ha.spin_limit = 1 << 24;
+  hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, p->counters, 1 + 2 * kMaxHetero + 1);
+  HIP_TRY(hipGetLastError(), "launch k_counter_reset");
+  const int grid = p->n_cu * std::max(1, p->tune.wg_per_cu);
+  const int slot = p->prof.begin(st);
+  hipLaunchKernelGGL(k_hetero, dim3((unsigned)grid), dim3(kBlock), lds, st, ha);
+  HIP_TRY(hipGetLastError(), "launch k_hetero");
+  p->prof.end(slot, st, K_HETERO);
   return PWFS_OK;
 }
 
@@ -470,6 +560,7 @@ int prepare_kernels() {
   if ((rc = set_lds_limits_q<512>())) return rc;
   if ((rc = set_lds_limits_q<768>())) return rc;
   lds_limit((const void*)k_slopes);
+  lds_limit((const void*)k_hetero);
   done = true;
   return PWFS_OK;
 }
@@ -556,9 +647,22 @@ int pwfs_plan(const pwfs_sensor_desc* s, int n, int max_frames, void* ws, size_t
   if (!p) return fail(PWFS_EINVAL, "out of host memory");
   p->max_frames = max_frames;
   p->chunk = L.chunk;
+  p->max_chunk = L.chunk;
+  p->tune.mode = PWFS_MODE_LAUNCHES;
+  p->tune.chunk = L.chunk;
+  p->tune.wg_per_cu = 2;
+  p->tune.row_groups = 2048;
+  p->tune.max_chunk = L.chunk;
   p->ws = (char*)ws;
   p->ws_bytes = ws_bytes;
   p->rbuf = (float2*)((char*)ws + L.rbuf_offset);
+  p->counters = (int*)((char*)ws + L.counters_offset);
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      p->n_cu = ncu;
+  }
   size_t opd = 0, inten = 0, sl = 0;
   std::vector<std::vector<char>> keep;
   for (int i = 0; i < n; ++i) {
@@ -566,6 +670,7 @@ int pwfs_plan(const pwfs_sensor_desc* s, int n, int max_frames, void* ws, size_t
     sp.desc = s[i];
     sp.g = geometry(s[i]);
     for (int r = 0; r < kRegions; ++r) sp.dev[r] = (char*)ws + L.offsets[(size_t)i * kRegions + r];
+    sp.rbuf = (float2*)((char*)ws + L.sensor_rbuf[i]);
     std::vector<float> A;
     std::vector<uint8_t> V;
     pupil_and_valid(s[i], A, V);
@@ -616,12 +721,45 @@ int pwfs_forward(pwfs_plan_t p, const float* opd, int nf, float* out, void* stre
   if (nf < 1 || nf > p->max_frames)
     return fail(PWFS_ESTATE, "n_frames %d outside [1, max_frames=%d]", nf, p->max_frames);
   hipStream_t st = (hipStream_t)stream;
+  if (p->tune.mode == PWFS_MODE_PERSISTENT) {
+    for (int f0 = 0; f0 < nf; f0 += p->chunk) {
+      const int rc = forward_hetero(p, opd, f0, std::min(p->chunk, nf - f0), out, st);
+      if (rc) return rc;
+    }
+    return PWFS_OK;
+  }
   for (size_t i = 0; i < p->s.size(); ++i) {
     const SensorPlan& sp = p->s[i];
     const int rc = forward_sensor(p, (int)i, opd + sp.opd_offset, (long long)p->opd_stride,
                                   out + sp.int_offset, (long long)p->int_stride, nf, st);
     if (rc) return rc;
   }
+  return PWFS_OK;
+}
+
+int pwfs_get_tuning(pwfs_plan_t p, pwfs_tuning* t) {
+  if (!p || !t) return fail(PWFS_EINVAL, "NULL argument");
+  *t = p->tune;
+  t->max_chunk = p->max_chunk;
+  return PWFS_OK;
+}
+
+int pwfs_set_tuning(pwfs_plan_t p, const pwfs_tuning* t) {
+  if (!p || !t) return fail(PWFS_EINVAL, "NULL argument");
+  if (t->mode != PWFS_MODE_LAUNCHES && t->mode != PWFS_MODE_PERSISTENT) return fail(PWFS_EINVAL, "unknown mode");
+  if (t->chunk < 1 || t->chunk > p->max_chunk)
+    return fail(PWFS_EINVAL, "chunk must be in [1, %d] (the workspace's pass size)", p->max_chunk);
+  if (t->wg_per_cu < 1 || t->wg_per_cu > 8) return fail(PWFS_EINVAL, "wg_per_cu must be in [1, 8]");
+  if (t->row_groups < 1 || t->row_groups > (1 << 20)) return fail(PWFS_EINVAL, "row_groups out of range");
+  if (t->mode == PWFS_MODE_PERSISTENT) {
+    if ((int)p->s.size() > kMaxHetero) return fail(PWFS_EUNSUPPORTED, "persistent mode takes at most 8 sensors");
+    for (const SensorPlan& sp : p->s)
+      if (!hetero_eligible(sp))
+        return fail(PWFS_EUNSUPPORTED, "persistent mode needs FP32 sensors with N >= 256 and few non-zero first-stage inputs");
+  }
+  p->tune = *t;
+  p->tune.max_chunk = p->max_chunk;
+  p->chunk = t->chunk;
   return PWFS_OK;
 }
 
@@ -730,9 +868,9 @@ int forward_sensor(pwfs_plan_s* p, int i, const float* opd, long long opd_stride
     float* r = out + (long long)f0 * out_stride;
     int rc;
     if (sp.desc.precision == PWFS_FP32)
-      rc = forward_fp32(sp, o, opd_stride, r, out_stride, n, p->rbuf, st, &p->prof);
+      rc = forward_fp32(sp, o, opd_stride, r, out_stride, n, sp.rbuf, st, &p->prof);
     else
-      rc = forward_mfma(sp, o, opd_stride, r, out_stride, n, p->rbuf, st, &p->prof);
+      rc = forward_mfma(sp, o, opd_stride, r, out_stride, n, sp.rbuf, st, &p->prof);
     if (rc) return rc;
   }
   return PWFS_OK;

@@ -60,6 +60,14 @@ class CSensorInfo(ctypes.Structure):
     ]
 
 
+class CTuning(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("row_groups", ctypes.c_int32), ("max_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+MODE_LAUNCHES = 0
+MODE_PERSISTENT = 1
+
 _lib = None
 
 
@@ -95,6 +103,8 @@ def lib() -> ctypes.CDLL:
     L.pwfs_profile_read.argtypes = [vp, i32, P(ctypes.c_double), P(ctypes.c_int)]
     L.pwfs_destroy.argtypes = [vp]
     L.pwfs_destroy.restype = None
+    L.pwfs_get_tuning.argtypes = [vp, P(CTuning)]
+    L.pwfs_set_tuning.argtypes = [vp, P(CTuning)]
     ll = ctypes.c_longlong
     L.pwfs_gemm_workspace_size.argtypes = [i32, i32, i32, i32, P(ctypes.c_size_t)]
     L.pwfs_gemm.argtypes = [vp, ll, vp, ll, vp, ll, i32, i32, i32, ctypes.c_float, i32, vp, ctypes.c_size_t, vp]
@@ -273,7 +283,21 @@ class Plan:
         s, fl = self.slopes(I, slopes, flux, stream)
         return I, s, fl
 
-    KERNELS = {"rows": 0, "cols": 1, "slopes": 2, "mfma": 3, "field": 4}
+    KERNELS = {"rows": 0, "cols": 1, "slopes": 2, "mfma": 3, "field": 4, "hetero": 5}
+
+    def get_tuning(self) -> dict:
+        t = CTuning()
+        check(lib().pwfs_get_tuning(self._h, ctypes.byref(t)))
+        return {"mode": t.mode, "chunk": t.chunk, "wg_per_cu": t.wg_per_cu, "row_groups": t.row_groups,
+                "max_chunk": t.max_chunk}
+
+    def set_tuning(self, **kw) -> dict:
+        cur = self.get_tuning()
+        cur.update({k: v for k, v in kw.items() if v is not None})
+        t = CTuning(int(cur["mode"]), int(cur["chunk"]), int(cur["wg_per_cu"]), int(cur["row_groups"]),
+                    int(cur["max_chunk"]))
+        check(lib().pwfs_set_tuning(self._h, ctypes.byref(t)))
+        return self.get_tuning()
 
     def profile(self, max_launches: int) -> None:
         """Time the next ``max_launches`` kernel launches with HIP events (0 = off)."""

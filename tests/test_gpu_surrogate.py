@@ -17,7 +17,7 @@ def test_surrogate_beats_linear_interaction_matrix_and_falls_back():
     s = w.sensors[0]
     ex = w.extra
     modes, ev = kl_modes(s.n_pupil, s.obstruction, s.diameter_m, w.L0_m, ex["n_modes"])
-    sig = coefficient_sigmas(ev, ex["residual_nm"], s.lambdas_nm[0])
+    sig = coefficient_sigmas(ev, ex["residual_rms_nm"], s.lambdas_nm[0])
     pipe = SurrogatePipeline(s, modes, sig)
     print("[gpu] surrogate: generating 40k train / 4k test samples", flush=True)
     z, S = pipe.generate(40960, seed=5)
