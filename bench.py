@@ -323,6 +323,29 @@ def main() -> int:
         torch.cuda.synchronize(dev)
         del src, dst
 
+    # per-timestep latency: one frame's forward + slopes captured in a HIP graph
+    lat_plan = P.Plan([s], max_frames=1, device=dev, stream=stream)
+    side = torch.cuda.Stream(device=dev)
+    x1 = x[:1]
+    I1 = lat_plan.new_intensity(1)
+    S1 = lat_plan.new_slopes(1)
+    F1 = torch.zeros((1, 1), dtype=torch.float32, device=dev)
+    with torch.cuda.stream(side):
+        lat_plan.step(x1, I1, S1, F1, stream=side)
+    side.synchronize()
+    S_eager = S1.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        lat_plan.step(x1, I1, S1, F1, stream=side)
+    graph.replay()
+    torch.cuda.synchronize(dev)
+    graph_ok = bool(torch.equal(S1, S_eager)) and bool(torch.equal(S1, S[:1]))
+    t0 = time.perf_counter()
+    for _ in range(200):
+        graph.replay()
+    torch.cuda.synchronize(dev)
+    graph_ms = (time.perf_counter() - t0) / 200 * 1e3
+
     forms = {}
     if not args.no_forms:
         from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16X3
@@ -380,6 +403,9 @@ def main() -> int:
             "flops_per_frame": flops["path"],
             "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
         },
+        "graph_timestep": {"ms": round(graph_ms, 4), "frames_per_s": round(1e3 / graph_ms, 1),
+                           "replay_matches_batched": graph_ok,
+                           "what": "one frame (forward + slopes) per HIP graph replay"},
         "forms": forms,
         "cpu_baseline": cpu,
     }

@@ -58,20 +58,20 @@ def _flat_grads(g):
     return np.concatenate([np.concatenate([gw.T.ravel(), gb]) for gw, gb in g])
 
 
-@pytest.mark.parametrize("prec_name,tol", [("bf16x3", 1e-4), ("bf16", 3e-2)])
-def test_mlp_forward_grad_adam_vs_oracle(prec_name, tol):
+@pytest.mark.parametrize("prec_name,tol,sizes,B", [("bf16x3", 1e-4, [40, 96, 64, 30], 64),
+                                                   ("bf16", 3e-2, [40, 96, 64, 30], 64),
+                                                   ("bf16x3", 1e-4, [500, 1024, 1024, 3200], 128)])
+def test_mlp_forward_grad_adam_vs_oracle(prec_name, tol, sizes, B):
     P = _P()
     from workloads.modes import init_params
     prec = P.BF16X3 if prec_name == "bf16x3" else P.BF16
-    sizes = [40, 96, 64, 30]
-    B = 64
     rng = np.random.default_rng(3)
     x = rng.standard_normal((B, sizes[0])).astype(np.float32)
     t = rng.standard_normal((B, sizes[-1])).astype(np.float32)
     p0 = init_params(sizes, 11)
     p0[-sizes[-1]:] = 0.1                      # non-zero output bias
     print(f"[gpu] mlp {prec_name} sizes {sizes}", flush=True)
-    mlp = P.MLP(sizes, max_batch=128, precision=prec)
+    mlp = P.MLP(sizes, max_batch=max(128, B), precision=prec)
     mlp.set_params(torch.from_numpy(p0).cuda())
     xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
     y = mlp.forward(xd, out_scale=2.0)
