@@ -204,13 +204,14 @@ int pwfs_profile_read(pwfs_plan_t plan, int kernel, double* total_ms, int* launc
 int pwfs_gemm_workspace_size(int M, int N, int K, int precision, size_t* bytes);
 
 /*
- * C[M][N] = alpha * sum_k A[M][k] B[N][k]: all float32 device arrays,
- * row-major with leading dimensions lda >= K, ldb >= K, ldc >= N.  The
- * operands are converted into 16-bit planes in d_workspace (256-byte
+ * C[M][N] = alpha * sum_k A[M][k] B[N][k] + beta * C[M][N]: all float32
+ * device arrays, row-major with leading dimensions lda >= K, ldb >= K,
+ * ldc >= N; with beta == 0 the old C is not read (it may hold anything).
+ * The operands are converted into 16-bit planes in d_workspace (256-byte
  * aligned, >= pwfs_gemm_workspace_size bytes).  Asynchronous on hip_stream.
  */
 int pwfs_gemm(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc, int M, int N,
-              int K, float alpha, int precision, void* d_workspace, size_t ws_bytes, void* hip_stream);
+              int K, float alpha, float beta, int precision, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
 /* out[r] = sqrt(mean_c x[r][c]^2) for r < rows (float32 device arrays). */
 int pwfs_row_rms(const float* x, long long ld, int rows, int cols, float* out, void* hip_stream);

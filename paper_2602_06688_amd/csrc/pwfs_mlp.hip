@@ -50,7 +50,7 @@ struct GemmArgs {
   const uint16_t* b;
   long long a_plane, b_plane, lda, ldb;
   int M, N, K, mtiles, ntiles;
-  float alpha;
+  float alpha, beta;      // E_STORE: c = alpha * acc + beta * c (c is not read when beta == 0)
   float* c;               // fp32 output [M][ldc] (E_STORE, E_OUTPUT)
   long long ldc;
   const float* bias;      // [N]
@@ -116,7 +116,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
         if (m >= p.M || n >= p.N) continue;
         const float v = eng.value(i, j, e);
         if constexpr (EPI == E_STORE) {
-          p.c[(long long)m * p.ldc + n] = p.alpha * v;
+          float* cp = p.c + (long long)m * p.ldc + n;
+          *cp = (p.beta != 0.f) ? p.alpha * v + p.beta * *cp : p.alpha * v;
         } else if constexpr (EPI == E_HIDDEN) {
           const float zz = v + p.bias[n];
           p.z[(long long)m * p.ldz + n] = zz;
@@ -297,7 +298,8 @@ extern "C" int pwfs_gemm_workspace_size(int M, int N, int K, int precision, size
 }
 
 extern "C" int pwfs_gemm(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc,
-                         int M, int N, int K, float alpha, int precision, void* ws, size_t ws_bytes, void* stream) {
+                         int M, int N, int K, float alpha, float beta, int precision, void* ws, size_t ws_bytes,
+                         void* stream) {
   size_t need = 0;
   int rc = pwfs_gemm_workspace_size(M, N, K, precision, &need);
   if (rc) return rc;
@@ -322,6 +324,7 @@ extern "C" int pwfs_gemm(const float* A, long long lda, const float* B, long lon
   g.N = N;
   g.K = Kp;
   g.alpha = alpha;
+  g.beta = beta;
   g.c = C;
   g.ldc = ldc;
   return gemm_dispatch<E_STORE>(pl, g, st);

@@ -107,7 +107,8 @@ def lib() -> ctypes.CDLL:
     L.pwfs_set_tuning.argtypes = [vp, P(CTuning)]
     ll = ctypes.c_longlong
     L.pwfs_gemm_workspace_size.argtypes = [i32, i32, i32, i32, P(ctypes.c_size_t)]
-    L.pwfs_gemm.argtypes = [vp, ll, vp, ll, vp, ll, i32, i32, i32, ctypes.c_float, i32, vp, ctypes.c_size_t, vp]
+    L.pwfs_gemm.argtypes = [vp, ll, vp, ll, vp, ll, i32, i32, i32, ctypes.c_float, ctypes.c_float, i32, vp,
+                            ctypes.c_size_t, vp]
     L.pwfs_row_rms.argtypes = [vp, ll, i32, i32, vp, vp]
     L.pwfs_mlp_workspace_size.argtypes = [i32, P(ctypes.c_int32), i32, i32, P(ctypes.c_size_t)]
     L.pwfs_mlp_create.argtypes = [i32, P(ctypes.c_int32), i32, i32, vp, ctypes.c_size_t, vp, P(vp)]
@@ -331,21 +332,25 @@ def _aligned_workspace(nbytes: int, device):
     return buf, ptr
 
 
-def gemm(A, B, out=None, alpha: float = 1.0, precision: int = BF16X3, stream=None):
-    """out [M, N] = alpha * A [M, K] @ B [N, K]^T on the matrix cores."""
+def gemm(A, B, out=None, alpha: float = 1.0, beta: float = 0.0, precision: int = BF16X3, stream=None):
+    """out [M, N] = alpha * A [M, K] @ B [N, K]^T + beta * out on the matrix
+    cores (with beta == 0 the old contents of ``out`` are not read)."""
     import torch
     M, K = A.shape
     N, K2 = B.shape
     if K2 != K:
         raise ValueError("inner dimensions differ")
     if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs an output to accumulate into")
         out = torch.empty((M, N), dtype=torch.float32, device=A.device)
     n = ctypes.c_size_t()
     check(lib().pwfs_gemm_workspace_size(M, N, K, precision, ctypes.byref(n)))
     ws, ptr = _aligned_workspace(n.value, A.device)
     check(lib().pwfs_gemm(_dev_ptr(A, "A", torch.float32), A.stride(0), _dev_ptr(B, "B", torch.float32),
                           B.stride(0), _dev_ptr(out, "out", torch.float32), out.stride(0), M, N, K,
-                          float(alpha), precision, ctypes.c_void_p(ptr), n.value, _stream_ptr(stream)))
+                          float(alpha), float(beta), precision, ctypes.c_void_p(ptr), n.value,
+                          _stream_ptr(stream)))
     return out
 
 

@@ -1,17 +1,24 @@
 """Learned-surrogate form of the pyramid sensor: modal coefficients -> slopes.
 
-The network (fully connected, GELU, bf16 weights, fp32 accumulation) is
-trained on data the plain sensor kernels generate, on the GPU by the
-library's own forward/backward/Adam kernels.  The plain sensor stays the
-judge of the surrogate's error and its fallback for inputs outside the
-training distribution.  Every product and every sensor step runs in the
-library (``pwfs.gemm``, ``pwfs.Plan``, ``pwfs.MLP``); torch only holds
-device memory.
+The surrogate is the linear push-pull interaction matrix (the method without
+the network) plus a fully connected network (GELU, bf16 weights, fp32
+accumulation) that learns what the linear model misses -- mostly the
+sensor's loss of sensitivity (optical gain) and the cross-talk between modes
+at a residual of this size:
+
+    s(z) ~ IM z + r_rms * net(z).
+
+The network is trained on the residual s - IM z of data the plain sensor
+kernels generate, on the GPU by the library's own forward/backward/Adam
+kernels; its output layer starts at zero, so training starts from the linear
+model.  The plain sensor stays the judge of the surrogate's error and its
+fallback for inputs outside the training distribution.  Every product and
+every sensor step runs in the library (``pwfs.gemm``, ``pwfs.Plan``,
+``pwfs.MLP``); torch only holds device memory.
 
 Inputs of the network are the standard-normal draws z (coefficient / its
 RMS); OPD = sum_j z_j sigma_j Z_j * lambda / (2 pi) with the KL-like basis
-Z of ``workloads.modes``.  The network predicts slopes / s_rms, where s_rms
-is the RMS of the training slopes.
+Z of ``workloads.modes``.  r_rms is the RMS of the training residual.
 """
 
 from __future__ import annotations
@@ -95,15 +102,27 @@ class SurrogatePipeline:
         return P.gemm(z, self.im, precision=P.BF16X3)
 
     # ---------------------------------------------------------- surrogate --
+    def residual(self, z, s):
+        """s - IM z (device), the part of the slopes the linear model misses."""
+        r = s.clone()
+        P.gemm(z, self.im, out=r, alpha=-1.0, beta=1.0, precision=P.BF16X3)
+        return r
+
     def train(self, z, s, hidden=(1024, 1024), epochs: int = 20, batch: int = 1024, lr: float = 1e-3,
               lr_final: float = 5e-5, seed: int = 5, precision: int = P.BF16) -> TrainReport:
+        """Trains the network on the residual of (z, s) over the interaction
+        matrix (built first if missing); cosine learning-rate decay from
+        ``lr`` to ``lr_final``; one Adam step per batch."""
         from workloads.modes import init_params
         torch = self.torch
+        if self.im is None:
+            self.interaction_matrix()
         n = int(z.shape[0]) // batch * batch
         sizes = [self.n_modes, *hidden, self.n_out]
         self.mlp = P.MLP(sizes, max_batch=max(batch, self.chunk), precision=precision, device=self.device)
-        self.mlp.set_params(torch.from_numpy(init_params(sizes, seed)).to(self.device))
-        rms = P.row_rms(s[:n])
+        self.mlp.set_params(torch.from_numpy(init_params(sizes, seed, zero_last=True)).to(self.device))
+        r = self.residual(z[:n], s[:n])
+        rms = P.row_rms(r)
         self.s_scale = float(torch.sqrt((rms.double() ** 2).mean()).item())
         ts = 1.0 / self.s_scale
         steps = epochs * (n // batch)
@@ -114,7 +133,7 @@ class SurrogatePipeline:
             for i0 in range(0, n, batch):
                 frac = k / max(1, steps - 1)
                 lr_k = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * frac))
-                self.mlp.grad(z[i0:i0 + batch], s[i0:i0 + batch], ts)
+                self.mlp.grad(z[i0:i0 + batch], r[i0:i0 + batch], ts)
                 self.mlp.adam(lr_k)
                 k += 1
             losses.append(float(self.mlp.loss_buf.item()))
@@ -122,7 +141,8 @@ class SurrogatePipeline:
         return TrainReport(epochs, steps, time.perf_counter() - t0, losses)
 
     def predict(self, z, out=None):
-        """Surrogate slopes [n][n_out] (device), in chunks of max_batch."""
+        """Surrogate slopes [n][n_out] (device): the network in chunks of
+        max_batch, then the linear part accumulated on top."""
         torch = self.torch
         n = int(z.shape[0])
         if out is None:
@@ -131,6 +151,7 @@ class SurrogatePipeline:
         for i0 in range(0, n, mb):
             i1 = min(n, i0 + mb)
             self.mlp.forward(z[i0:i1], out=out[i0:i1], out_scale=self.s_scale)
+        P.gemm(z, self.im, out=out, alpha=1.0, beta=1.0, precision=P.BF16X3)
         return out
 
     def predict_with_fallback(self, z, rms_limit: float = 1.5):

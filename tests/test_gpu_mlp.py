@@ -43,6 +43,24 @@ def test_gemm_matches_float64(M, N, K):
         assert e <= tol
 
 
+def test_gemm_accumulates_with_beta_and_ignores_old_output_without():
+    P = _P()
+    rng = np.random.default_rng(11)
+    M, N, K = 300, 190, 70
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((N, K)).astype(np.float32)
+    C0 = rng.standard_normal((M, N)).astype(np.float32)
+    print(f"[gpu] gemm beta {M}x{N}x{K}", flush=True)
+    out = torch.from_numpy(C0).cuda()
+    P.gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), out=out, alpha=-1.0, beta=2.0)
+    ref = -(A.astype(np.float64) @ B.astype(np.float64).T) + 2.0 * C0.astype(np.float64)
+    assert _rel(out.cpu().numpy(), ref) <= 2e-5
+    nan = torch.full((M, N), float("nan"), device="cuda")
+    P.gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), out=nan, alpha=1.0, beta=0.0)
+    assert torch.isfinite(nan).all()
+    assert _rel(nan.cpu().numpy(), A.astype(np.float64) @ B.astype(np.float64).T) <= 2e-5
+
+
 def _to_oracle(params, sizes):
     out, off = [], 0
     for i, o in zip(sizes[:-1], sizes[1:]):

@@ -1,6 +1,7 @@
 """The learned-surrogate pipeline on the 160 px sensor at reduced size:
-data from the plain kernels, training on the GPU, comparison with the linear
-interaction-matrix method (the method without the network), fallback."""
+data from the plain kernels, training of the correction network on the GPU,
+comparison with the linear interaction-matrix method (the method without the
+network), fallback."""
 
 import numpy as np
 import pytest
@@ -30,7 +31,9 @@ def test_surrogate_beats_linear_interaction_matrix_and_falls_back():
     print(f"      linear IM {e_lin:.3e}, surrogate {e_nn:.3e}, losses {rep.losses[0]:.3e}->{rep.losses[-1]:.3e}",
           flush=True)
     assert rep.losses[-1] < rep.losses[0]
-    assert e_nn < e_lin
+    # the network must remove a real part of what the linear model misses
+    # (observed: 0.73 of the linear error at this size)
+    assert e_nn < 0.85 * e_lin
     # fallback: rows far outside the training distribution go to the plain sensor
     zz = zt[:64].clone()
     zz[::4] *= 3.0

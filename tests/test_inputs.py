@@ -70,3 +70,17 @@ def test_kl_modes_orthonormal_ordered_and_scaled():
     ramp = ramp / np.sqrt((ramp ** 2).mean())
     proj = (m[:2] @ ramp / m.shape[1])
     assert np.hypot(*proj) > 0.95
+
+
+def test_init_params_he_scale_and_zero_output_layer():
+    from workloads.modes import init_params
+    sizes = [500, 1024, 64]
+    a = init_params(sizes, 3)
+    b = init_params(sizes, 3, zero_last=True)
+    n0 = 500 * 1024
+    W0 = a[:n0]
+    assert abs(W0.std() - math.sqrt(2.0 / 500)) < 0.01 * math.sqrt(2.0 / 500)
+    assert np.array_equal(a[:n0 + 1024], b[:n0 + 1024])            # hidden layer unchanged
+    last = b[n0 + 1024:n0 + 1024 + 1024 * 64]
+    assert not last.any() and a[n0 + 1024:n0 + 1024 + 1024 * 64].any()
+    assert a.size == b.size == n0 + 1024 + 1024 * 64 + 64

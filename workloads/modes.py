@@ -95,12 +95,19 @@ def draws(n: int, n_modes: int, seed: int, chunk: int = 4096) -> np.ndarray:
     return out
 
 
-def init_params(sizes, seed: int) -> np.ndarray:
+def init_params(sizes, seed: int, zero_last: bool = False) -> np.ndarray:
     """He-normal weights (std sqrt(2/fan_in)), zero biases, packed per layer
-    as W [out][in] then b [out] (float32)."""
+    as W [out][in] then b [out] (float32).  With ``zero_last`` the output
+    layer's weights start at zero (the draws are still taken, so the hidden
+    layers are the same either way): a network that learns a correction then
+    starts from no correction."""
     rng = np.random.default_rng(seed)
     parts = []
-    for i, o in zip(sizes[:-1], sizes[1:]):
-        parts.append((rng.standard_normal((o, i)) * math.sqrt(2.0 / i)).ravel())
+    n_layers = len(sizes) - 1
+    for l, (i, o) in enumerate(zip(sizes[:-1], sizes[1:])):
+        w = rng.standard_normal((o, i)) * math.sqrt(2.0 / i)
+        if zero_last and l == n_layers - 1:
+            w[:] = 0.0
+        parts.append(w.ravel())
         parts.append(np.zeros(o))
     return np.concatenate(parts).astype(np.float32)
