@@ -17,9 +17,12 @@ LIB = os.path.join(HERE, "libpwfs.so")
 
 SOURCES = ["pwfs_lib.hip", "pwfs_mfma.hip", "pwfs_mlp.hip"]
 
-# packed fp32 instructions are kept out of every kernel
+# Packed fp32 instructions are kept out of every kernel.  Multiply-adds are
+# fused only within one source expression (-ffp-contract=on), so a kernel
+# body rounds the same wherever it is inlined: the persistent launch and the
+# per-sensor launches give bit-identical results.
 HIP_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]

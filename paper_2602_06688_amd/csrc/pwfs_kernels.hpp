@@ -31,6 +31,21 @@ template <> struct RowTile<64> { static constexpr int RW = 32; };
 template <> struct RowTile<128> { static constexpr int RW = 16; };
 template <> struct RowTile<384> { static constexpr int RW = 16; };
 
+// Slot of element (column xc, row yl) in the row pass's transpose tile
+// [Nc][RW].  Rows are unpadded; the row index is XOR-swizzled by bits of xc
+// so that a wavefront writing one yl for consecutive xc (the FFT output) and
+// one that reads whole rows in order (the coalesced copy-out) both hit
+// distinct 8-byte slots in every 16- or 32-lane LDS cycle.
+template <int RW>
+__device__ __forceinline__ int tile_slot(int xc, int yl) {
+  static_assert(RW == 8 || RW == 16 || RW == 32, "row tile");
+  int sw;
+  if constexpr (RW == 8) sw = ((xc >> 1) & 7) ^ ((xc >> 4) & 1);
+  else if constexpr (RW == 16) sw = (xc & 15) ^ ((xc >> 4) & 1);
+  else sw = xc & 31;
+  return xc * RW + (yl ^ sw);
+}
+
 struct FieldArgs {
   const float* opd;        // sensor's first frame of the chunk; frame stride opd_stride
   const float* amp;        // [D][D] pupil amplitude
@@ -151,9 +166,12 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
   constexpr int RW = RowTile<N>::RW, RPG = RW / G, BL = BufLen<N>::value, NL = NB0 * QM;
   static_assert(RPG >= 1 && RW % G == 0, "row tile");
 
+  // palindromic plans take twiddles and mask straight into registers; the
+  // others keep both tables in LDS
+  constexpr bool PAL = Palindromic<N>::value;
   float2* s_tw = smem;
-  float2* s_m = s_tw + N;
-  float2* s_buf = s_m + N;
+  float2* s_m = s_tw + (PAL ? 0 : N);
+  float2* s_buf = s_m + (PAL ? 0 : N);
   float2* s_tile = s_buf + G * BL;
 
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
@@ -165,15 +183,19 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
   const int la0 = agi * p.ag;
   const int la1 = min(la0 + p.ag, p.n_la);
 
-  for (int i = tid; i < N; i += kBlock) {
-    s_tw[i] = p.tw[i];
-    s_m[i] = p.mrow[i];
-  }
-  __syncthreads();
-
   FftPair<N, QM> fp;
-  fp.init(t, s_buf + g * BL, s_tw);
-  fp.set_mask(s_m);
+  if constexpr (PAL) {
+    fp.init(t, s_buf + g * BL, p.tw);
+    fp.set_mask(p.mrow);
+  } else {
+    for (int i = tid; i < N; i += kBlock) {
+      s_tw[i] = p.tw[i];
+      s_m[i] = p.mrow[i];
+    }
+    __syncthreads();
+    fp.init(t, s_buf + g * BL, s_tw);
+    fp.set_mask(s_m);
+  }
 
   // this lane's input columns
   int xx[NL];
@@ -187,23 +209,57 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
       xin[i * QM + q] = x < p.D;
     }
 
+  // With one wavelength the field rows of this lane group are the same for
+  // every (wavelength, cosine) pair of the workgroup.  Where they are few
+  // registers (HOLD) they are loaded once and kept; otherwise each row is
+  // loaded for each pair, the next row prefetched during the current
+  // transform.  The row tilt of the next pair is prefetched either way.
+  // outputs outside the image windows go to a per-lane spare slot past the
+  // tile, so the tile writes need no branches
+  const int spare = p.Nc * RW + t;
+  constexpr bool HOLD = RPG * NL <= 8;
+  constexpr int NH = HOLD ? RPG : 1;
+  float2 en[NH][NL];
+  int lam_loaded = -1;
+  float2 rxv[NL];
+  {
+    const float2* rx = p.rx + (size_t)la0 * p.D;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) rxv[l] = xin[l] ? rx[xx[l]] : czero();
+  }
+
   for (int la = la0; la < la1; ++la) {
     const int lam = la / p.n_a, a = la % p.n_a;
     const float2* e0 = p.field + ((size_t)f * p.n_lam + lam) * p.D * p.D;
-    const float2* rx = p.rx + (size_t)la * p.D;
-    float2 rxv[NL];
+    if (!HOLD || lam != lam_loaded) {
 #pragma unroll
-    for (int l = 0; l < NL; ++l) rxv[l] = xin[l] ? rx[xx[l]] : czero();
-    float2 en[NL];
-    {
-      const int yy = min(y0 + g * RPG, p.D - 1);
+      for (int rr = 0; rr < NH; ++rr) {
+        const int yy = min(y0 + g * RPG + rr, p.D - 1);
 #pragma unroll
-      for (int l = 0; l < NL; ++l) en[l] = e0[(size_t)yy * p.D + xx[l]];
+        for (int l = 0; l < NL; ++l) en[rr][l] = e0[(size_t)yy * p.D + xx[l]];
+      }
+      lam_loaded = lam;
+    }
+    float2 rxc[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) rxc[l] = rxv[l];
+    if (la + 1 < la1) {   // prefetch the next pair's row tilt
+      const float2* rx = p.rx + (size_t)(la + 1) * p.D;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) rxv[l] = xin[l] ? rx[xx[l]] : czero();
     }
 #pragma unroll 1
     for (int rr = 0; rr < RPG; ++rr) {
       const int yl = g * RPG + rr;
       const bool yin = y0 + yl < p.D;
+      float2 er[NL];   // this row's values, chosen by selects (no dynamic register indexing)
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        er[l] = en[0][l];
+#pragma unroll
+        for (int r2 = 1; r2 < NH; ++r2)
+          if (rr == r2) er[l] = en[r2][l];
+      }
       float2 v[V];
 #pragma unroll
       for (int i = 0; i < NB0; ++i)
@@ -211,22 +267,22 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
         for (int q = 0; q < R0; ++q) {
           if (q < QM) {
             const int l = i * QM + q;
-            v[i * R0 + q] = yin ? cmul(en[l], rxv[l]) : czero();
+            v[i * R0 + q] = yin ? cmul(er[l], rxc[l]) : czero();
           } else {
             v[i * R0 + q] = czero();
           }
         }
-      if (rr + 1 < RPG) {   // prefetch the next row of the field
+      if (!HOLD && rr + 1 < RPG) {   // prefetch the next row of the field
         const int yy = min(y0 + yl + 1, p.D - 1);
 #pragma unroll
-        for (int l = 0; l < NL; ++l) en[l] = e0[(size_t)yy * p.D + xx[l]];
+        for (int l = 0; l < NL; ++l) en[0][l] = e0[(size_t)yy * p.D + xx[l]];
       }
       fp.run(v);
 #pragma unroll
       for (int s = 0; s < V; ++s) {
         const int X = space_index<N>(t, s);
         const int xc = p.full ? X : window_index(X, p.D, p.win_lo, p.win_hi);
-        if (xc >= 0) s_tile[xc * (RW + 1) + yl] = v[s];
+        s_tile[xc >= 0 ? tile_slot<RW>(xc, yl) : spare] = v[s];
       }
     }
     __syncthreads();
@@ -234,7 +290,7 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
     const int rows = min(RW, p.D - y0);
     for (int e = tid; e < p.Nc * RW; e += kBlock) {
       const int xc = e / RW, yl = e % RW;
-      if (yl < rows) dst[(size_t)xc * p.Dp + y0 + yl] = s_tile[xc * (RW + 1) + yl];
+      if (yl < rows) dst[(size_t)xc * p.Dp + y0 + yl] = s_tile[tile_slot<RW>(xc, yl)];
     }
     __syncthreads();
   }
@@ -254,9 +310,12 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
   constexpr int QM = QM_ < R0 ? QM_ : R0;
   constexpr int BL = BufLen<N>::value, NL = NB0 * QM;
 
+  // palindromic plans: twiddles and mask straight into registers, LDS only
+  // for the exchange buffers; the others keep both tables in LDS
+  constexpr bool PAL = Palindromic<N>::value;
   float2* s_tw = smem;
-  float2* s_m = s_tw + N;               // [n_lam][N]
-  float2* s_buf = s_m + p.n_lam * N;
+  float2* s_m = s_tw + (PAL ? 0 : N);                    // [n_lam][N]
+  float2* s_buf = s_m + (PAL ? 0 : p.n_lam * N);
 
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
   const int cb = bid % p.colblocks;
@@ -265,12 +324,17 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
   const bool live = xc < p.Nc;
   const int xcl = live ? xc : 0;
 
-  for (int i = tid; i < N; i += kBlock) s_tw[i] = p.tw[i];
-  for (int i = tid; i < p.n_lam * N; i += kBlock) s_m[i] = p.mcol[i];
-  __syncthreads();
-
+  const float2* masks = p.mcol;
   FftPair<N, QM> fp;
-  fp.init(t, s_buf + g * BL, s_tw);
+  if constexpr (PAL) {
+    fp.init(t, s_buf + g * BL, p.tw);
+  } else {
+    for (int i = tid; i < N; i += kBlock) s_tw[i] = p.tw[i];
+    for (int i = tid; i < p.n_lam * N; i += kBlock) s_m[i] = p.mcol[i];
+    __syncthreads();
+    fp.init(t, s_buf + g * BL, s_tw);
+    masks = s_m;
+  }
 
   // this lane's input rows and whether they hold pupil data
   int yy[NL];
@@ -290,7 +354,7 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
 
   const size_t frame_base = (size_t)f * p.n_lam * p.n_a;
   for (int lam = 0; lam < p.n_lam; ++lam) {
-    fp.set_mask(s_m + lam * N);
+    fp.set_mask(masks + lam * N);
     const float2* rbl = p.rbuf + ((frame_base + (size_t)lam * p.n_a) * p.Nc + xcl) * p.Dp;
     const float2* ryl = p.ry + (size_t)lam * p.n_mod * p.D;
     float2 cn[NL], rn[NL];
@@ -350,38 +414,41 @@ __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
 }
 
 // -------------------------------------------------------------- slopes ----
-__global__ __launch_bounds__(kBlock) void k_slopes(SlopeArgs p) {
+// One workgroup per frame.  Block sums are work items (quadrant, subaperture)
+// spread over the NT threads; consecutive threads read consecutive blocks of
+// a pixel row.  NT = 1024 serves small frame counts, where the frame's own
+// latency is the cost.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_slopes(SlopeArgs p) {
   extern __shared__ float s_q[];        // [4][n*n]
-  __shared__ double s_red[kBlock];
+  __shared__ double s_red[NT];
   const int tid = threadIdx.x, f = blockIdx.x;
   const int nn = p.n * p.n;
   const float* I = p.in + (long long)f * p.in_stride;
 
-  double tsum = 0.0;
-  for (int s = tid; s < nn; s += kBlock) {
+  for (int it = tid; it < 4 * nn; it += NT) {
+    const int q = it / nn, s = it % nn;
     const int i = s / p.n, j = s % p.n;
-    float tot = 0.f;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float* blk = I + (size_t)(p.org_r[q] + i * p.b) * p.N + p.org_c[q] + j * p.b;
-      float acc = 0.f;
-      for (int r = 0; r < p.b; ++r)
-        for (int c = 0; c < p.b; ++c) acc += blk[(size_t)r * p.N + c];
-      s_q[q * nn + s] = acc;
-      tot += acc;
-    }
-    if (p.valid[s]) tsum += (double)tot;
+    const float* blk = I + (size_t)(p.org_r[q] + i * p.b) * p.N + p.org_c[q] + j * p.b;
+    float acc = 0.f;
+    for (int r = 0; r < p.b; ++r)
+      for (int c = 0; c < p.b; ++c) acc += blk[(size_t)r * p.N + c];
+    s_q[it] = acc;
   }
+  __syncthreads();
+  double tsum = 0.0;
+  for (int s = tid; s < nn; s += NT)
+    if (p.valid[s]) tsum += (double)(((s_q[s] + s_q[nn + s]) + s_q[2 * nn + s]) + s_q[3 * nn + s]);
   s_red[tid] = tsum;
   __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (tid < w) s_red[tid] += s_red[tid + w];
     __syncthreads();
   }
   const double flux = s_red[0];
   const float gnorm = (float)(flux / (double)p.n_valid);
   float* out = p.slopes + (long long)f * p.slope_stride;
-  for (int s = tid; s < nn; s += kBlock) {
+  for (int s = tid; s < nn; s += NT) {
     float sx = 0.f, sy = 0.f;
     if (p.valid[s]) {
       const float q0 = s_q[s], q1 = s_q[nn + s], q2 = s_q[2 * nn + s], q3 = s_q[3 * nn + s];

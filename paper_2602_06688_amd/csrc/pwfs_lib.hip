@@ -175,8 +175,10 @@ size_t rbuf_field_offset(const pwfs_sensor_desc& d, int nf) {
 }
 
 int choose_chunk(const pwfs_sensor_desc* s, int n, int max_frames) {
-  // enough frames per pass that the column pass launches >= ~2048 workgroups,
-  // with the scratch of one pass (all sensors) capped at 2 GiB
+  // enough frames per pass that the column pass launches >= ~16384 workgroups
+  // (16 rounds of the chip's resident workgroups, so a launch's tail is a
+  // small part of it), with the scratch of one pass (all sensors) capped at
+  // 2 GiB
   size_t per = 0;
   int want = 1;
   for (int i = 0; i < n; ++i) {
@@ -189,7 +191,7 @@ int choose_chunk(const pwfs_sensor_desc* s, int n, int max_frames) {
     } else {   // matrix-core form: one 128 x 128 tile grid of stage 2 per frame
       colwg = ((2 * g.Nc + 127) / 128) * ((g.Nc + 127) / 128);
     }
-    want = std::max(want, (2048 + colwg - 1) / colwg);
+    want = std::max(want, (16384 + colwg - 1) / colwg);
   }
   const size_t cap = (size_t)2 << 30;
   int c = std::min(want, max_frames);
@@ -402,7 +404,8 @@ static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd
   ra.win_lo = g.win_lo;
   ra.win_hi = g.win_hi;
   ra.full = g.full;
-  pa.lds_rows = sizeof(float2) * (2 * N + G * BufLen<N>::value + (size_t)g.Nc * (RW + 1));
+  constexpr bool PAL = Palindromic<N>::value;   // tables in registers, not LDS
+  pa.lds_rows = sizeof(float2) * ((PAL ? 0 : 2 * N) + G * BufLen<N>::value + (size_t)g.Nc * RW + T);
   pa.grid_rows = (unsigned)((long long)nf * ra.rowblocks * ra.n_agroups);
 
   ColArgs& ca = pa.ca;
@@ -423,7 +426,7 @@ static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd
   ca.win_lo = g.win_lo;
   ca.win_hi = g.win_hi;
   ca.full = g.full;
-  pa.lds_cols = sizeof(float2) * ((size_t)N + (size_t)g.n_lam * N + (size_t)G * BufLen<N>::value);
+  pa.lds_cols = sizeof(float2) * ((PAL ? 0 : (size_t)N + (size_t)g.n_lam * N) + (size_t)G * BufLen<N>::value);
   pa.grid_cols = (unsigned)(nf * ca.colblocks);
   return pa;
 }
@@ -559,11 +562,15 @@ int prepare_kernels() {
   if ((rc = set_lds_limits_q<384>())) return rc;
   if ((rc = set_lds_limits_q<512>())) return rc;
   if ((rc = set_lds_limits_q<768>())) return rc;
-  lds_limit((const void*)k_slopes);
+  lds_limit((const void*)k_slopes<kBlock>);
+  lds_limit((const void*)k_slopes<1024>);
   lds_limit((const void*)k_hetero);
   done = true;
   return PWFS_OK;
 }
+
+// below this many frames the slope stage runs 1024 threads per frame
+constexpr int kSlopesWideBelow = 64;
 
 int slopes_launch(const SensorPlan& sp, const float* in, long long in_stride, float* slopes, long long slope_stride,
                   float* flux, long long flux_stride, const float* ref, int nf, hipStream_t st, Prof* prof) {
@@ -590,7 +597,10 @@ int slopes_launch(const SensorPlan& sp, const float* in, long long in_stride, fl
     }
   const size_t lds = sizeof(float) * 4 * g.n * g.n;
   const int slot = prof ? prof->begin(st) : -1;
-  hipLaunchKernelGGL(k_slopes, dim3((unsigned)nf), dim3(kBlock), lds, st, a);
+  if (nf >= kSlopesWideBelow)
+    hipLaunchKernelGGL(k_slopes<kBlock>, dim3((unsigned)nf), dim3(kBlock), lds, st, a);
+  else
+    hipLaunchKernelGGL(k_slopes<1024>, dim3((unsigned)nf), dim3(1024), lds, st, a);
   HIP_TRY(hipGetLastError(), "launch k_slopes");
   if (prof) prof->end(slot, st, K_SLOPES);
   return PWFS_OK;
