@@ -1,0 +1,276 @@
+"""FP64 CPU oracle of the detector stage that follows the pyramid sensor.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import or call
+this module: only the tests, the smoke check of the entry file and the CPU
+baseline leg of the benchmark do.  It shares no code with the HIP library.
+
+The paper lists a ``CCD`` processing object between the sensor and the slope
+computer (Table 4) and gives its parameters in the SOUL listing of
+Appendix B: detector size, integration time, bandwidth, switches for photon,
+readout and excess noise, the readout level and the quantum efficiency.  It
+does not write the model down, so the readings here are the textbook ones:
+
+  1. expected photo-electrons per detector pixel: lam = n_e * (sum of the
+     rebin x rebin block of the normalised intensity), the block sum taken
+     in float64 in row-major order over the central rebin * n_det square of
+     the N x N plane;
+  2. photon noise: a Poisson draw of mean lam;
+  3. excess noise (electron-multiplying register at high gain): the output
+     of n electrons is Gamma(n, 1) distributed (mean n, variance n);
+  4. readout noise: plus a zero-mean Gaussian of RMS sigma_e.
+
+Random numbers come from the counter-based generator Philox4x64-10
+(Salmon, Moraes, Dror and Shaw, SC'11), keyed by (seed, 0); each draw has
+its own counter (pixel, frame, purpose, block), so any frame of any chunk
+gives the same numbers.  From a 64-bit word w, a uniform in [0, 1) is
+(w >> 11) * 2^-53; a normal is Box-Muller on two uniforms.  Poisson draws
+invert the CDF; the integer they return is decided in float64 with basic
+operations only (exp(-mu) is formed by a fixed Taylor series and repeated
+squaring), so an implementation that performs the same operations in the
+same order returns the same integers.  Gamma draws use Marsaglia and Tsang's
+method (ACM TOMS 2000).
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+PHOTON = 1
+READOUT = 2
+EXCESS = 4
+
+# purposes (third counter word)
+P_PHOTON, P_EXCESS, P_READOUT = 0, 1, 2
+
+POISSON_CHUNK = 256.0      # largest mean drawn by one inversion
+POISSON_KCAP = 1024        # inversion stops here (unreachable at mean <= 256 in practice)
+GAMMA_TRIES = 64           # Marsaglia-Tsang attempts before giving up (returns d)
+
+_M0 = np.uint64(0xD2E7470EE14C6C93)
+_M1 = np.uint64(0xCA5A826395121157)
+_W0 = np.uint64(0x9E3779B97F4A7C15)
+_W1 = np.uint64(0xBB67AE8584CAA73B)
+_LO32 = np.uint64(0xFFFFFFFF)
+_S32 = np.uint64(32)
+
+
+# --------------------------------------------------------------- Philox ---
+
+def _mulhilo(a: np.uint64, b: np.ndarray):
+    """(high, low) 64-bit halves of the 128-bit products a * b."""
+    b = np.asarray(b, np.uint64)
+    a_lo, a_hi = a & _LO32, a >> _S32
+    b_lo, b_hi = b & _LO32, b >> _S32
+    ll = a_lo * b_lo
+    lh = a_lo * b_hi
+    hl = a_hi * b_lo
+    hh = a_hi * b_hi
+    cross = (ll >> _S32) + (lh & _LO32) + (hl & _LO32)
+    hi = hh + (lh >> _S32) + (hl >> _S32) + (cross >> _S32)
+    with np.errstate(over="ignore"):
+        lo = a * b
+    return hi, lo
+
+
+def philox4x64(c0, c1, c2, c3, k0, k1):
+    """Philox4x64-10 of counters (c0, c1, c2, c3) (uint64 arrays, broadcast)
+    under key (k0, k1); returns the four output words."""
+    c0, c1, c2, c3 = (np.asarray(x, np.uint64) for x in np.broadcast_arrays(c0, c1, c2, c3))
+    k0 = np.uint64(k0)
+    k1 = np.uint64(k1)
+    with np.errstate(over="ignore"):
+        for r in range(10):
+            if r:
+                k0 = np.uint64(k0 + _W0)
+                k1 = np.uint64(k1 + _W1)
+            h0, l0 = _mulhilo(_M0, c0)
+            h1, l1 = _mulhilo(_M1, c2)
+            c0, c1, c2, c3 = h1 ^ c1 ^ k0, l1, h0 ^ c3 ^ k1, l0
+    return c0, c1, c2, c3
+
+
+def uniform(w) -> np.ndarray:
+    """[0, 1) float64 from 64-bit words."""
+    return (np.asarray(w, np.uint64) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+def box_muller(w0, w1) -> np.ndarray:
+    """Standard normal from two 64-bit words."""
+    u1 = 1.0 - uniform(w0)              # (0, 1]
+    u2 = uniform(w1)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
+# -------------------------------------------------------------- samplers ---
+
+def exp_neg(mu: np.ndarray) -> np.ndarray:
+    """exp(-mu) for 0 <= mu <= 256 with + - * / only: a 24-term Taylor
+    series at mu / 256 (Horner), then eight squarings."""
+    x = np.asarray(mu, np.float64) / 256.0
+    e = np.ones_like(x)
+    for i in range(24, 0, -1):
+        t = e * x
+        t = t / float(i)
+        e = 1.0 - t
+    for _ in range(8):
+        e = e * e
+    return e
+
+
+def poisson_inversion(mu: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Smallest k with u <= F(k) for Poisson(mu), F built by p_k = p_{k-1} mu / k
+    in float64; stops at POISSON_KCAP."""
+    mu = np.asarray(mu, np.float64)
+    u = np.asarray(u, np.float64)
+    p = exp_neg(mu)
+    F = p.copy()
+    k = np.zeros(mu.shape, np.int64)
+    live = u > F
+    while live.any():
+        kk = k[live] + 1
+        pp = p[live] * mu[live]
+        pp = pp / kk.astype(np.float64)
+        FF = F[live] + pp
+        k[live] = kk
+        p[live] = pp
+        F[live] = FF
+        idx = np.flatnonzero(live)
+        live[idx] = (u[idx] > FF) & (kk < POISSON_KCAP)
+    return k
+
+
+def poisson(lam: np.ndarray, pix: np.ndarray, frame: int, key) -> np.ndarray:
+    """Poisson(lam) per pixel: lam split into m = ceil(lam / 256) equal parts,
+    one inversion each (part j uses counter block j), summed."""
+    lam = np.asarray(lam, np.float64)
+    out = np.zeros(lam.shape, np.int64)
+    m = np.where(lam > 0, np.ceil(lam / POISSON_CHUNK), 0).astype(np.int64)
+    mu = np.where(m > 0, lam / np.maximum(m, 1), 0.0)
+    for j in range(int(m.max()) if m.size else 0):
+        sel = m > j
+        w = philox4x64(pix[sel], frame, P_PHOTON, j, key[0], key[1])[0]
+        out[sel] += poisson_inversion(mu[sel], uniform(w))
+    return out
+
+
+def gamma_mt(n: np.ndarray, pix: np.ndarray, frame: int, key) -> np.ndarray:
+    """Gamma(n, 1) for shapes n >= 1 (Marsaglia-Tsang); attempt i uses
+    counter block i: words 0, 1 -> normal x, word 2 -> uniform u."""
+    n = np.asarray(n, np.float64)
+    d = n - 1.0 / 3.0
+    c = 1.0 / np.sqrt(9.0 * d)
+    out = d.copy()
+    live = np.ones(n.shape, bool)
+    for i in range(GAMMA_TRIES):
+        if not live.any():
+            break
+        idx = np.flatnonzero(live)
+        w = philox4x64(pix[idx], frame, P_EXCESS, i, key[0], key[1])
+        x = box_muller(w[0], w[1])
+        u = uniform(w[2])
+        v = 1.0 + c[idx] * x
+        ok = v > 0.0
+        v3 = np.where(ok, v * v * v, 1.0)
+        with np.errstate(divide="ignore"):
+            acc = ok & (np.log(u) < 0.5 * x * x + d[idx] - d[idx] * v3 + d[idx] * np.log(v3))
+        out[idx[acc]] = d[idx[acc]] * v3[acc]
+        live[idx[acc]] = False
+    return out
+
+
+# ------------------------------------------------------------- detector ---
+
+def expected_electrons(I: np.ndarray, n_det: int, rebin: int, electrons: float) -> np.ndarray:
+    """lam [n_det][n_det]: electrons * float64 row-major block sums of the
+    float32 intensity I [N][N] over its central rebin * n_det square."""
+    N = I.shape[-1]
+    w = rebin * n_det
+    off = (N - w) // 2
+    win = np.asarray(I[off:off + w, off:off + w], np.float32)
+    s = np.zeros((n_det, n_det), np.float64)
+    for i in range(rebin):
+        for j in range(rebin):
+            s = s + win[i::rebin, j::rebin].astype(np.float64)
+    return s * float(electrons)
+
+
+def detector_frame(I: np.ndarray, n_det: int, rebin: int, electrons: float, flags: int, readout_e: float,
+                   seed: int, frame: int) -> np.ndarray:
+    """Detector pixels [n_det][n_det] (electrons, float64) of one frame of
+    normalised intensity I [N][N] (float32); `frame` is the global frame
+    index that keys the random numbers."""
+    if (flags & EXCESS) and not (flags & PHOTON):
+        raise ValueError("excess noise needs photon noise")
+    key = (int(seed) & ((1 << 64) - 1), 0)
+    lam = expected_electrons(I, n_det, rebin, electrons).ravel()
+    pix = np.arange(n_det * n_det, dtype=np.uint64)
+    if flags & PHOTON:
+        val = poisson(lam, pix, frame, key).astype(np.float64)
+        if flags & EXCESS:
+            pos = val > 0
+            val[pos] = gamma_mt(val[pos], pix[pos], frame, key)
+    else:
+        val = lam.copy()
+    if flags & READOUT:
+        w = philox4x64(pix, frame, P_READOUT, 0, key[0], key[1])
+        val = val + float(readout_e) * box_muller(w[0], w[1])
+    return val.reshape(n_det, n_det)
+
+
+def detector(I: np.ndarray, n_det: int, rebin: int, electrons: float, flags: int, readout_e: float, seed: int,
+             frame0: int = 0) -> np.ndarray:
+    """detector_frame over frames I [F][N][N]; frame f uses index frame0 + f."""
+    return np.stack([detector_frame(I[f], n_det, rebin, electrons, flags, readout_e, seed, frame0 + f)
+                     for f in range(I.shape[0])])
+
+
+# ---------------------------------------------------------- detector slopes --
+
+def detector_geometry(s, n_det: int, rebin: int):
+    """(image origins in detector pixels, image size, detector pixels per
+    subaperture) for sensor s read out on an n_det detector of rebin x rebin
+    FFT pixels; raises if the pupil images do not fall on whole detector
+    pixels."""
+    from . import pwfs as O
+    N, D = s.n_fft, s.n_pupil
+    off2 = N - rebin * n_det
+    if off2 < 0 or off2 % 2 or D % rebin or (D // rebin) % s.n_subap:
+        raise ValueError("detector does not tile the pupil images")
+    off = off2 // 2
+    org = []
+    for r0, c0 in O.image_origins(s):
+        if (r0 - off) % rebin or (c0 - off) % rebin or r0 < off or c0 < off:
+            raise ValueError("pupil image not aligned with detector pixels")
+        org.append(((r0 - off) // rebin, (c0 - off) // rebin))
+    return org, D // rebin, D // rebin // s.n_subap
+
+
+def detector_quadrants(P: np.ndarray, s, n_det: int, rebin: int) -> np.ndarray:
+    """Q [F][4][n][n]: the four pupil images of detector frames P [F][n_det][n_det]
+    summed over b_det x b_det blocks."""
+    org, Dd, b = detector_geometry(s, n_det, rebin)
+    P = np.asarray(P, np.float64)
+    n = s.n_subap
+    Q = np.zeros((P.shape[0], 4, n, n))
+    for q, (r0, c0) in enumerate(org):
+        Q[:, q] = P[:, r0:r0 + Dd, c0:c0 + Dd].reshape(P.shape[0], n, b, n, b).sum(axis=(2, 4))
+    return Q
+
+
+def detector_slopes(P: np.ndarray, s, n_det: int, rebin: int):
+    """(slopes [F][2][n][n], flux [F]) of detector frames: the sensor's slope
+    definition on detector pixels, minus the raw slopes of the noise-free
+    detector frame of a flat wavefront (when reference subtraction is on)."""
+    from . import pwfs as O
+    valid = O.valid_subapertures(s)
+    local = bool(s.flags & O.FLAG_LOCAL_NORM)
+    sl, flux = O.raw_slopes(detector_quadrants(P, s, n_det, rebin), valid, local)
+    if s.flags & O.FLAG_REF_SLOPES:
+        I0 = O.forward(np.zeros((1, s.n_pupil, s.n_pupil)), s).astype(np.float32)
+        P0 = detector(I0, n_det, rebin, 1.0, 0, 0.0, 0)
+        ref = O.raw_slopes(detector_quadrants(P0, s, n_det, rebin), valid, local)[0][0]
+        sl = sl - ref[None]
+        sl[:, :, ~valid] = 0.0
+    return sl, flux
