@@ -24,6 +24,7 @@ if ROOT not in sys.path:
 METRIC = "PWFS frames/s @160px pupil,48 mod pts: plain vs MFMA/surrogate at stated error"
 FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0}   # MI355X dense matrix peaks
+HBM_PEAK_GBS = 8000.0        # MI355X published HBM3E bandwidth
 
 
 def nominal_flops(s) -> dict:
@@ -153,6 +154,48 @@ def surrogate_form(torch, dev, n_train, n_test, epochs, reps):
                          "traffic": None}}
 
 
+def detector_form(P, torch, dev, stream, x, plan, I, s, steps: int):
+    """The plain path followed by the detector (120 x 120, photon + excess +
+    readout noise, magnitude-8 source) and the slopes on detector pixels:
+    frames/s over the 1000-frame batch, and the detector kernel against the
+    HBM roof (it reads the four pupil images and writes the detector frame)."""
+    from workloads.configs import soul_detector
+    F = int(x.shape[0])
+    det = soul_detector(s)
+    flags = P.CCD_PHOTON | P.CCD_EXCESS | P.CCD_READOUT
+    d = P.ccd_desc(det["n_det"], det["rebin"], det["electrons"], flags, det["readout_e"], seed=11)
+    pix = torch.empty((F, det["n_det"], det["n_det"]), dtype=torch.float32, device=dev)
+    sl = torch.empty((F, 2, s.n_subap, s.n_subap), dtype=torch.float32, device=dev)
+    fl = torch.zeros(F, dtype=torch.float32, device=dev)
+
+    def one(k):
+        plan.forward(x, I, stream=stream)
+        plan.ccd(I, d, frame0=k * F, out=pix, stream=stream)
+        plan.ccd_slopes(pix, d, out=sl, flux=fl, stream=stream)
+
+    one(0)
+    torch.cuda.synchronize(dev)
+    plan.profile(4096)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        one(k + 1)
+    torch.cuda.synchronize(dev)
+    dt = (time.perf_counter() - t0) / steps
+    ccd_ms, ccd_n = plan.profile_read("ccd")
+    plan.profile(0)
+    byts = 4.0 * (4 * s.n_pupil ** 2 + det["n_det"] ** 2)        # image pixels read + detector pixels written
+    ach = byts * F * steps / (ccd_ms / 1e3) / 1e9
+    print(f"# detector: {F / dt:.0f} frames/s, k_ccd {ccd_ms / max(1, ccd_n):.3f} ms per launch", file=sys.stderr,
+          flush=True)
+    return {"value": round(F / dt, 1), "unit": "frames/s", "ms_per_step": round(dt * 1e3, 4),
+            "detector": {"n_det": det["n_det"], "rebin": det["rebin"], "electrons_per_frame": round(det["electrons"], 1),
+                         "readout_e": det["readout_e"], "noise": "photon+excess+readout"},
+            "roofline": {"kernel": "k_ccd (rebin, Poisson, Gamma, Gaussian per detector pixel)", "bound": "hbm",
+                         "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_frame": byts,
+                         "avg_launch_ms": round(ccd_ms / max(1, ccd_n), 4), "traffic": None}}
+
+
 def hetero_form(P, torch, dev, stream, steps: int, graph_reps: int = 200):
     """Six sensors (80-240 px pupils, FFT 256-768, 16-96 points, 3 wavelengths)
     in one plan: autotuned execution, timesteps/s over the 500-frame batch, and
@@ -261,9 +304,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-frames", type=int, default=32)
+    ap.add_argument("--cpu-frames", type=int, default=192,
+                    help="frames of the oracle CPU baseline (about 10 s on 16 host processes)")
     ap.add_argument("--no-forms", action="store_true", help="time only the plain FP32 path")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate form")
+    ap.add_argument("--no-detector", action="store_true", help="skip the path with the detector stage")
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous six-sensor batch")
     ap.add_argument("--surrogate-train", type=int, default=200_000)
     ap.add_argument("--surrogate-epochs", type=int, default=20)
@@ -357,6 +402,8 @@ def main() -> int:
                                             ("mfma_bf16", PREC_BF16, 1, "bf16")):
             forms[label] = time_form(P, torch, s.with_(precision=prec), x, w.n_frames, max(2, args.steps // 2),
                                      1, I, S, dev, stream, label, terms, dt_name)
+    if not args.no_detector:
+        forms["detector"] = detector_form(P, torch, dev, stream, x, plan, I, s, max(2, args.steps // 2))
     if not args.no_surrogate:
         forms["surrogate"] = surrogate_form(torch, dev, args.surrogate_train, 20_000, args.surrogate_epochs, 5)
     if not args.no_hetero:

@@ -193,6 +193,62 @@ int pwfs_profile(pwfs_plan_t plan, int max_launches);
 int pwfs_profile_read(pwfs_plan_t plan, int kernel, double* total_ms, int* launches);
 
 /* ------------------------------------------------------------------------
+ * Detector stage: the paper's CCD processing object between the sensor and
+ * the slope computer (Table 4), with the parameters of its SOUL
+ * configuration (Appendix B): detector size, photon / readout / excess
+ * noise switches, readout level; the source flux, integration time,
+ * bandwidth and quantum efficiency enter through `electrons`.
+ *
+ * Per detector pixel p and frame f (global frame index frame0 + f):
+ *   lam = electrons * sum of the rebin x rebin block of the intensity plane
+ *         over its central rebin*n_det square (float64, row-major order);
+ *         without PWFS_F_FULL_PLANE only pixels inside the four pupil images
+ *         count (the rest of the plane is not written by pwfs_forward);
+ *   photon noise: n ~ Poisson(lam) (else the value is lam);
+ *   excess noise: n -> Gamma(n, 1) (electron multiplication at high gain);
+ *   readout noise: + N(0, readout_e^2).
+ * Random numbers: Philox4x64-10 keyed by (seed, 0), counter (p, frame,
+ * purpose, block), so results depend only on (seed, frame index, pixel),
+ * not on how frames are batched.
+ * ------------------------------------------------------------------------ */
+
+enum { PWFS_CCD_PHOTON = 1, PWFS_CCD_READOUT = 2, PWFS_CCD_EXCESS = 4 };
+
+typedef struct {
+  int32_t n_det;      /* detector pixels per side */
+  int32_t rebin;      /* transform pixels per detector pixel, per side */
+  uint32_t flags;     /* PWFS_CCD_* (excess noise needs photon noise) */
+  int32_t reserved;   /* must be 0 */
+  double electrons;   /* expected photo-electrons per frame over the whole normalised plane, >= 0 */
+  double readout_e;   /* readout noise RMS [electrons / pixel / frame], >= 0 */
+  uint64_t seed;      /* key of the random draws */
+} pwfs_ccd_desc;
+
+/*
+ * Detector frames of one sensor: d_intensity as written by pwfs_forward
+ * ([n_frames][intensity_stride], the sensor's plane at its intensity
+ * offset) -> d_pixels [n_frames][n_det][n_det] float32 electrons.
+ * Requires rebin * n_det <= N with N - rebin * n_det even; without
+ * PWFS_F_FULL_PLANE also that the pupil images fall on whole detector
+ * pixels.  PWFS_EINVAL for a bad description, PWFS_ESTATE for n_frames
+ * outside [1, max_frames].  Asynchronous on hip_stream.
+ */
+int pwfs_ccd(pwfs_plan_t plan, int sensor, const pwfs_ccd_desc* ccd, const float* d_intensity, int n_frames,
+             long long frame0, float* d_pixels, void* hip_stream);
+
+/*
+ * Slope stage on detector frames: the sensor's slope definition applied to
+ * the four pupil images on the detector (D / rebin pixels each, binned
+ * D / (rebin * n_subap) per subaperture), minus the sensor's reference
+ * slopes when PWFS_F_REF_SLOPES is set.  d_slopes [n_frames][2][n][n],
+ * d_flux [n_frames] or NULL.  Requires the pupil images to fall on whole
+ * detector pixels tiled by the subapertures (PWFS_EINVAL otherwise).
+ * Asynchronous on hip_stream.
+ */
+int pwfs_ccd_slopes(pwfs_plan_t plan, int sensor, const pwfs_ccd_desc* ccd, const float* d_pixels, int n_frames,
+                    float* d_slopes, float* d_flux, void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Matrix-core products.  The learned-surrogate form and its data pipeline
  * (modal coefficients -> OPD, the linear interaction-matrix baseline) need
  * dense products; they run on the same split-precision MFMA tiles as the

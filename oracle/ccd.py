@@ -45,6 +45,7 @@ EXCESS = 4
 P_PHOTON, P_EXCESS, P_READOUT = 0, 1, 2
 
 POISSON_CHUNK = 256.0      # largest mean drawn by one inversion
+MAX_LAM = 2.0 ** 24        # larger or non-finite expected counts give NaN (bounds the O(lam) draw)
 POISSON_KCAP = 1024        # inversion stops here (unreachable at mean <= 256 in practice)
 GAMMA_TRIES = 64           # Marsaglia-Tsang attempts before giving up (returns d)
 
@@ -142,17 +143,22 @@ def poisson_inversion(mu: np.ndarray, u: np.ndarray) -> np.ndarray:
 
 
 def poisson(lam: np.ndarray, pix: np.ndarray, frame: int, key) -> np.ndarray:
-    """Poisson(lam) per pixel: lam split into m = ceil(lam / 256) equal parts,
-    one inversion each (part j uses counter block j), summed."""
+    """Poisson(lam) per pixel (float64): lam split into m = ceil(lam / 256)
+    equal parts, one inversion each (part j uses counter block j), summed;
+    lam <= 0 gives 0, lam > 2^24 or non-finite gives NaN."""
     lam = np.asarray(lam, np.float64)
+    bad = ~(lam <= MAX_LAM)
+    ok = np.where(bad, 0.0, lam)
     out = np.zeros(lam.shape, np.int64)
-    m = np.where(lam > 0, np.ceil(lam / POISSON_CHUNK), 0).astype(np.int64)
-    mu = np.where(m > 0, lam / np.maximum(m, 1), 0.0)
+    m = np.where(ok > 0, np.ceil(ok / POISSON_CHUNK), 0).astype(np.int64)
+    mu = np.where(m > 0, ok / np.maximum(m, 1), 0.0)
     for j in range(int(m.max()) if m.size else 0):
         sel = m > j
         w = philox4x64(pix[sel], frame, P_PHOTON, j, key[0], key[1])[0]
         out[sel] += poisson_inversion(mu[sel], uniform(w))
-    return out
+    res = out.astype(np.float64)
+    res[bad] = np.nan
+    return res
 
 
 def gamma_mt(n: np.ndarray, pix: np.ndarray, frame: int, key) -> np.ndarray:
@@ -207,7 +213,7 @@ def detector_frame(I: np.ndarray, n_det: int, rebin: int, electrons: float, flag
     lam = expected_electrons(I, n_det, rebin, electrons).ravel()
     pix = np.arange(n_det * n_det, dtype=np.uint64)
     if flags & PHOTON:
-        val = poisson(lam, pix, frame, key).astype(np.float64)
+        val = poisson(lam, pix, frame, key)
         if flags & EXCESS:
             pos = val > 0
             val[pos] = gamma_mt(val[pos], pix[pos], frame, key)

@@ -1,0 +1,293 @@
+// pwfs_ccd.hip -- detector stage after the pyramid sensor (the paper's CCD
+// processing object, Table 4; its parameters in the SOUL configuration of
+// Appendix B): integer rebinning of the normalised intensity onto detector
+// pixels, photon noise (Poisson), electron-multiplication excess noise
+// (Gamma(n, 1) at high gain) and readout noise (Gaussian), and the slope
+// stage on detector pixels.
+//
+// One thread per detector pixel and frame.  Random numbers are Philox4x64-10
+// (Salmon, Moraes, Dror, Shaw, SC'11) keyed by (seed, 0) with counter
+// (pixel, frame, purpose, block): every draw is a pure function of where it
+// is used, so results do not depend on the launch shape or the chunking of
+// frames.  The Poisson integer is decided in float64 by CDF inversion built
+// from correctly rounded + - * / only (exp(-mu) by a fixed Taylor series and
+// repeated squaring; contraction off), so it is reproducible bit for bit by
+// any implementation doing the same operations in the same order.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "pwfs.h"
+#include "pwfs_internal.hpp"
+
+namespace pwfs {
+namespace {
+
+constexpr double kPoissonChunk = 256.0;  // largest mean of one inversion
+constexpr int kPoissonKcap = 1024;       // inversion stops here
+constexpr int kGammaTries = 64;          // Marsaglia-Tsang attempts
+constexpr double kMaxLam = 16777216.0;   // 2^24: larger (or non-finite) expected counts give NaN
+constexpr uint64_t kPhotonPurpose = 0, kExcessPurpose = 1, kReadoutPurpose = 2;
+
+struct u64x4 {
+  uint64_t w[4];
+};
+
+// Philox4x64-10: ten rounds of two 64x64->128 multiplies, Weyl key schedule
+__device__ __forceinline__ u64x4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                        uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t h0 = __umul64hi(M0, c0), l0 = M0 * c0;
+    const uint64_t h1 = __umul64hi(M1, c2), l1 = M1 * c2;
+    const uint64_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = l1;
+    c2 = n2;
+    c3 = l0;
+  }
+  return {{c0, c1, c2, c3}};
+}
+
+__device__ __forceinline__ double uniform01(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
+
+__device__ double box_muller(uint64_t w0, uint64_t w1) {
+  const double u1 = 1.0 - uniform01(w0);   // (0, 1]
+  const double u2 = uniform01(w1);
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2);
+}
+
+// exp(-mu), 0 <= mu <= 256: 24-term Taylor series at mu / 256, eight squarings
+__device__ double exp_neg(double mu) {
+#pragma clang fp contract(off)
+  const double x = mu / 256.0;
+  double e = 1.0;
+  for (int i = 24; i >= 1; --i) {
+    double t = e * x;
+    t = t / (double)i;
+    e = 1.0 - t;
+  }
+  for (int i = 0; i < 8; ++i) e = e * e;
+  return e;
+}
+
+// smallest k with u <= F(k), p_k = p_{k-1} mu / k, stopping at kPoissonKcap
+__device__ int poisson_inversion(double mu, double u) {
+#pragma clang fp contract(off)
+  double p = exp_neg(mu);
+  double F = p;
+  int k = 0;
+  while (u > F && k < kPoissonKcap) {
+    ++k;
+    double q = p * mu;
+    q = q / (double)k;
+    F = F + q;
+    p = q;
+  }
+  return k;
+}
+
+__device__ long long poisson(double lam, uint64_t pix, uint64_t frame, uint64_t k0, uint64_t k1) {
+#pragma clang fp contract(off)
+  if (!(lam > 0.0)) return 0;
+  const long long m = (long long)ceil(lam / kPoissonChunk);
+  const double mu = lam / (double)m;
+  long long n = 0;
+  for (long long j = 0; j < m; ++j) {
+    const u64x4 w = philox(pix, frame, kPhotonPurpose, (uint64_t)j, k0, k1);
+    n += poisson_inversion(mu, uniform01(w.w[0]));
+  }
+  return n;
+}
+
+// Gamma(n, 1), n >= 1 (Marsaglia-Tsang); attempt i uses counter block i
+__device__ double gamma_mt(double n, uint64_t pix, uint64_t frame, uint64_t k0, uint64_t k1) {
+#pragma clang fp contract(off)
+  const double d = n - 1.0 / 3.0;
+  const double c = 1.0 / sqrt(9.0 * d);
+  for (int i = 0; i < kGammaTries; ++i) {
+    const u64x4 w = philox(pix, frame, kExcessPurpose, (uint64_t)i, k0, k1);
+    const double x = box_muller(w.w[0], w.w[1]);
+    const double u = uniform01(w.w[2]);
+    double v = 1.0 + c * x;
+    if (!(v > 0.0)) continue;
+    v = v * v * v;
+    const double lhs = log(u);
+    double rhs = 0.5 * x * x;
+    rhs = rhs + d;
+    rhs = rhs - d * v;
+    rhs = rhs + d * log(v);
+    if (lhs < rhs) return d * v;
+  }
+  return d;
+}
+
+struct CcdArgs {
+  const float* in;          // sensor's intensity plane of the first frame
+  long long in_stride;      // floats between frames
+  float* out;               // [frames][n_det][n_det]
+  int N, n_det, rebin, off; // plane size, detector size, pixels per detector pixel, window offset
+  int windows;              // count only detector pixels inside the four pupil images
+  int img_r[2], img_c[2];   // image starts in detector pixels (two rows x two columns)
+  int img;                  // image size in detector pixels
+  uint32_t flags;
+  double electrons, readout_e;
+  uint64_t k0, k1;
+  long long frame0;
+};
+
+__global__ __launch_bounds__(256) void k_ccd(CcdArgs p) {
+#pragma clang fp contract(off)
+  const int nn = p.n_det * p.n_det;
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  if (pix >= nn) return;
+  const int f = blockIdx.y;
+  const int r = pix / p.n_det, c = pix % p.n_det;
+  bool inside = true;
+  if (p.windows) {
+    const bool rin = (r >= p.img_r[0] && r < p.img_r[0] + p.img) || (r >= p.img_r[1] && r < p.img_r[1] + p.img);
+    const bool cin = (c >= p.img_c[0] && c < p.img_c[0] + p.img) || (c >= p.img_c[1] && c < p.img_c[1] + p.img);
+    inside = rin && cin;
+  }
+  double s = 0.0;
+  if (inside) {
+    const float* I = p.in + (long long)f * p.in_stride + (long long)(p.off + r * p.rebin) * p.N + p.off + c * p.rebin;
+    for (int i = 0; i < p.rebin; ++i)
+      for (int j = 0; j < p.rebin; ++j) s = s + (double)I[(long long)i * p.N + j];
+  }
+  const double lam = s * p.electrons;
+  const uint64_t frame = (uint64_t)(p.frame0 + f);
+  double v;
+  if (p.flags & PWFS_CCD_PHOTON) {
+    if (!(lam <= kMaxLam)) {   // bounds the O(lam) inversion; also catches NaN / inf inputs
+      v = __builtin_nan("");
+    } else {
+      const long long n = poisson(lam, (uint64_t)pix, frame, p.k0, p.k1);
+      v = (double)n;
+      if ((p.flags & PWFS_CCD_EXCESS) && n > 0) v = gamma_mt(v, (uint64_t)pix, frame, p.k0, p.k1);
+    }
+  } else {
+    v = lam;
+  }
+  if (p.flags & PWFS_CCD_READOUT) {
+    const u64x4 w = philox((uint64_t)pix, frame, kReadoutPurpose, 0, p.k0, p.k1);
+    v = v + p.readout_e * box_muller(w.w[0], w.w[1]);
+  }
+  p.out[(long long)f * nn + pix] = (float)v;
+}
+
+int cfail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  set_last_error(buf);
+  return code;
+}
+
+// detector geometry of sensor sp; `aligned` also requires the pupil images
+// to fall on whole detector pixels and to be tiled by the subapertures
+struct DetGeom {
+  int off, img, b, img_r[2], img_c[2];
+};
+
+int det_geometry(const SensorPlan& sp, const pwfs_ccd_desc* d, bool aligned, DetGeom& out) {
+  const Geometry& g = sp.g;
+  if (d->n_det < 1 || d->rebin < 1 || d->reserved != 0) return cfail(PWFS_EINVAL, "bad detector size or rebin");
+  if (d->flags & ~(uint32_t)(PWFS_CCD_PHOTON | PWFS_CCD_READOUT | PWFS_CCD_EXCESS))
+    return cfail(PWFS_EINVAL, "unknown detector flags");
+  if ((d->flags & PWFS_CCD_EXCESS) && !(d->flags & PWFS_CCD_PHOTON))
+    return cfail(PWFS_EINVAL, "excess noise needs photon noise");
+  if (!(d->electrons >= 0.0) || !(d->readout_e >= 0.0) || !std::isfinite(d->electrons))
+    return cfail(PWFS_EINVAL, "electrons and readout noise must be finite and >= 0");
+  const long long w = (long long)d->rebin * d->n_det;
+  if (w > g.N || (g.N - w) % 2) return cfail(PWFS_EINVAL, "rebin * n_det must be <= N with N - rebin * n_det even");
+  out.off = (int)((g.N - w) / 2);
+  if (!aligned && g.full) return PWFS_OK;
+  if (g.D % d->rebin || (g.D / d->rebin) % g.n)
+    return cfail(PWFS_EINVAL, "the pupil images must be whole detector pixels tiled by the subapertures");
+  out.img = g.D / d->rebin;
+  out.b = out.img / g.n;
+  for (int q = 0; q < 2; ++q) {
+    const int sgn = q ? 1 : -1;
+    const int o = g.N / 2 + sgn * g.S / 2 - g.D / 2 - out.off;
+    if (o < 0 || o % d->rebin || o / d->rebin + out.img > d->n_det)
+      return cfail(PWFS_EINVAL, "pupil image not aligned with the detector pixels");
+    out.img_r[q] = out.img_c[q] = o / d->rebin;
+  }
+  return PWFS_OK;
+}
+
+}  // namespace
+}  // namespace pwfs
+
+using namespace pwfs;
+
+extern "C" int pwfs_ccd(pwfs_plan_t p, int sensor, const pwfs_ccd_desc* d, const float* in, int nf, long long frame0,
+                        float* out, void* stream) {
+  if (!p || !d) return cfail(PWFS_EINVAL, "NULL argument");
+  if (!in || !out) return cfail(PWFS_EINVAL, "NULL device pointer");
+  if (sensor < 0 || sensor >= (int)p->s.size()) return cfail(PWFS_EINVAL, "sensor index out of range");
+  if (nf < 1 || nf > p->max_frames) return cfail(PWFS_ESTATE, "n_frames %d outside [1, max_frames]", nf);
+  if (frame0 < 0) return cfail(PWFS_EINVAL, "frame0 must be >= 0");
+  const SensorPlan& sp = p->s[sensor];
+  DetGeom dg{};
+  int rc = det_geometry(sp, d, false, dg);
+  if (rc) return rc;
+  CcdArgs a{};
+  a.in = in + sp.int_offset;
+  a.in_stride = (long long)p->int_stride;
+  a.out = out;
+  a.N = sp.g.N;
+  a.n_det = d->n_det;
+  a.rebin = d->rebin;
+  a.off = dg.off;
+  a.windows = sp.g.full ? 0 : 1;
+  for (int q = 0; q < 2; ++q) {
+    a.img_r[q] = dg.img_r[q];
+    a.img_c[q] = dg.img_c[q];
+  }
+  a.img = dg.img;
+  a.flags = d->flags;
+  a.electrons = d->electrons;
+  a.readout_e = d->readout_e;
+  a.k0 = d->seed;
+  a.k1 = 0;
+  a.frame0 = frame0;
+  const int nn = d->n_det * d->n_det;
+  hipStream_t st = (hipStream_t)stream;
+  const int slot = p->prof.begin(st);
+  hipLaunchKernelGGL(k_ccd, dim3((unsigned)((nn + 255) / 256), (unsigned)nf), dim3(256), 0, st, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return cfail(PWFS_EHIP, "launch k_ccd: %s", hipGetErrorString(e));
+  p->prof.end(slot, st, K_CCD);
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_ccd_slopes(pwfs_plan_t p, int sensor, const pwfs_ccd_desc* d, const float* pixels, int nf,
+                               float* slopes, float* flux, void* stream) {
+  if (!p || !d) return cfail(PWFS_EINVAL, "NULL argument");
+  if (!pixels || !slopes) return cfail(PWFS_EINVAL, "NULL device pointer");
+  if (sensor < 0 || sensor >= (int)p->s.size()) return cfail(PWFS_EINVAL, "sensor index out of range");
+  if (nf < 1 || nf > p->max_frames) return cfail(PWFS_ESTATE, "n_frames %d outside [1, max_frames]", nf);
+  const SensorPlan& sp = p->s[sensor];
+  DetGeom dg{};
+  int rc = det_geometry(sp, d, true, dg);
+  if (rc) return rc;
+  const int org_r[4] = {dg.img_r[0], dg.img_r[0], dg.img_r[1], dg.img_r[1]};
+  const int org_c[4] = {dg.img_c[0], dg.img_c[1], dg.img_c[0], dg.img_c[1]};
+  const float* ref = (sp.desc.flags & PWFS_F_REF_SLOPES) ? (const float*)sp.dev[R_REF] : nullptr;
+  const int nn = d->n_det * d->n_det;
+  return slopes_launch_at(sp, pixels, nn, slopes, 2LL * sp.g.n * sp.g.n, flux, 1, ref, nf, d->n_det, dg.b, org_r,
+                          org_c, (hipStream_t)stream, &p->prof);
+}

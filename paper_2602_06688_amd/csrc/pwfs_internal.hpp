@@ -62,7 +62,7 @@ int forward_mfma(const SensorPlan& sp, const float* opd, long long opd_stride, f
 
 // Optional per-kernel timing: HIP events recorded on the launch stream
 // around each kernel (pool created when profiling is switched on).
-enum KernelId { K_ROWS = 0, K_COLS = 1, K_SLOPES = 2, K_MFMA = 3, K_FIELD = 4, K_HETERO = 5, kKernelIds = 8 };
+enum KernelId { K_ROWS = 0, K_COLS = 1, K_SLOPES = 2, K_MFMA = 3, K_FIELD = 4, K_HETERO = 5, K_CCD = 6, kKernelIds = 8 };
 
 struct Prof {
   bool on = false;
@@ -96,6 +96,12 @@ struct pwfs_plan_s {
 };
 
 namespace pwfs {
+// slope stage on an n_in x n_in input whose four pupil images start at
+// (org_r[q], org_c[q]) and are binned b x b (the intensity plane, or the
+// detector pixels of the detector stage)
+int slopes_launch_at(const SensorPlan& sp, const float* in, long long in_stride, float* slopes,
+                     long long slope_stride, float* flux, long long flux_stride, const float* ref, int nf, int n_in,
+                     int b, const int* org_r, const int* org_c, hipStream_t st, Prof* prof);
 int forward_sensor(pwfs_plan_s* p, int i, const float* opd, long long opd_stride, float* out, long long out_stride,
                    int nf, hipStream_t st);
 }

@@ -572,8 +572,9 @@ int prepare_kernels() {
 // below this many frames the slope stage runs 1024 threads per frame
 constexpr int kSlopesWideBelow = 64;
 
-int slopes_launch(const SensorPlan& sp, const float* in, long long in_stride, float* slopes, long long slope_stride,
-                  float* flux, long long flux_stride, const float* ref, int nf, hipStream_t st, Prof* prof) {
+int slopes_launch_at(const SensorPlan& sp, const float* in, long long in_stride, float* slopes,
+                     long long slope_stride, float* flux, long long flux_stride, const float* ref, int nf, int n_in,
+                     int b, const int* org_r, const int* org_c, hipStream_t st, Prof* prof) {
   const Geometry& g = sp.g;
   SlopeArgs a{};
   a.in = in;
@@ -584,17 +585,15 @@ int slopes_launch(const SensorPlan& sp, const float* in, long long in_stride, fl
   a.in_stride = in_stride;
   a.slope_stride = slope_stride;
   a.flux_stride = flux_stride;
-  a.N = g.N;
+  a.N = n_in;
   a.n = g.n;
-  a.b = g.b;
+  a.b = b;
   a.n_valid = sp.n_valid;
   a.local_norm = (sp.desc.flags & PWFS_F_LOCAL_NORM) ? 1 : 0;
-  int q = 0;
-  for (int sy = -1; sy <= 1; sy += 2)
-    for (int sx = -1; sx <= 1; sx += 2, ++q) {
-      a.org_r[q] = g.N / 2 + sy * g.S / 2 - g.D / 2;
-      a.org_c[q] = g.N / 2 + sx * g.S / 2 - g.D / 2;
-    }
+  for (int q = 0; q < 4; ++q) {
+    a.org_r[q] = org_r[q];
+    a.org_c[q] = org_c[q];
+  }
   const size_t lds = sizeof(float) * 4 * g.n * g.n;
   const int slot = prof ? prof->begin(st) : -1;
   if (nf >= kSlopesWideBelow)
@@ -604,6 +603,20 @@ int slopes_launch(const SensorPlan& sp, const float* in, long long in_stride, fl
   HIP_TRY(hipGetLastError(), "launch k_slopes");
   if (prof) prof->end(slot, st, K_SLOPES);
   return PWFS_OK;
+}
+
+int slopes_launch(const SensorPlan& sp, const float* in, long long in_stride, float* slopes, long long slope_stride,
+                  float* flux, long long flux_stride, const float* ref, int nf, hipStream_t st, Prof* prof) {
+  const Geometry& g = sp.g;
+  int org_r[4], org_c[4];
+  int q = 0;
+  for (int sy = -1; sy <= 1; sy += 2)
+    for (int sx = -1; sx <= 1; sx += 2, ++q) {
+      org_r[q] = g.N / 2 + sy * g.S / 2 - g.D / 2;
+      org_c[q] = g.N / 2 + sx * g.S / 2 - g.D / 2;
+    }
+  return slopes_launch_at(sp, in, in_stride, slopes, slope_stride, flux, flux_stride, ref, nf, g.N, g.b, org_r, org_c,
+                          st, prof);
 }
 
 }  // namespace pwfs

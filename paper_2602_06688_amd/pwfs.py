@@ -68,6 +68,23 @@ class CTuning(ctypes.Structure):
 MODE_LAUNCHES = 0
 MODE_PERSISTENT = 1
 
+CCD_PHOTON = 1
+CCD_READOUT = 2
+CCD_EXCESS = 4
+
+
+class CCcdDesc(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int32), ("rebin", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32), ("electrons", ctypes.c_double), ("readout_e", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+def ccd_desc(n_det: int, rebin: int, electrons: float, flags: int = CCD_PHOTON, readout_e: float = 0.0,
+             seed: int = 0) -> CCcdDesc:
+    """A detector description (see pwfs_ccd_desc in include/pwfs.h)."""
+    return CCcdDesc(int(n_det), int(rebin), int(flags), 0, float(electrons), float(readout_e),
+                    int(seed) & ((1 << 64) - 1))
+
 _lib = None
 
 
@@ -103,6 +120,8 @@ def lib() -> ctypes.CDLL:
     L.pwfs_profile_read.argtypes = [vp, i32, P(ctypes.c_double), P(ctypes.c_int)]
     L.pwfs_destroy.argtypes = [vp]
     L.pwfs_destroy.restype = None
+    L.pwfs_ccd.argtypes = [vp, i32, P(CCcdDesc), vp, i32, ctypes.c_longlong, vp, vp]
+    L.pwfs_ccd_slopes.argtypes = [vp, i32, P(CCcdDesc), vp, i32, vp, vp, vp]
     L.pwfs_get_tuning.argtypes = [vp, P(CTuning)]
     L.pwfs_set_tuning.argtypes = [vp, P(CTuning)]
     ll = ctypes.c_longlong
@@ -124,7 +143,7 @@ def lib() -> ctypes.CDLL:
                  "pwfs_query", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
                  "pwfs_gemm_workspace_size", "pwfs_gemm", "pwfs_row_rms", "pwfs_mlp_workspace_size",
                  "pwfs_mlp_create", "pwfs_mlp_param_count", "pwfs_mlp_set_params", "pwfs_mlp_get_params",
-                 "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam"):
+                 "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam", "pwfs_ccd", "pwfs_ccd_slopes"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -284,7 +303,36 @@ class Plan:
         s, fl = self.slopes(I, slopes, flux, stream)
         return I, s, fl
 
-    KERNELS = {"rows": 0, "cols": 1, "slopes": 2, "mfma": 3, "field": 4, "hetero": 5}
+    def ccd(self, intensity, ccd: CCcdDesc, frame0: int = 0, out=None, sensor: int = 0, stream=None):
+        """Detector frames [F, n_det, n_det] (electrons) of one sensor's
+        intensity, as written by ``forward``; frame f draws its noise as
+        global frame frame0 + f."""
+        import torch
+        F = int(intensity.shape[0])
+        n = int(ccd.n_det)
+        if out is None:
+            out = torch.empty((F, n, n), dtype=torch.float32, device=self.device)
+        pi = _dev_ptr(intensity, "intensity", torch.float32, F * self.intensity_stride)
+        po = _dev_ptr(out, "pixels", torch.float32, F * n * n)
+        check(lib().pwfs_ccd(self._h, int(sensor), ctypes.byref(ccd), pi, F, int(frame0), po, _stream_ptr(stream)))
+        return out
+
+    def ccd_slopes(self, pixels, ccd: CCcdDesc, out=None, flux=None, sensor: int = 0, stream=None):
+        """Slopes [F, 2, n, n] and flux [F] of detector frames."""
+        import torch
+        F = int(pixels.shape[0])
+        n = int(self.info[sensor].n_subap)
+        if out is None:
+            out = torch.empty((F, 2, n, n), dtype=torch.float32, device=self.device)
+        if flux is None:
+            flux = torch.zeros(F, dtype=torch.float32, device=self.device)
+        pp = _dev_ptr(pixels, "pixels", torch.float32, F * int(ccd.n_det) ** 2)
+        ps = _dev_ptr(out, "slopes", torch.float32, F * 2 * n * n)
+        pf = _dev_ptr(flux, "flux", torch.float32, F)
+        check(lib().pwfs_ccd_slopes(self._h, int(sensor), ctypes.byref(ccd), pp, F, ps, pf, _stream_ptr(stream)))
+        return out, flux
+
+    KERNELS = {"rows": 0, "cols": 1, "slopes": 2, "mfma": 3, "field": 4, "hetero": 5, "ccd": 6}
 
     def get_tuning(self) -> dict:
         t = CTuning()

@@ -3,6 +3,7 @@ its host-only entry points (validation, workspace sizing) behave.  No compute
 call is made here: these run without a GPU."""
 
 import ctypes
+import os
 
 import pytest
 
@@ -83,3 +84,32 @@ def test_workspace_grows_with_frames_and_flags():
     b = P.workspace_size([s], 100)
     c = P.workspace_size([s.with_(flags=P.F_REF_SLOPES | P.F_FULL_PLANE)], 100)
     assert a < b <= c
+
+
+def test_ctypes_structs_match_header_layout(tmp_path):
+    """sizeof / offsetof of every C struct of include/pwfs.h (compiled with the
+    host C compiler) against the binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"pwfs_sensor_desc": P.CSensorDesc, "pwfs_sensor_info": P.CSensorInfo, "pwfs_tuning": P.CTuning,
+               "pwfs_ccd_desc": P.CCcdDesc}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pwfs.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)

@@ -1,0 +1,164 @@
+"""Detector stage on the GPU (pwfs_ccd, pwfs_ccd_slopes) against the oracle
+(oracle/ccd.py) on the same float32 intensity planes, which the oracle's
+sensor model produces: photon counts bit for bit, values with Gaussian or
+Gamma draws to float tolerance, slopes on detector pixels; batching
+invariance in the benchmark's launch configuration; the noise-free detector
+reproduces the intensity slopes; argument errors."""
+
+import numpy as np
+import pytest
+
+from oracle import ccd as C
+from oracle import pwfs as O
+from workloads import FLAG_FULL_PLANE, FLAG_REF_SLOPES, tiny_sensor, workload, workload_opd
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    from paper_2602_06688_amd import pwfs as P
+    return P
+
+
+def _small(full=True):
+    return tiny_sensor(n_pupil=32, n_fft=64, n_subap=8, n_mod=8, pupil_sep_px=32.0, mod_radius_lod=2.0,
+                       obstruction=0.2, flags=FLAG_REF_SLOPES | (FLAG_FULL_PLANE if full else 0))
+
+
+def _window_mask(s):
+    m = np.zeros((s.n_fft, s.n_fft), bool)
+    D = s.n_pupil
+    for r0, c0 in O.image_origins(s):
+        m[r0:r0 + D, c0:c0 + D] = True
+    return m
+
+
+FLAGS = [("none", 0), ("photon", 1), ("readout", 2), ("photon+readout", 3), ("photon+excess+readout", 7)]
+
+
+@pytest.mark.parametrize("electrons", [60.0, 7.0e4, 2.0e6])
+@pytest.mark.parametrize("label,flags", FLAGS)
+def test_detector_matches_oracle_small(label, flags, electrons):
+    P = _P()
+    s = _small()
+    rng = np.random.default_rng(21)
+    I = O.forward(rng.normal(0.0, 80.0, (3, 32, 32)), s).astype(np.float32)
+    plan = P.Plan([s], max_frames=3)
+    d = P.ccd_desc(16, 4, electrons, flags, readout_e=0.7, seed=1234)
+    print(f"[gpu] ccd small {label} electrons={electrons:g}", flush=True)
+    got = plan.ccd(torch.from_numpy(I).cuda(), d, frame0=5).cpu().numpy()
+    want = C.detector(I, 16, 4, electrons, flags, 0.7, 1234, frame0=5).astype(np.float32)
+    if flags & 2 or flags & 4:
+        np.testing.assert_allclose(got, want, rtol=1e-6, atol=1e-5)
+    else:
+        np.testing.assert_array_equal(got, want)      # integers (photon) or float64 expectations cast once
+
+
+def test_window_mode_counts_only_the_pupil_images():
+    P = _P()
+    s = _small(full=False)
+    rng = np.random.default_rng(22)
+    I = O.forward(rng.normal(0.0, 80.0, (2, 32, 32)), s).astype(np.float32)   # full plane, light everywhere
+    plan = P.Plan([s], max_frames=2)
+    d = P.ccd_desc(16, 4, 5e4, P.CCD_PHOTON, seed=3)
+    print("[gpu] ccd window mode", flush=True)
+    got = plan.ccd(torch.from_numpy(I).cuda(), d).cpu().numpy()
+    want = C.detector(I * _window_mask(s)[None], 16, 4, 5e4, C.PHOTON, 0.0, 3).astype(np.float32)
+    np.testing.assert_array_equal(got, want)
+
+
+def _cfg2():
+    w = workload("cfg2")
+    return w, w.sensors[0]
+
+
+def test_full_size_sampled_frames_and_detector_slopes():
+    """160 px / N=512 sensor, 120 px detector (rebin 4): two sampled frames
+    of the 1000-frame workload through the oracle's sensor model, then the
+    GPU's and the oracle's detector and detector slopes."""
+    P = _P()
+    w, s = _cfg2()
+    idx = [0, 999]
+    opd = workload_opd(w, frames=idx)
+    I = O.forward(opd, s).astype(np.float32)
+    Iw = I * _window_mask(s)[None]
+    plan = P.Plan([s], max_frames=1000)
+    d = P.ccd_desc(120, 4, 9.0e4, P.CCD_PHOTON | P.CCD_EXCESS | P.CCD_READOUT, readout_e=0.4, seed=77)
+    for j, f in enumerate(idx):
+        print(f"[gpu] ccd full size frame {f}", flush=True)
+        got = plan.ccd(torch.from_numpy(I[j:j + 1]).cuda(), d, frame0=f)
+        want = C.detector(Iw[j:j + 1], 120, 4, 9.0e4, 7, 0.4, 77, frame0=f)
+        np.testing.assert_allclose(got.cpu().numpy(), want.astype(np.float32), rtol=1e-6, atol=1e-5)
+        sl, fl = plan.ccd_slopes(got, d)
+        ws, wf = C.detector_slopes(want, s, 120, 4)
+        valid = O.valid_subapertures(s)
+        assert O.slope_rel_rms(sl.cpu().numpy(), ws, valid) < 1e-5
+        assert abs(fl.item() / wf[0] - 1.0) < 1e-6
+
+
+def test_full_batch_launch_equals_single_frames_and_noise_free_slopes():
+    """The benchmark's launch (1000 frames in one call after the GPU forward
+    model) gives each frame exactly what a one-frame launch keyed by its
+    index gives; with no noise the detector slopes equal the intensity
+    slopes."""
+    P = _P()
+    w, s = _cfg2()
+    x = torch.from_numpy(workload_opd(w)).cuda()
+    plan = P.Plan([s], max_frames=w.n_frames)
+    I = plan.forward(x)
+    d = P.ccd_desc(120, 4, 9.0e4, P.CCD_PHOTON | P.CCD_EXCESS | P.CCD_READOUT, readout_e=0.4, seed=5)
+    print("[gpu] ccd full batch", flush=True)
+    full = plan.ccd(I, d)
+    for f in (0, 517, 999):
+        one = plan.ccd(I[f:f + 1].contiguous(), d, frame0=f)
+        assert torch.equal(full[f:f + 1], one)
+    assert torch.isfinite(full).all()
+    d0 = P.ccd_desc(120, 4, 9.0e4, 0, seed=5)
+    P0 = plan.ccd(I[:16].contiguous(), d0)
+    s_det, f_det = plan.ccd_slopes(P0, d0)
+    s_int, f_int = plan.slopes(I[:16].contiguous())
+    valid = torch.from_numpy(plan.valid_map(0)).cuda()
+    a = s_det.reshape(16, 2, -1)[:, :, valid.reshape(-1)]
+    b = s_int.reshape(16, 2, -1)[:, :, valid.reshape(-1)]
+    assert float((a - b).norm() / b.norm()) < 1e-5
+    assert torch.allclose(f_det / 9.0e4, f_int[:, 0], rtol=1e-5)
+
+
+def test_huge_or_nonfinite_expectation_gives_nan():
+    P = _P()
+    s = _small()
+    I = np.zeros((1, 64, 64), np.float32)
+    I[0, 10, 10] = 1.0
+    I[0, 30, 30] = np.inf
+    plan = P.Plan([s], max_frames=1)
+    d = P.ccd_desc(16, 4, 2.0 ** 25, P.CCD_PHOTON, seed=1)
+    print("[gpu] ccd bounds", flush=True)
+    got = plan.ccd(torch.from_numpy(I).cuda(), d).cpu().numpy()[0]
+    want = C.detector(I, 16, 4, 2.0 ** 25, C.PHOTON, 0.0, 1)[0]
+    assert np.isnan(got[2, 2]) and np.isnan(got[7, 7]) and np.isnan(want[2, 2]) and np.isnan(want[7, 7])
+    ok = ~np.isnan(want)
+    np.testing.assert_array_equal(got[ok], want[ok].astype(np.float32))
+
+
+def test_errors():
+    P = _P()
+    w, s = _cfg2()
+    plan = P.Plan([s], max_frames=2)
+    I = torch.zeros((2, 512, 512), device="cuda")
+    with pytest.raises(P.PwfsError) as e:
+        plan.ccd(I, P.ccd_desc(120, 4, 1e4, P.CCD_EXCESS))
+    assert e.value.code == P.PWFS_EINVAL
+    with pytest.raises(P.PwfsError) as e:
+        plan.ccd(I, P.ccd_desc(119, 4, 1e4, P.CCD_PHOTON))          # images not on whole detector pixels
+    assert e.value.code == P.PWFS_EINVAL
+    with pytest.raises(P.PwfsError) as e:
+        plan.ccd(I, P.ccd_desc(130, 4, 1e4, P.CCD_PHOTON))          # larger than the plane
+    assert e.value.code == P.PWFS_EINVAL
+    bad = P.ccd_desc(120, 4, 1e4, P.CCD_PHOTON)
+    bad.reserved = 1
+    with pytest.raises(P.PwfsError):
+        plan.ccd(I, bad)
+    with pytest.raises(P.PwfsError) as e:
+        plan.ccd(torch.zeros((3, 512, 512), device="cuda"), P.ccd_desc(120, 4, 1e4, P.CCD_PHOTON))
+    assert e.value.code == P.PWFS_ESTATE

@@ -135,3 +135,9 @@ def test_noise_free_detector_slopes_equal_sensor_slopes():
     assert O.slope_rel_rms(got, want, valid) < 1e-6
     with pytest.raises(ValueError):
         C.detector_geometry(s, 15, 4)
+
+
+def test_poisson_bounds():
+    pix = np.arange(4, dtype=np.uint64)
+    k = C.poisson(np.array([-1.0, 0.0, np.inf, 2.0 ** 24 + 1]), pix, 0, (1, 0))
+    assert k[0] == 0 and k[1] == 0 and np.isnan(k[2]) and np.isnan(k[3])

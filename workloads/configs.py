@@ -11,6 +11,8 @@ axis) are listed in the design doc.
 
 from __future__ import annotations
 
+import math
+
 from dataclasses import dataclass, field, replace
 from typing import Optional, Tuple
 
@@ -107,6 +109,30 @@ def _cfg5() -> Workload:
                     r0_m=0.12, L0_m=25.0, seeds=(5,),
                     extra=dict(n_modes=500, hidden=1024, n_test=20_000, test_seed=6,
                                residual_rms_nm=100.0))
+
+
+# Detector of the 160 px sensor after the SOUL configuration (Appendix B):
+# 120 x 120 pixels = the central 480 x 480 of the 512 plane in 4 x 4 blocks
+# (one pixel per subaperture, the pupil images 40 px wide at 48 px spacing),
+# a magnitude-8 source at 750 nm, 0.588 ms integration, 300 nm band,
+# quantum efficiency x transmission 0.32, readout 0.4 e-.  The paper gives no
+# photometric zero point; 5.0e7 photons / s / m^2 / nm at magnitude 0 near
+# 750 nm (about Vega's flux there) is the reading used.
+ZERO_POINT_PH = 5.0e7
+
+
+def photo_electrons(magnitude: float, diameter_m: float, obstruction: float, band_nm: float, dt_s: float,
+                    qe: float, zero_point: float = ZERO_POINT_PH) -> float:
+    """Expected detected photo-electrons per frame from a source of the given
+    magnitude on an annular pupil (obstruction as a diameter ratio)."""
+    area = math.pi / 4.0 * diameter_m ** 2 * (1.0 - obstruction ** 2)
+    return zero_point * 10.0 ** (-0.4 * magnitude) * area * band_nm * dt_s * qe
+
+
+def soul_detector(s: SensorDesc) -> dict:
+    """Detector parameters (pwfs_ccd_desc fields) for the 160 px sensor."""
+    return dict(n_det=120, rebin=4, readout_e=0.4,
+                electrons=photo_electrons(8.0, s.diameter_m, s.obstruction, 300.0, 0.000588, 0.32))
 
 
 WORKLOADS = {
