@@ -196,6 +196,66 @@ def detector_form(P, torch, dev, stream, x, plan, I, s, steps: int):
                          "avg_launch_ms": round(ccd_ms / max(1, ccd_n), 4), "traffic": None}}
 
 
+def loop_form(torch, dev, steps: int = 2000):
+    """Closed AO loop of the SOUL configuration around the 160 px sensor
+    (500 KL modes, four frozen-flow layers, the listing's integrator and
+    delay): calibrated by push-pull, one timestep captured in a HIP graph,
+    `steps` replays timed; then the residual wavefront over 200 more steps."""
+    import numpy as np
+    from paper_2602_06688_amd import pwfs as P
+    from paper_2602_06688_amd.loop import ClosedLoop
+    from workloads import workload
+    from workloads.configs import soul_loop
+    from workloads.modes import kl_modes
+    from workloads.screens import periodic_layer
+    s = workload("cfg2").sensors[0]
+    cfg = soul_loop(s)
+    t0 = time.perf_counter()
+    Z, _ = kl_modes(s.n_pupil, s.obstruction, s.diameter_m, cfg["L0_m"], cfg["n_modes"])
+    screens = np.stack([periodic_layer(cfg["screen_px"], cfg["pixel_m"], cfg["r0_m"], cfg["L0_m"], sd)
+                        for sd in cfg["seeds"]])
+    params = [(float(np.sqrt(c)), o[0], o[1], v[0], v[1])
+              for c, o, v in zip(cfg["cn2"], cfg["origins_px"], cfg["velocities_px"])]
+    g = np.concatenate([np.full(n, v) for v, n in zip(cfg["gains"], cfg["groups"])])
+    ff = np.concatenate([np.full(n, v) for v, n in zip(cfg["ff"], cfg["groups"])])
+    loop = ClosedLoop(s, Z.T.copy(), screens, params, g, ff, cfg["delay"], device=dev)
+    loop.calibrate(delta_nm=10.0)
+    t_setup = time.perf_counter() - t0
+    loop.reset()
+    loop.capture()
+    loop.run(50)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    loop.run(steps)
+    torch.cuda.synchronize(dev)
+    dt = (time.perf_counter() - t0) / steps
+    # residual and open-loop wavefront (telemetry, outside the timed region)
+    c = np.arange(s.n_pupil) - (s.n_pupil - 1) / 2.0
+    r2 = c[None, :] ** 2 + c[:, None] ** 2
+    rad = s.n_pupil / 2.0
+    pupil = (r2 <= rad * rad) & (r2 >= (s.obstruction * rad) ** 2)
+    closed = []
+    loop.run(200, record=lambda lp: closed.append(lp.residual_rms(pupil)))
+    st = torch.zeros(1, dtype=torch.int64, device=dev)
+    opn = []
+    for t in range(0, steps + 250, 250):
+        st.fill_(t)
+        o = P.layers(loop.screens, loop.layer_params, s.n_pupil, st).cpu().numpy()[pupil]
+        opn.append(float(np.sqrt(np.mean((o - o.mean()) ** 2))))
+    fl = nominal_flops(s)["path"]
+    ach = fl / dt / 1e12
+    print(f"# closed loop: {1.0 / dt:.0f} timesteps/s ({dt * 1e3:.3f} ms), residual {np.mean(closed):.0f} nm "
+          f"(open loop {np.mean(opn):.0f} nm)", file=sys.stderr, flush=True)
+    return {"value": round(1.0 / dt, 1), "unit": "timesteps/s", "ms_per_timestep": round(dt * 1e3, 4),
+            "steps_timed": steps, "setup_seconds": round(t_setup, 2),
+            "residual_rms_nm": round(float(np.mean(closed)), 1), "open_loop_rms_nm": round(float(np.mean(opn)), 1),
+            "what": "layers + mirror GEMM + sensor (1 frame) + slopes + reconstructor GEMM + integrator, "
+                    "one HIP graph replay per timestep",
+            "roofline": {"kernel": "whole timestep (sensor flops at one frame per launch)", "bound": "alu",
+                         "achieved": round(ach, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(ach / FP32_PEAK_TFLOPS, 4), "flops_per_timestep": fl, "traffic": None}}
+
+
 def hetero_form(P, torch, dev, stream, steps: int, graph_reps: int = 200):
     """Six sensors (80-240 px pupils, FFT 256-768, 16-96 points, 3 wavelengths)
     in one plan: autotuned execution, timesteps/s over the 500-frame batch, and
@@ -309,6 +369,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="time only the plain FP32 path")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate form")
     ap.add_argument("--no-detector", action="store_true", help="skip the path with the detector stage")
+    ap.add_argument("--no-loop", action="store_true", help="skip the closed AO loop")
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous six-sensor batch")
     ap.add_argument("--surrogate-train", type=int, default=200_000)
     ap.add_argument("--surrogate-epochs", type=int, default=20)
@@ -406,6 +467,8 @@ def main() -> int:
         forms["detector"] = detector_form(P, torch, dev, stream, x, plan, I, s, max(2, args.steps // 2))
     if not args.no_surrogate:
         forms["surrogate"] = surrogate_form(torch, dev, args.surrogate_train, 20_000, args.surrogate_epochs, 5)
+    if not args.no_loop:
+        forms["closed_loop"] = loop_form(torch, dev)
     if not args.no_hetero:
         forms["hetero6_poly3"] = hetero_form(P, torch, dev, stream, max(2, args.steps // 5))
 

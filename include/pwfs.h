@@ -249,6 +249,51 @@ int pwfs_ccd_slopes(pwfs_plan_t plan, int sensor, const pwfs_ccd_desc* ccd, cons
                     float* d_slopes, float* d_flux, void* hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Closed loop (the SOUL chain of Appendix B: atmosphere -> mirror -> pyramid
+ * -> Modalrec -> Integrator, closed through the delayed connection of
+ * Section 2.1).  The mirror (OPD -= B c) and the reconstructor (m = R s) are
+ * pwfs_gemm products; these two calls are the rest.  The time index t is an
+ * int64 in device memory, read by pwfs_layers and advanced by
+ * pwfs_integrator, so one captured timestep replays unchanged.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  double weight;               /* multiplies the layer's screen */
+  double origin_x, origin_y;   /* screen coordinates (pixels) of pupil pixel (0, 0) at t = 0 */
+  double vel_x, vel_y;         /* pixels per time step */
+} pwfs_layer;
+
+/*
+ * d_opd [D][D] float32 = sum_l weight_l * S_l(x + origin_x_l + vel_x_l t,
+ * y + origin_y_l + vel_y_l t) with t = *d_step: frozen-flow layers, each
+ * screen S_l periodic ([n_layers][rows][cols] float32 on the device),
+ * sampled bilinearly in float64 (pupil pixel (x, y) = column x, row y).
+ * layers is a host array of n_layers (1..16) entries.  Asynchronous.
+ */
+int pwfs_layers(const float* d_screens, int n_layers, int rows, int cols, const pwfs_layer* layers, int D,
+                const long long* d_step, float* d_opd, void* hip_stream);
+
+/*
+ * Integrator step at t = *d_step: c(t) = ff * c(t-1) + gain * m(t) per mode
+ * (c(-1) = 0), stored in d_hist [delay + 1][n_modes] at slot t mod
+ * (delay + 1); d_applied <- c(t + 1 - delay) (zero before it exists), the
+ * command the mirror applies at the next step; then *d_step = t + 1.
+ * d_hist must be zeroed with *d_step = 0 to start a loop.  delay in [1, 64].
+ * Asynchronous (one workgroup).
+ */
+int pwfs_integrator(const float* d_modes, const float* d_gain, const float* d_ff, int n_modes, int delay,
+                    float* d_hist, float* d_applied, long long* d_step, void* hip_stream);
+
+/*
+ * y[M] = alpha * A[M][K] x[K] + beta * y in float32 (fma accumulation per
+ * row, fixed-order sum): the loop's mirror (OPD -= B c) and reconstructor
+ * (m = R s), matrix-vector products bound by reading A once.  Row-major A
+ * with lda >= K; with beta == 0 the old y is not read.  Asynchronous.
+ */
+int pwfs_gemv(const float* d_A, long long lda, const float* d_x, float* d_y, int M, int K, float alpha, float beta,
+              void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Matrix-core products.  The learned-surrogate form and its data pipeline
  * (modal coefficients -> OPD, the linear interaction-matrix baseline) need
  * dense products; they run on the same split-precision MFMA tiles as the

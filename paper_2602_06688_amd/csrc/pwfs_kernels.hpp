@@ -418,21 +418,34 @@ __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
 // spread over the NT threads; consecutive threads read consecutive blocks of
 // a pixel row.  NT = 1024 serves small frame counts, where the frame's own
 // latency is the cost.
-template <int NT>
+// BB: the block size b when known at compile time (its loads are then issued
+// together), 0 for a run-time b.
+template <int NT, int BB>
 __global__ __launch_bounds__(NT) void k_slopes(SlopeArgs p) {
   extern __shared__ float s_q[];        // [4][n*n]
   __shared__ double s_red[NT];
   const int tid = threadIdx.x, f = blockIdx.x;
   const int nn = p.n * p.n;
   const float* I = p.in + (long long)f * p.in_stride;
+  const int b = BB ? BB : p.b;
 
   for (int it = tid; it < 4 * nn; it += NT) {
     const int q = it / nn, s = it % nn;
     const int i = s / p.n, j = s % p.n;
-    const float* blk = I + (size_t)(p.org_r[q] + i * p.b) * p.N + p.org_c[q] + j * p.b;
+    const float* blk = I + (size_t)(p.org_r[q] + i * b) * p.N + p.org_c[q] + j * b;
     float acc = 0.f;
-    for (int r = 0; r < p.b; ++r)
-      for (int c = 0; c < p.b; ++c) acc += blk[(size_t)r * p.N + c];
+    if constexpr (BB > 0) {
+      float v[BB * BB];
+#pragma unroll
+      for (int r = 0; r < BB; ++r)
+#pragma unroll
+        for (int c = 0; c < BB; ++c) v[r * BB + c] = blk[(size_t)r * p.N + c];
+#pragma unroll
+      for (int e = 0; e < BB * BB; ++e) acc += v[e];
+    } else {
+      for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) acc += blk[(size_t)r * p.N + c];
+    }
     s_q[it] = acc;
   }
   __syncthreads();

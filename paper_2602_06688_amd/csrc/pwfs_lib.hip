@@ -562,8 +562,16 @@ int prepare_kernels() {
   if ((rc = set_lds_limits_q<384>())) return rc;
   if ((rc = set_lds_limits_q<512>())) return rc;
   if ((rc = set_lds_limits_q<768>())) return rc;
-  lds_limit((const void*)k_slopes<kBlock>);
-  lds_limit((const void*)k_slopes<1024>);
+  lds_limit((const void*)k_slopes<kBlock, 0>);
+  lds_limit((const void*)k_slopes<kBlock, 1>);
+  lds_limit((const void*)k_slopes<kBlock, 2>);
+  lds_limit((const void*)k_slopes<kBlock, 4>);
+  lds_limit((const void*)k_slopes<kBlock, 8>);
+  lds_limit((const void*)k_slopes<1024, 0>);
+  lds_limit((const void*)k_slopes<1024, 1>);
+  lds_limit((const void*)k_slopes<1024, 2>);
+  lds_limit((const void*)k_slopes<1024, 4>);
+  lds_limit((const void*)k_slopes<1024, 8>);
   lds_limit((const void*)k_hetero);
   done = true;
   return PWFS_OK;
@@ -596,10 +604,20 @@ int slopes_launch_at(const SensorPlan& sp, const float* in, long long in_stride,
   }
   const size_t lds = sizeof(float) * 4 * g.n * g.n;
   const int slot = prof ? prof->begin(st) : -1;
-  if (nf >= kSlopesWideBelow)
-    hipLaunchKernelGGL(k_slopes<kBlock>, dim3((unsigned)nf), dim3(kBlock), lds, st, a);
-  else
-    hipLaunchKernelGGL(k_slopes<1024>, dim3((unsigned)nf), dim3(1024), lds, st, a);
+  const bool wide = nf < kSlopesWideBelow;
+  const dim3 grid((unsigned)nf), block(wide ? 1024 : kBlock);
+  switch ((wide ? 100 : 0) + (b == 1 || b == 2 || b == 4 || b == 8 ? b : 0)) {
+    case 1: hipLaunchKernelGGL((k_slopes<kBlock, 1>), grid, block, lds, st, a); break;
+    case 2: hipLaunchKernelGGL((k_slopes<kBlock, 2>), grid, block, lds, st, a); break;
+    case 4: hipLaunchKernelGGL((k_slopes<kBlock, 4>), grid, block, lds, st, a); break;
+    case 8: hipLaunchKernelGGL((k_slopes<kBlock, 8>), grid, block, lds, st, a); break;
+    case 0: hipLaunchKernelGGL((k_slopes<kBlock, 0>), grid, block, lds, st, a); break;
+    case 101: hipLaunchKernelGGL((k_slopes<1024, 1>), grid, block, lds, st, a); break;
+    case 102: hipLaunchKernelGGL((k_slopes<1024, 2>), grid, block, lds, st, a); break;
+    case 104: hipLaunchKernelGGL((k_slopes<1024, 4>), grid, block, lds, st, a); break;
+    case 108: hipLaunchKernelGGL((k_slopes<1024, 8>), grid, block, lds, st, a); break;
+    default: hipLaunchKernelGGL((k_slopes<1024, 0>), grid, block, lds, st, a); break;
+  }
   HIP_TRY(hipGetLastError(), "launch k_slopes");
   if (prof) prof->end(slot, st, K_SLOPES);
   return PWFS_OK;

@@ -79,6 +79,11 @@ class CCcdDesc(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class CLayer(ctypes.Structure):
+    _fields_ = [("weight", ctypes.c_double), ("origin_x", ctypes.c_double), ("origin_y", ctypes.c_double),
+                ("vel_x", ctypes.c_double), ("vel_y", ctypes.c_double)]
+
+
 def ccd_desc(n_det: int, rebin: int, electrons: float, flags: int = CCD_PHOTON, readout_e: float = 0.0,
              seed: int = 0) -> CCcdDesc:
     """A detector description (see pwfs_ccd_desc in include/pwfs.h)."""
@@ -122,6 +127,9 @@ def lib() -> ctypes.CDLL:
     L.pwfs_destroy.restype = None
     L.pwfs_ccd.argtypes = [vp, i32, P(CCcdDesc), vp, i32, ctypes.c_longlong, vp, vp]
     L.pwfs_ccd_slopes.argtypes = [vp, i32, P(CCcdDesc), vp, i32, vp, vp, vp]
+    L.pwfs_layers.argtypes = [vp, i32, i32, i32, P(CLayer), i32, vp, vp, vp]
+    L.pwfs_integrator.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
+    L.pwfs_gemv.argtypes = [vp, ctypes.c_longlong, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, vp]
     L.pwfs_get_tuning.argtypes = [vp, P(CTuning)]
     L.pwfs_set_tuning.argtypes = [vp, P(CTuning)]
     ll = ctypes.c_longlong
@@ -143,7 +151,7 @@ def lib() -> ctypes.CDLL:
                  "pwfs_query", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
                  "pwfs_gemm_workspace_size", "pwfs_gemm", "pwfs_row_rms", "pwfs_mlp_workspace_size",
                  "pwfs_mlp_create", "pwfs_mlp_param_count", "pwfs_mlp_set_params", "pwfs_mlp_get_params",
-                 "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam", "pwfs_ccd", "pwfs_ccd_slopes"):
+                 "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam", "pwfs_ccd", "pwfs_ccd_slopes", "pwfs_layers", "pwfs_integrator", "pwfs_gemv"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -400,6 +408,48 @@ def gemm(A, B, out=None, alpha: float = 1.0, beta: float = 0.0, precision: int =
                           float(alpha), float(beta), precision, ctypes.c_void_p(ptr), n.value,
                           _stream_ptr(stream)))
     return out
+
+
+def layers(screens, params, D: int, step, out=None, stream=None):
+    """Frozen-flow OPD [D, D] at t = step[0] (int64 device tensor) of screens
+    [L, rows, cols]; params: sequence of (weight, origin_x, origin_y, vel_x,
+    vel_y) per layer (see pwfs_layers)."""
+    import torch
+    Lr, rows, cols = (int(v) for v in screens.shape)
+    arr = (CLayer * Lr)(*[CLayer(*[float(v) for v in p]) for p in params])
+    if out is None:
+        out = torch.empty((D, D), dtype=torch.float32, device=screens.device)
+    check(lib().pwfs_layers(_dev_ptr(screens, "screens", torch.float32, Lr * rows * cols), Lr, rows, cols, arr, int(D),
+                            _dev_ptr(step, "step", torch.int64, 1), _dev_ptr(out, "opd", torch.float32, D * D),
+                            _stream_ptr(stream)))
+    return out
+
+
+def gemv(A, x, out=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+    """out [M] = alpha * A [M, K] @ x [K] + beta * out, float32 (see pwfs_gemv)."""
+    import torch
+    M, K = (int(v) for v in A.shape)
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs an output to accumulate into")
+        out = torch.empty(M, dtype=torch.float32, device=A.device)
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major")
+    check(lib().pwfs_gemv(ctypes.c_void_p(A.data_ptr()), A.stride(0), _dev_ptr(x, "x", torch.float32, K),
+                          _dev_ptr(out, "out", torch.float32, M), M, K, float(alpha), float(beta),
+                          _stream_ptr(stream)))
+    return out
+
+
+def integrator(modes, gain, ff, delay: int, hist, applied, step, stream=None):
+    """One integrator step (see pwfs_integrator); advances step[0]."""
+    import torch
+    n = int(modes.numel())
+    check(lib().pwfs_integrator(_dev_ptr(modes, "modes", torch.float32, n), _dev_ptr(gain, "gain", torch.float32, n),
+                                _dev_ptr(ff, "ff", torch.float32, n), n, int(delay),
+                                _dev_ptr(hist, "hist", torch.float32, (int(delay) + 1) * n),
+                                _dev_ptr(applied, "applied", torch.float32, n),
+                                _dev_ptr(step, "step", torch.int64, 1), _stream_ptr(stream)))
 
 
 def row_rms(x, out=None, stream=None):

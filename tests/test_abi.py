@@ -95,7 +95,7 @@ def test_ctypes_structs_match_header_layout(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = {"pwfs_sensor_desc": P.CSensorDesc, "pwfs_sensor_info": P.CSensorInfo, "pwfs_tuning": P.CTuning,
-               "pwfs_ccd_desc": P.CCcdDesc}
+               "pwfs_ccd_desc": P.CCcdDesc, "pwfs_layer": P.CLayer}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pwfs.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')

@@ -72,6 +72,22 @@ def von_karman_opd(frames, n_pupil: int, diameter_m: float, r0_m: float, L0_m: f
     return out
 
 
+def periodic_layer(n: int, pixel_m: float, r0_m: float, L0_m: float, seed: int,
+                   r0_lambda_nm: float = 500.0) -> np.ndarray:
+    """One whole periodic von Karman OPD screen [n][n] in nm (float32): the
+    real part of an n x n FFT screen with pixel size pixel_m (same spectrum
+    and normalisation as von_karman_opd), for frozen-flow layers."""
+    f = np.fft.fftfreq(n, d=pixel_m)
+    f2 = f[None, :] ** 2 + f[:, None] ** 2
+    psd = 0.0229 * r0_m ** (-5.0 / 3.0) * (f2 + L0_m ** -2) ** (-11.0 / 6.0)
+    psd[0, 0] = 0.0
+    amp = np.sqrt(psd) / (n * pixel_m)
+    rng = np.random.default_rng([int(seed), 1 << 20])
+    c = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    scr = scipy.fft.ifft2(c * amp, workers=_workers()) * (n * n)
+    return (scr.real * (r0_lambda_nm / (2.0 * math.pi))).astype(np.float32)
+
+
 def _centred(n_pupil: int) -> np.ndarray:
     return np.arange(n_pupil, dtype=np.float64) - (n_pupil - 1) / 2.0
 
