@@ -303,7 +303,16 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
 }
 
 // ------------------------------------------------------------- columns ----
-template <int N, int QM_>
+// The modulation points, in k-order, are cut into G contiguous groups (G =
+// lane groups per workgroup), group g = [g n_mod / G, (g + 1) n_mod / G).
+// The intensity is summed as: over wavelengths, over groups, the group's
+// partial sum.  Without SPLIT one lane group runs every group of its own
+// column; with SPLIT (few frames) the G lane groups of a workgroup run the
+// G groups of one column and the partials meet in LDS.  The additions are
+// the same in both, so both give the same bits.
+__device__ __forceinline__ int kgroup_lo(int g, int n_mod, int G) { return g * n_mod / G; }
+
+template <int N, int QM_, bool SPLIT>
 __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* smem) {
   using P = FftPlan<N>;
   constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
@@ -316,11 +325,17 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
   float2* s_tw = smem;
   float2* s_m = s_tw + (PAL ? 0 : N);                    // [n_lam][N]
   float2* s_buf = s_m + (PAL ? 0 : p.n_lam * N);
+  float* s_part = (float*)(s_buf + G * BL);              // SPLIT: [n_lam][G][V][T]
 
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
-  const int cb = bid % p.colblocks;
-  const int f = bid / p.colblocks;
-  const int xc = cb * G + g;
+  int xc, f;
+  if constexpr (SPLIT) {
+    xc = bid % p.Nc;
+    f = bid / p.Nc;
+  } else {
+    xc = (bid % p.colblocks) * G + g;
+    f = bid / p.colblocks;
+  }
   const bool live = xc < p.Nc;
   const int xcl = live ? xc : 0;
 
@@ -352,14 +367,16 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
 #pragma unroll
   for (int s = 0; s < V; ++s) acc[s] = 0.f;
 
+  const int it0 = SPLIT ? kgroup_lo(g, p.n_mod, G) : 0;
+  const int it1 = SPLIT ? kgroup_lo(g + 1, p.n_mod, G) : p.n_mod;
   const size_t frame_base = (size_t)f * p.n_lam * p.n_a;
   for (int lam = 0; lam < p.n_lam; ++lam) {
     fp.set_mask(masks + lam * N);
     const float2* rbl = p.rbuf + ((frame_base + (size_t)lam * p.n_a) * p.Nc + xcl) * p.Dp;
     const float2* ryl = p.ry + (size_t)lam * p.n_mod * p.D;
     float2 cn[NL], rn[NL];
-    {
-      const int2 ka = p.kord[0];
+    if (it0 < it1) {
+      const int2 ka = p.kord[it0];
       const float2* col = rbl + (size_t)ka.y * p.Nc * p.Dp;
       const float2* ry = ryl + (size_t)ka.x * p.D;
 #pragma unroll
@@ -368,7 +385,12 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
         rn[l] = ry[yy[l]];
       }
     }
-    for (int it = 0; it < p.n_mod; ++it) {
+    float part[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) part[s] = 0.f;
+    int gi = 0;                                    // group of `it` (no SPLIT)
+    int gend = kgroup_lo(1, p.n_mod, G);
+    for (int it = it0; it < it1; ++it) {
       float2 v[V];
 #pragma unroll
       for (int i = 0; i < NB0; ++i)
@@ -381,7 +403,7 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
             v[i * R0 + q] = czero();
           }
         }
-      if (it + 1 < p.n_mod) {   // prefetch the next point's column and tilt
+      if (it + 1 < it1) {   // prefetch the next point's column and tilt
         const int2 ka = p.kord[it + 1];
         const float2* col = rbl + (size_t)ka.y * p.Nc * p.Dp;
         const float2* ry = ryl + (size_t)ka.x * p.D;
@@ -393,8 +415,36 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
       }
       fp.run(v);
 #pragma unroll
-      for (int s = 0; s < V; ++s) acc[s] += cabs2(v[s]);
+      for (int s = 0; s < V; ++s) part[s] += cabs2(v[s]);
+      if constexpr (!SPLIT) {
+        while (gi < G - 1 && it + 1 >= gend) {   // leaving group gi (empty groups add nothing)
+          if (it + 1 == gend) {
+#pragma unroll
+            for (int s = 0; s < V; ++s) {
+              acc[s] += part[s];
+              part[s] = 0.f;
+            }
+          }
+          ++gi;
+          gend = kgroup_lo(gi + 1, p.n_mod, G);
+        }
+      }
     }
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int s = 0; s < V; ++s) s_part[(((size_t)lam * G + g) * V + s) * T + t] = part[s];
+    } else {
+#pragma unroll
+      for (int s = 0; s < V; ++s) acc[s] += part[s];     // the last group
+    }
+  }
+  if constexpr (SPLIT) {
+    __syncthreads();
+    if (g != 0) return;
+    for (int lam = 0; lam < p.n_lam; ++lam)
+      for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+        for (int s = 0; s < V; ++s) acc[s] += s_part[(((size_t)lam * G + gg) * V + s) * T + t];
   }
   if (!live) return;
   const int X = p.full ? xc : window_coord(xc, p.D, p.win_lo, p.win_hi);
@@ -407,10 +457,10 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
   }
 }
 
-template <int N, int QM>
+template <int N, int QM, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
   extern __shared__ float2 smem[];
-  cols_body<N, QM>(p, blockIdx.x, smem);
+  cols_body<N, QM, SPLIT>(p, blockIdx.x, smem);
 }
 
 // -------------------------------------------------------------- slopes ----
@@ -518,7 +568,7 @@ __device__ __forceinline__ void hetero_rows(const RowArgs& a, int bid, float2* s
 }
 template <int N>
 __device__ __forceinline__ void hetero_cols(const ColArgs& a, int bid, float2* smem) {
-  cols_body<N, 3>(a, bid, smem);
+  cols_body<N, 3, false>(a, bid, smem);
 }
 
 __global__ __launch_bounds__(kBlock, 1) void k_hetero(HeteroArgs p) {

@@ -359,8 +359,8 @@ struct PassArgs {
   FieldArgs fa;
   RowArgs ra;
   ColArgs ca;
-  unsigned grid_field, grid_rows, grid_cols;
-  size_t lds_rows, lds_cols;
+  unsigned grid_field, grid_rows, grid_cols, grid_cols_split;
+  size_t lds_rows, lds_cols, lds_cols_split;
 };
 
 template <int N>
@@ -428,6 +428,9 @@ static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd
   ca.full = g.full;
   pa.lds_cols = sizeof(float2) * ((PAL ? 0 : (size_t)N + (size_t)g.n_lam * N) + (size_t)G * BufLen<N>::value);
   pa.grid_cols = (unsigned)(nf * ca.colblocks);
+  // split column pass (one column per workgroup): its lane groups' partial sums meet in LDS
+  pa.grid_cols_split = (unsigned)(nf * g.Nc);
+  pa.lds_cols_split = pa.lds_cols + sizeof(float) * (size_t)g.n_lam * G * N;
   return pa;
 }
 
@@ -443,6 +446,10 @@ static PassArgs build_pass_any(const SensorPlan& sp, const float* opd, long long
   }
 }
 
+// below this many column workgroups (about two per CU) the column pass runs
+// split: G workgroups per column instead of one per G columns
+constexpr unsigned kColsSplitBelow = 512;
+
 template <int N, int QM>
 static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_stride, float* out,
                        long long out_stride, int nf, float2* rbuf, hipStream_t st, Prof* prof) {
@@ -456,7 +463,10 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
   HIP_TRY(hipGetLastError(), "launch k_rows");
   prof->end(slot, st, K_ROWS);
   slot = prof->begin(st);
-  hipLaunchKernelGGL((k_cols<N, QM>), dim3(pa.grid_cols), dim3(kBlock), pa.lds_cols, st, pa.ca);
+  if (pa.grid_cols < kColsSplitBelow)   // few frames: one column per workgroup, more workgroups
+    hipLaunchKernelGGL((k_cols<N, QM, true>), dim3(pa.grid_cols_split), dim3(kBlock), pa.lds_cols_split, st, pa.ca);
+  else
+    hipLaunchKernelGGL((k_cols<N, QM, false>), dim3(pa.grid_cols), dim3(kBlock), pa.lds_cols, st, pa.ca);
   HIP_TRY(hipGetLastError(), "launch k_cols");
   prof->end(slot, st, K_COLS);
   return PWFS_OK;
@@ -540,7 +550,8 @@ static void lds_limit(const void* fn) {
 template <int N, int QM>
 static int set_lds_limits() {
   lds_limit((const void*)k_rows<N, QM>);
-  lds_limit((const void*)k_cols<N, QM>);
+  lds_limit((const void*)k_cols<N, QM, false>);
+  lds_limit((const void*)k_cols<N, QM, true>);
   return PWFS_OK;
 }
 
