@@ -90,8 +90,9 @@ __global__ __launch_bounds__(1024) void k_integrator(IntegratorArgs p) {
 
 // y[M] = alpha * A[M][K] x[K] + beta * y (y not read when beta == 0), fp32.
 // TPR threads per row (64: one wavefront, 256: the whole workgroup); each
-// thread strides the row by TPR (coalesced), then a fixed-order tree sum.
-template <int TPR>
+// thread strides the row by TPR (coalesced; 16-byte loads when VEC), then a
+// fixed-order tree sum.
+template <int TPR, bool VEC>
 __global__ __launch_bounds__(256) void k_gemv(const float* A, long long lda, const float* x, float* y, int M, int K,
                                               float alpha, float beta) {
   __shared__ float s_red[256];
@@ -101,7 +102,19 @@ __global__ __launch_bounds__(256) void k_gemv(const float* A, long long lda, con
   float acc = 0.f;
   if (row < M) {
     const float* a = A + (long long)row * lda;
-    for (int k = lane; k < K; k += TPR) acc = fmaf(a[k], x[k], acc);
+    if (VEC) {   // 16-byte loads: K and lda multiples of 4, A and x 16-byte aligned
+      const float4* a4 = (const float4*)a;
+      const float4* x4 = (const float4*)x;
+      for (int k = lane; k < K / 4; k += TPR) {
+        const float4 av = a4[k], xv = x4[k];
+        acc = fmaf(av.x, xv.x, acc);
+        acc = fmaf(av.y, xv.y, acc);
+        acc = fmaf(av.z, xv.z, acc);
+        acc = fmaf(av.w, xv.w, acc);
+      }
+    } else {
+      for (int k = lane; k < K; k += TPR) acc = fmaf(a[k], x[k], acc);
+    }
   }
   s_red[threadIdx.x] = acc;
   __syncthreads();
@@ -176,10 +189,19 @@ extern "C" int pwfs_gemv(const float* A, long long lda, const float* x, float* y
   if (!A || !x || !y) return lfail(PWFS_EINVAL, "NULL device pointer");
   if (M < 1 || K < 1 || lda < K) return lfail(PWFS_EINVAL, "bad sizes (M, K >= 1, lda >= K)");
   hipStream_t st = (hipStream_t)stream;
-  if (K >= 1024)
-    hipLaunchKernelGGL(k_gemv<256>, dim3((unsigned)M), dim3(256), 0, st, A, lda, x, y, M, K, alpha, beta);
-  else
-    hipLaunchKernelGGL(k_gemv<64>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, A, lda, x, y, M, K, alpha, beta);
+  const bool vec = K % 4 == 0 && lda % 4 == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)x & 15) == 0;
+  const dim3 wide((unsigned)M), narrow((unsigned)((M + 3) / 4));
+  if (K >= 1024) {
+    if (vec)
+      hipLaunchKernelGGL((k_gemv<256, true>), wide, dim3(256), 0, st, A, lda, x, y, M, K, alpha, beta);
+    else
+      hipLaunchKernelGGL((k_gemv<256, false>), wide, dim3(256), 0, st, A, lda, x, y, M, K, alpha, beta);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((k_gemv<64, true>), narrow, dim3(256), 0, st, A, lda, x, y, M, K, alpha, beta);
+    else
+      hipLaunchKernelGGL((k_gemv<64, false>), narrow, dim3(256), 0, st, A, lda, x, y, M, K, alpha, beta);
+  }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return lfail(PWFS_EHIP, "launch k_gemv: %s", hipGetErrorString(e));
   return PWFS_OK;
