@@ -91,6 +91,29 @@ def modulation_ramp(n_pupil: int, radius_lod: float, theta: float) -> np.ndarray
     return np.exp(1j * arg)
 
 
+def source_points(s) -> np.ndarray:
+    """Points of the source in lambda/D at lambda_ref, [P][2] (x, y): the
+    centre, plus, for an extended source of radius rho sampled with R rings,
+    ring q = 1..R at radius rho q / R with 6 q points at angles 2 pi j / (6 q).
+    Equal weights: with 6 q points on ring q the points are uniformly dense
+    over the disk.  A point source is the centre alone."""
+    R = int(getattr(s, "src_rings", 0))
+    rho = float(getattr(s, "src_radius_lod", 0.0))
+    pts = [(0.0, 0.0)]
+    for q in range(1, R + 1):
+        for j in range(6 * q):
+            a = 2.0 * np.pi * j / (6 * q)
+            pts.append((rho * q / R * np.cos(a), rho * q / R * np.sin(a)))
+    return np.array(pts)
+
+
+def tilt_ramp(n_pupil: int, tx_lod: float, ty_lod: float) -> np.ndarray:
+    """Pupil-plane tilt exp(i 2 pi (tx x + ty y) / D): the focal spot moves by
+    (tx, ty) lambda/D."""
+    c = centred(n_pupil)
+    return np.exp(1j * 2.0 * np.pi * (tx_lod * c[None, :] + ty_lod * c[:, None]) / n_pupil)
+
+
 def image_origins(s) -> list:
     """Top-left corner (row, col) of the four pupil images, quadrant order
     q = 2*iy + ix with iy, ix = 0 for the image at N/2 - S/2 and 1 for N/2 + S/2."""
@@ -126,24 +149,30 @@ def pyramid_image(E_pupil: np.ndarray, n_fft: int, m: np.ndarray) -> np.ndarray:
 def forward_frame(opd_nm: np.ndarray, s, mask: np.ndarray | None = None) -> np.ndarray:
     """Normalised modulated intensity of one frame, float64 [N][N].
 
-    I = sum_l w_l (1/n_mod) sum_k |e_{l,k}|^2 / sum(A^2); phase 2 pi OPD / lambda,
-    modulation radius r_ref * lambda_ref / lambda (a fixed angle on the sky),
-    mask in pixel units independent of lambda."""
+    I = sum_l w_l (1/(n_mod P)) sum_k sum_p |e_{l,k,p}|^2 / sum(A^2) over the
+    modulation points k and the P source points p; phase 2 pi OPD / lambda,
+    modulation radius and source offsets scaled by lambda_ref / lambda (fixed
+    angles on the sky), mask in pixel units independent of lambda."""
     D, N = s.n_pupil, s.n_fft
     A = pupil_amplitude(D, s.obstruction)
     sA2 = float((A * A).sum())
     m = mask_vector(N, s.pupil_sep_px) if mask is None else mask
     th = modulation_angles(s.n_mod)
+    src = source_points(s)
     opd = np.asarray(opd_nm, dtype=np.float64)
     I = np.zeros((N, N), np.float64)
     for lam, w in zip(s.lambdas_nm, s.lambda_weights):
         E0 = A * np.exp(1j * 2.0 * np.pi * opd / lam)
-        r = s.mod_radius_lod * s.lambda_ref_nm / lam
+        sc = s.lambda_ref_nm / lam
+        r = s.mod_radius_lod * sc
         acc = np.zeros((N, N), np.float64)
         for t in th:
-            e = pyramid_image(E0 * modulation_ramp(D, r, t), N, m)
-            acc += e.real ** 2 + e.imag ** 2
-        I += w * acc / (s.n_mod * sA2)
+            Em = E0 * modulation_ramp(D, r, t)
+            for dx, dy in src:
+                Ep = Em if (dx == 0.0 and dy == 0.0) else Em * tilt_ramp(D, sc * dx, sc * dy)
+                e = pyramid_image(Ep, N, m)
+                acc += e.real ** 2 + e.imag ** 2
+        I += w * acc / (s.n_mod * len(src) * sA2)
     return I
 
 
@@ -174,7 +203,10 @@ def separable_operator(n_fft: int, n_pupil: int, pupil_sep: float) -> np.ndarray
 
 
 def forward_frame_separable(opd_nm: np.ndarray, s) -> np.ndarray:
-    """The same intensity as ``forward_frame`` through e_k = P (E o R_k) P^T."""
+    """The same intensity as ``forward_frame`` through e_k = P (E o R_k) P^T
+    (point sources only)."""
+    if int(getattr(s, "src_rings", 0)) > 0:
+        raise ValueError("the separable form is written for a point source")
     D, N = s.n_pupil, s.n_fft
     A = pupil_amplitude(D, s.obstruction)
     sA2 = float((A * A).sum())
