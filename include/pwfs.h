@@ -85,7 +85,9 @@ typedef struct {
   int32_t n_lambda;       /* 1 .. PWFS_MAX_LAMBDA                              */
   int32_t precision;      /* pwfs_precision                                    */
   uint32_t flags;         /* PWFS_F_*                                          */
-  int32_t reserved;       /* must be 0                                         */
+  int32_t src_rings;      /* extended source: rings sampling a uniform disk of
+                             radius src_radius_lod (centre + 6q points on ring
+                             q), 0 = point source; 0..8, FP32 path only        */
   double diameter_m;      /* telescope diameter (> 0; informational)           */
   double obstruction;     /* linear central obstruction ratio, [0, 1)          */
   double pupil_sep_px;    /* S: even integer, D <= S, S + D <= N                */
@@ -93,6 +95,7 @@ typedef struct {
   double lambda_ref_nm;   /* wavelength at which the radius is given, > 0       */
   double lambda_nm[PWFS_MAX_LAMBDA];      /* sensing wavelengths, > 0          */
   double lambda_weight[PWFS_MAX_LAMBDA];  /* >= 0, summing to 1 (to 1e-9)      */
+  double src_radius_lod;  /* extended-source radius in lambda/D at lambda_ref  */
 } pwfs_sensor_desc;
 
 /* What a plan reports about one of its sensors. */

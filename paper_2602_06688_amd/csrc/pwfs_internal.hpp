@@ -43,6 +43,11 @@ struct Layout {
   int chunk = 1;
 };
 
+struct TiltPoint {
+  double tx, ty;   // lambda/D at lambda_ref
+  int key;         // index of the distinct x-tilt (row-pass result) it uses
+};
+void tilt_points(const pwfs_sensor_desc& d, std::vector<TiltPoint>& pts, std::vector<double>& key_tx);
 Geometry geometry(const pwfs_sensor_desc& d);
 void set_last_error(const char* msg);   // message returned by pwfs_last_error
 void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vector<uint8_t>& V);

@@ -70,7 +70,7 @@ struct ColArgs {
   const float2* ry;        // [n_lam][n_mod][D] column tilt
   const float2* mcol;      // [n_lam][N] column mask, offset phase, 1/N, sqrt(weight)
   const float2* tw;        // [N]
-  const int2* kord;        // [n_mod] (point k, distinct-cosine index a), k and n_mod-k adjacent
+  const int2* kord;        // [n_points] (tilt point, its x-tilt key), points sharing a key adjacent
   float* out;              // sensor's first frame of the chunk; frame stride out_stride
   long long out_stride;
   int D, Dp, Nc, n_a, n_lam, n_mod, colblocks;

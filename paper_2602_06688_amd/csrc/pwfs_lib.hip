@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -57,7 +58,14 @@ void set_last_error(const char* msg) { g_err = msg; }
 
 int validate_one(const pwfs_sensor_desc& d, int idx) {
   auto bad = [&](const char* why) { return fail(PWFS_EINVAL, "sensor %d: %s", idx, why); };
-  if (d.reserved != 0) return bad("reserved field must be 0");
+  if (d.src_rings < 0 || d.src_rings > 8) return bad("src_rings must be in [0, 8]");
+  if (d.src_rings > 0) {
+    if (!(d.src_radius_lod >= 0.0) || !std::isfinite(d.src_radius_lod)) return bad("src_radius_lod must be >= 0");
+    if (d.precision != PWFS_FP32)
+      return fail(PWFS_EUNSUPPORTED, "sensor %d: an extended source needs the FP32 path", idx);
+    if ((long long)d.n_mod * (1 + 3LL * d.src_rings * (d.src_rings + 1)) > 8192)
+      return bad("modulation points x source points must be <= 8192");
+  }
   if (d.flags & ~uint32_t(PWFS_F_REF_SLOPES | PWFS_F_FULL_PLANE | PWFS_F_LOCAL_NORM))
     return bad("unknown flag bits");
   if (d.n_pupil < 4 || (d.n_pupil & 1)) return bad("n_pupil must be even and >= 4");
@@ -119,6 +127,61 @@ void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vect
     }
 }
 
+// --------------------------------------------------------- tilt points ----
+// The tilts the sensor sums over, in lambda/D at lambda_ref: every
+// modulation point (radius r_m, angle 2 pi k / n_mod) plus every point of the
+// source (a point source: the centre only; an extended source: the centre
+// and src_rings rings, ring q at radius rho q / src_rings with 6 q points at
+// angles 2 pi j / (6 q)), all with equal weight.  Points whose x-tilts are
+// equal by construction (k and n_mod - k; j and 6q - j) get the same key, so
+// they share a row transform: the x-tilt of a key is computed once from
+// its integer indices.  Points are listed in key order.
+void tilt_points(const pwfs_sensor_desc& d, std::vector<TiltPoint>& pts, std::vector<double>& key_tx) {
+  const int R = d.src_rings;
+  const double rho = R > 0 ? d.src_radius_lod : 0.0;
+  // source points: (ring, j, count)
+  struct Src {
+    int ring, j, m;
+  };
+  std::vector<Src> src{{0, 0, 1}};
+  for (int q = 1; q <= R; ++q)
+    for (int j = 0; j < 6 * q; ++j) src.push_back({q, j, 6 * q});
+  const int n = d.n_mod;
+  // key of an x-tilt: (min(k, n - k), ring, min(j, m - j))
+  std::vector<std::array<int, 3>> keys;
+  std::vector<std::pair<int, int>> key_of;   // per point: (key index, point order)
+  pts.clear();
+  key_tx.clear();
+  std::vector<TiltPoint> raw;
+  std::vector<std::array<int, 3>> raw_key;
+  for (int k = 0; k < n; ++k) {
+    const int ak = std::min(k, n - k);
+    const double cx = d.mod_radius_lod * std::cos(2.0 * kPi * ak / n);
+    const double sy = d.mod_radius_lod * std::sin(2.0 * kPi * k / n);
+    for (const Src& e : src) {
+      const int aj = std::min(e.j, e.m - e.j);
+      const double rr = R > 0 ? rho * e.ring / R : 0.0;
+      const double tx = cx + rr * std::cos(2.0 * kPi * aj / e.m);
+      const double ty = sy + rr * std::sin(2.0 * kPi * e.j / e.m);
+      raw.push_back({tx, ty, 0});
+      raw_key.push_back({ak, e.ring, aj});
+    }
+  }
+  std::vector<std::array<int, 3>> sorted_keys = raw_key;
+  std::sort(sorted_keys.begin(), sorted_keys.end());
+  sorted_keys.erase(std::unique(sorted_keys.begin(), sorted_keys.end()), sorted_keys.end());
+  std::vector<std::vector<int>> members(sorted_keys.size());
+  for (size_t i = 0; i < raw.size(); ++i) {
+    const size_t a = std::lower_bound(sorted_keys.begin(), sorted_keys.end(), raw_key[i]) - sorted_keys.begin();
+    raw[i].key = (int)a;
+    members[a].push_back((int)i);
+  }
+  for (size_t a = 0; a < sorted_keys.size(); ++a) {
+    key_tx.push_back(raw[members[a][0]].tx);
+    for (int i : members[a]) pts.push_back(raw[i]);
+  }
+}
+
 // ----------------------------------------------------------- geometry ----
 Geometry geometry(const pwfs_sensor_desc& d) {
   Geometry g;
@@ -133,10 +196,14 @@ Geometry geometry(const pwfs_sensor_desc& d) {
   g.full = (d.flags & PWFS_F_FULL_PLANE) ? 1 : 0;
   g.Nc = g.full ? g.N : 2 * g.D;
   g.Dp = (g.D + 15) & ~15;
-  g.n_mod = d.n_mod;
   g.n_lam = d.n_lambda;
-  g.n_a = d.n_mod / 2 + 1;
-  if (g.n_a > d.n_mod) g.n_a = d.n_mod;
+  {
+    std::vector<TiltPoint> pts;
+    std::vector<double> key_tx;
+    tilt_points(d, pts, key_tx);
+    g.n_mod = (int)pts.size();
+    g.n_a = (int)key_tx.size();
+  }
   const int stride0 = g.N / fft_r0(g.N);   // distance between the inputs of a first-stage butterfly
   g.qmax = (g.D + stride0 - 1) / stride0;
   return g;
@@ -285,44 +352,38 @@ int upload_tables(const pwfs_sensor_desc& d, char* ws, const size_t* off, hipStr
   *sumA2_out = sumA2;
 
   const double h = -kPi / g.N;  // half-pixel tilt per array index
+  std::vector<TiltPoint> pts;
+  std::vector<double> key_tx;
+  tilt_points(d, pts, key_tx);
   std::vector<float> rx(2 * (size_t)g.n_lam * g.n_a * g.D), ry(2 * (size_t)g.n_lam * g.n_mod * g.D);
   for (int l = 0; l < g.n_lam; ++l) {
-    const double r = d.mod_radius_lod * d.lambda_ref_nm / d.lambda_nm[l];
+    const double sc = d.lambda_ref_nm / d.lambda_nm[l];   // tilts are given at lambda_ref
     for (int a = 0; a < g.n_a; ++a) {
-      const double th = 2.0 * kPi * a / d.n_mod;
       for (int x = 0; x < g.D; ++x) {
         const double xc = x - (g.D - 1) / 2.0;
-        put_c(rx, ((size_t)l * g.n_a + a) * g.D + x,
-              cis(2.0 * kPi * r * xc * std::cos(th) / g.D + h * (g.o + x)));
+        put_c(rx, ((size_t)l * g.n_a + a) * g.D + x, cis(2.0 * kPi * sc * key_tx[a] * xc / g.D + h * (g.o + x)));
       }
     }
     for (int k = 0; k < g.n_mod; ++k) {
-      const double th = 2.0 * kPi * k / d.n_mod;
       for (int y = 0; y < g.D; ++y) {
         const double yc = y - (g.D - 1) / 2.0;
-        put_c(ry, ((size_t)l * g.n_mod + k) * g.D + y,
-              cis(2.0 * kPi * r * yc * std::sin(th) / g.D + h * (g.o + y)));
+        put_c(ry, ((size_t)l * g.n_mod + k) * g.D + y, cis(2.0 * kPi * sc * pts[k].ty * yc / g.D + h * (g.o + y)));
       }
     }
   }
-  // visiting order of the modulation points: k and n_mod - k (same cosine,
-  // same row-pass result) back to back; entries are (k, a)
+  // visiting order: points in key order, so points sharing a row-pass result
+  // are back to back; entries are (point, key)
   std::vector<int> ak;
-  for (int a = 0; a < g.n_a; ++a) {
-    ak.push_back(a);
-    ak.push_back(a);
-    const int k2 = d.n_mod - a;
-    if (a > 0 && k2 != a && k2 < d.n_mod) {
-      ak.push_back(k2);
-      ak.push_back(a);
-    }
+  for (int k = 0; k < g.n_mod; ++k) {
+    ak.push_back(k);
+    ak.push_back(pts[k].key);
   }
   std::vector<float> mrow(2 * (size_t)g.N), mcol(2 * (size_t)g.n_lam * g.N), tw(2 * (size_t)g.N);
   {
     const std::vector<double> m = mask_table(g, 1.0);
     for (size_t i = 0; i < m.size(); ++i) mrow[i] = (float)m[i];
     for (int l = 0; l < g.n_lam; ++l) {
-      const double sc = std::sqrt(d.lambda_weight[l] / ((double)d.n_mod * sumA2));
+      const double sc = std::sqrt(d.lambda_weight[l] / ((double)g.n_mod * sumA2));
       const std::vector<double> mc = mask_table(g, sc);
       for (size_t i = 0; i < mc.size(); ++i) mcol[(size_t)l * 2 * g.N + i] = (float)mc[i];
     }

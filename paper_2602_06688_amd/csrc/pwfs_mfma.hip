@@ -361,7 +361,7 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
   a2.win_hi = g.win_hi;
   a2.full = g.full;
   for (int l = 0; l < m.n_lam; ++l)
-    a2.scale[l] = (float)(sp.desc.lambda_weight[l] / ((double)sp.desc.n_mod * sp.sumA2));
+    a2.scale[l] = (float)(sp.desc.lambda_weight[l] / ((double)sp.g.n_mod * sp.sumA2));
   const unsigned g2 = (unsigned)(nf * a2.mtiles * a2.ntiles);
   slot = prof->begin(st);
   hipLaunchKernelGGL((k_mfma_cols<NPL, F16>), dim3(g2), dim3(256), lds, st, a2);
@@ -448,22 +448,25 @@ int upload_mfma_tables(const pwfs_sensor_desc& d, char* dst, hipStream_t st, std
         }
       }
   };
+  // the tilt points in the order the visiting table refers to them (point
+  // index and distinct x-tilt key, as in the FP32 path)
+  std::vector<TiltPoint> pts;
+  std::vector<double> key_tx;
+  tilt_points(d, pts, key_tx);
   std::vector<std::complex<double>> ramp(D);
   for (int l = 0; l < m.n_lam; ++l) {
-    const double r = d.mod_radius_lod * d.lambda_ref_nm / d.lambda_nm[l];
+    const double sc = d.lambda_ref_nm / d.lambda_nm[l];
     for (int a = 0; a < m.n_a; ++a) {
-      const double th = 2.0 * kPi * a / d.n_mod;
-      for (int x = 0; x < D; ++x) ramp[x] = std::polar(1.0, 2.0 * kPi * r * (x - (D - 1) / 2.0) * std::cos(th) / D);
+      for (int x = 0; x < D; ++x) ramp[x] = std::polar(1.0, 2.0 * kPi * sc * key_tx[a] * (x - (D - 1) / 2.0) / D);
       put((size_t)l * m.n_a + a, ramp);
     }
   }
   // the two planes are laid out [plane][qx blocks ... qy blocks], so qy
   // blocks of plane 0 start after all qx blocks of plane 0
   for (int l = 0; l < m.n_lam; ++l) {
-    const double r = d.mod_radius_lod * d.lambda_ref_nm / d.lambda_nm[l];
+    const double sc = d.lambda_ref_nm / d.lambda_nm[l];
     for (int k = 0; k < m.n_mod; ++k) {
-      const double th = 2.0 * kPi * k / d.n_mod;
-      for (int y = 0; y < D; ++y) ramp[y] = std::polar(1.0, 2.0 * kPi * r * (y - (D - 1) / 2.0) * std::sin(th) / D);
+      for (int y = 0; y < D; ++y) ramp[y] = std::polar(1.0, 2.0 * kPi * sc * pts[k].ty * (y - (D - 1) / 2.0) / D);
       put((size_t)m.n_lam * m.n_a + (size_t)l * m.n_mod + k, ramp);
     }
   }

@@ -42,11 +42,12 @@ class CSensorDesc(ctypes.Structure):
     _fields_ = [
         ("n_pupil", ctypes.c_int32), ("n_fft", ctypes.c_int32), ("n_subap", ctypes.c_int32),
         ("n_mod", ctypes.c_int32), ("n_lambda", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("src_rings", ctypes.c_int32),
         ("diameter_m", ctypes.c_double), ("obstruction", ctypes.c_double),
         ("pupil_sep_px", ctypes.c_double), ("mod_radius_lod", ctypes.c_double),
         ("lambda_ref_nm", ctypes.c_double),
         ("lambda_nm", ctypes.c_double * MAX_LAMBDA), ("lambda_weight", ctypes.c_double * MAX_LAMBDA),
+        ("src_radius_lod", ctypes.c_double),
     ]
 
 
@@ -174,7 +175,8 @@ def to_c(s) -> CSensorDesc:
     d.n_lambda = len(lams)
     d.precision = int(getattr(s, "precision", FP32))
     d.flags = int(getattr(s, "flags", F_REF_SLOPES))
-    d.reserved = 0
+    d.src_rings = int(getattr(s, "src_rings", 0))
+    d.src_radius_lod = float(getattr(s, "src_radius_lod", 0.0))
     d.diameter_m = float(getattr(s, "diameter_m", 8.0))
     d.obstruction = float(s.obstruction)
     d.pupil_sep_px = float(s.pupil_sep_px)

@@ -44,6 +44,11 @@ def _bad(**kw):
     (dict(mod_radius_lod=-1.0), P.PWFS_EINVAL),
     (dict(n_fft=160, pupil_sep_px=64.0), P.PWFS_EUNSUPPORTED),   # no radix plan
     (dict(flags=64), P.PWFS_EINVAL),
+    (dict(src_rings=9, src_radius_lod=1.0), P.PWFS_EINVAL),
+    (dict(src_rings=-1), P.PWFS_EINVAL),
+    (dict(src_rings=2, src_radius_lod=-0.5), P.PWFS_EINVAL),
+    (dict(src_rings=8, src_radius_lod=1.0, n_mod=64), P.PWFS_EINVAL),         # > 8192 points
+    (dict(src_rings=1, src_radius_lod=1.0, precision=2), P.PWFS_EUNSUPPORTED),  # matrix-core form
 ])
 def test_validate_rejects(kw, code):
     assert P.validate([_bad(**kw)]) == code

@@ -103,6 +103,14 @@ EDGE = {
                              obstruction=0.12, mod_radius_lod=3.0, flags=3),
     "N768": tiny_sensor(n_pupil=240, n_fft=768, n_subap=60, pupil_sep_px=288.0, n_mod=8,
                         obstruction=0.28, mod_radius_lod=5.0),
+    # extended sources: modulation points x source points (rings of a uniform disk)
+    "extended_r1": tiny_sensor(n_pupil=64, n_fft=128, n_subap=16, pupil_sep_px=64.0, n_mod=8,
+                               mod_radius_lod=2.0, src_rings=1, src_radius_lod=1.5),
+    "extended_r2_unmod": tiny_sensor(n_pupil=48, n_fft=128, n_subap=12, pupil_sep_px=56.0, n_mod=1,
+                                     mod_radius_lod=0.0, src_rings=2, src_radius_lod=2.0, obstruction=0.2),
+    "extended_poly_N256": tiny_sensor(n_pupil=80, n_fft=256, n_subap=20, pupil_sep_px=96.0, n_mod=6,
+                                      mod_radius_lod=2.0, src_rings=1, src_radius_lod=1.0,
+                                      lambdas_nm=(650.0, 850.0), lambda_weights=(0.5, 0.5), flags=3),
 }
 
 
@@ -221,3 +229,20 @@ def test_frames_beyond_plan_rejected():
     with pytest.raises(P.PwfsError) as ei:
         plan.forward(x, out)
     assert ei.value.code == P.PWFS_ESTATE
+
+
+def test_extended_source_persistent_equals_launches():
+    """The persistent launch runs the same tables for an extended source
+    (modulation points x source points, shared row transforms by key)."""
+    P = _P()
+    s = EDGE["extended_poly_N256"]
+    from workloads import von_karman_opd
+    opd = von_karman_opd(2, s.n_pupil, 8.0, 0.5, 25.0, seed=17)
+    x = torch.from_numpy(np.ascontiguousarray(opd, dtype=np.float32)).cuda()
+    plan = P.Plan([s], max_frames=2)
+    _say("[gpu] extended source: launches vs persistent")
+    I0, S0, _ = [t.clone() for t in plan.step(x)]
+    plan.set_tuning(mode=P.MODE_PERSISTENT)
+    I1, S1, _ = plan.step(x)
+    torch.cuda.synchronize()
+    assert torch.equal(I0, I1) and torch.equal(S0, S1)

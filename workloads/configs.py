@@ -44,6 +44,8 @@ class SensorDesc:
     lambda_weights: Tuple[float, ...] = (1.0,)
     precision: int = PREC_FP32
     flags: int = FLAG_REF_SLOPES
+    src_rings: int = 0           # extended source: rings sampling a uniform disk (0 = point source)
+    src_radius_lod: float = 0.0  # extended-source radius in lambda/D at lambda_ref
 
     @property
     def n_lambda(self) -> int:
