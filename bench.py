@@ -256,6 +256,48 @@ def loop_form(torch, dev, steps: int = 2000):
                          "frac": round(ach / FP32_PEAK_TFLOPS, 4), "flops_per_timestep": fl, "traffic": None}}
 
 
+def sh_form(P, torch, dev, x, steps: int):
+    """Shack-Hartmann sensor: the paper's SCAO SH shape (Table 2: 160 px, 20 x 20
+    subapertures, 56 x 56 focal samples, 8 x 8 pixels each) over the 1000
+    160 px frames, and a MORFEO-LGS-like shape (68 x 68 subapertures of 7 px,
+    240 x 240 samples, 16 x 16 pixels) over 100 frames (six LGS sensors per
+    timestep).  Centre-of-gravity slopes; flops are those the kernel executes
+    (two complex products per subaperture, |F|^2)."""
+    import numpy as np
+    from workloads import von_karman_opd
+
+    def one(desc, opd, reps):
+        sh = P.SH(desc, max_frames=int(opd.shape[0]), device=dev)
+        sl = torch.empty((int(opd.shape[0]), 2, sh.n, sh.n), dtype=torch.float32, device=dev)
+        sh.forward(opd, slopes=sl)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sh.forward(opd, slopes=sl)
+        torch.cuda.synchronize(dev)
+        dt = (time.perf_counter() - t0) / reps
+        b, M = desc.n_pupil // desc.n_subap, desc.n_fft
+        fl = (8.0 * b * b * M + 8.0 * b * M * M + 3.0 * M * M) * sh.n_valid
+        return int(opd.shape[0]) / dt, fl, sh.n_valid
+
+    fs1, fl1, nv1 = one(P.sh_desc(160, 20, 56, 7, 0.0, 750.0), x, steps)
+    lgs = torch.from_numpy(von_karman_opd(100, 476, 38.5, 0.157, 25.0, seed=61)).to(dev)
+    fs2, fl2, nv2 = one(P.sh_desc(476, 68, 240, 15, 0.28, 750.0), lgs, max(2, steps // 4))
+    a1 = fl1 * fs1 / 1e12
+    a2 = fl2 * fs2 / 1e12
+    print(f"# shack-hartmann: SCAO {fs1:.0f} frames/s ({a1:.1f} TFLOP/s), LGS-like {fs2:.0f} frames/s "
+          f"= {fs2 / 6:.0f} six-sensor timesteps/s ({a2:.1f} TFLOP/s)", file=sys.stderr, flush=True)
+    return {"value": round(fs1, 1), "unit": "frames/s", "workload": "SCAO SH 160 px, 20x20 subap, 56x56, 8x8 px",
+            "valid_subapertures": nv1,
+            "roofline": {"kernel": "k_sh (per-subaperture focal DFT in LDS, |F|^2, binning, centroid)",
+                         "bound": "alu", "achieved": round(a1, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(a1 / FP32_PEAK_TFLOPS, 4), "flops_per_frame": fl1, "traffic": None},
+            "lgs_like": {"frames_per_s": round(fs2, 1), "six_sensor_timesteps_per_s": round(fs2 / 6, 1),
+                         "workload": "68x68 subap of 7 px (476 px pupil), 240x240 focal samples, 16x16 px",
+                         "valid_subapertures": nv2, "achieved_tflops": round(a2, 2),
+                         "frac": round(a2 / FP32_PEAK_TFLOPS, 4), "flops_per_frame": fl2}}
+
+
 def hetero_form(P, torch, dev, stream, steps: int, graph_reps: int = 200):
     """Six sensors (80-240 px pupils, FFT 256-768, 16-96 points, 3 wavelengths)
     in one plan: autotuned execution, timesteps/s over the 500-frame batch, and
@@ -370,6 +412,7 @@ def main() -> int:
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate form")
     ap.add_argument("--no-detector", action="store_true", help="skip the path with the detector stage")
     ap.add_argument("--no-loop", action="store_true", help="skip the closed AO loop")
+    ap.add_argument("--no-sh", action="store_true", help="skip the Shack-Hartmann sensor")
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous six-sensor batch")
     ap.add_argument("--surrogate-train", type=int, default=200_000)
     ap.add_argument("--surrogate-epochs", type=int, default=20)
@@ -467,6 +510,8 @@ def main() -> int:
         forms["detector"] = detector_form(P, torch, dev, stream, x, plan, I, s, max(2, args.steps // 2))
     if not args.no_surrogate:
         forms["surrogate"] = surrogate_form(torch, dev, args.surrogate_train, 20_000, args.surrogate_epochs, 5)
+    if not args.no_sh:
+        forms["shack_hartmann"] = sh_form(P, torch, dev, x, max(2, args.steps // 2))
     if not args.no_loop:
         forms["closed_loop"] = loop_form(torch, dev)
     if not args.no_hetero:

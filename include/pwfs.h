@@ -297,6 +297,53 @@ int pwfs_gemv(const float* d_A, long long lda, const float* d_x, float* d_y, int
               void* hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Shack-Hartmann sensor (the paper's SH processing object, Table 4; FFT
+ * workload shapes in Table 2, e.g. the SCAO SH: 160 px pupil, 20 x 20
+ * subapertures, 56 x 56 focal samples each).  Per frame and subaperture:
+ * the b x b block (b = n_pupil / n_subap) of A exp(i 2 pi OPD / lambda) is
+ * transformed onto n_fft x n_fft focal samples at the half-integer
+ * frequencies (u - n_fft/2 + 1/2) / n_fft, |F|^2 / (n_fft^2 sum A^2) is
+ * summed over rebin x rebin samples into n_pix x n_pix detector pixels
+ * (n_pix = n_fft / rebin), and the slopes are the pixels' centre of gravity
+ * in pixels from the subaperture centre (x along columns, then y).  A
+ * subaperture is valid when at least half of its pupil pixels are lit
+ * (pupil pixel centres at i - (D-1)/2, lit for eps R <= r <= R); invalid
+ * ones get zero slopes and pixels.
+ * ------------------------------------------------------------------------ */
+
+typedef struct pwfs_sh_s* pwfs_sh_t;
+
+typedef struct {
+  int32_t n_pupil;        /* D, a multiple of n_subap                          */
+  int32_t n_subap;        /* subapertures across; b = D / n_subap <= 32         */
+  int32_t n_fft;          /* focal samples per subaperture and axis, 2..512     */
+  int32_t rebin;          /* focal samples per detector pixel; divides n_fft    */
+  int32_t reserved;       /* must be 0                                         */
+  int32_t pad_;           /* must be 0                                         */
+  double obstruction;     /* linear central obstruction ratio, [0, 1)          */
+  double lambda_nm;       /* wavelength, > 0                                   */
+} pwfs_sh_desc;
+
+/* Host-only check: PWFS_EINVAL for a malformed description,
+ * PWFS_EUNSUPPORTED when b > 32 or the tables do not fit the LDS. */
+int pwfs_sh_validate(const pwfs_sh_desc* sh);
+int pwfs_sh_workspace_size(const pwfs_sh_desc* sh, int max_frames, size_t* bytes);
+
+/* Builds the tables (pupil, valid map, focal DFT matrix, float64 on the
+ * host) into d_workspace (caller owned, 256-byte aligned); synchronises
+ * hip_stream.  The handle holds host metadata only. */
+int pwfs_sh_plan(const pwfs_sh_desc* sh, int max_frames, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                 pwfs_sh_t* out);
+
+/* d_opd_nm [n_frames][D][D] -> d_slopes [n_frames][2][n_subap][n_subap] and,
+ * if d_pixels is not NULL, the detector pixels [n_frames][n_subap][n_subap]
+ * [n_pix][n_pix].  1 <= n_frames <= max_frames.  Asynchronous. */
+int pwfs_sh_forward(pwfs_sh_t plan, const float* d_opd_nm, int n_frames, float* d_pixels, float* d_slopes,
+                    void* hip_stream);
+int pwfs_sh_query(pwfs_sh_t plan, int32_t* n_valid, int32_t* n_pix);
+void pwfs_sh_destroy(pwfs_sh_t plan);
+
+/* ------------------------------------------------------------------------
  * Matrix-core products.  The learned-surrogate form and its data pipeline
  * (modal coefficients -> OPD, the linear interaction-matrix baseline) need
  * dense products; they run on the same split-precision MFMA tiles as the

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpwfs.so")
 
-SOURCES = ["pwfs_lib.hip", "pwfs_mfma.hip", "pwfs_mlp.hip", "pwfs_ccd.hip", "pwfs_loop.hip"]
+SOURCES = ["pwfs_lib.hip", "pwfs_mfma.hip", "pwfs_mlp.hip", "pwfs_ccd.hip", "pwfs_loop.hip", "pwfs_sh.hip"]
 
 # Packed fp32 instructions are kept out of every kernel.  Multiply-adds are
 # fused only within one source expression (-ffp-contract=on), so a kernel

@@ -1,0 +1,352 @@
+// pwfs_sh.hip -- Shack-Hartmann wavefront sensor (the paper's SH processing
+// object, Table 4; its FFT workload shapes in Table 2, e.g. 314 subapertures
+// of 56 x 56 for the SCAO SH).
+//
+// One workgroup per (frame, subaperture), everything in LDS:
+//   E[y][x]  = A exp(i 2 pi OPD / lambda) on the b x b block (float64 phase
+//              reduction, then float32 sincos);
+//   T[y][u]  = sum_x E[y][x] W[u][x]          (b x M)
+//   F[v][u]  = sum_y W[v][y] T[y][u]          (M x M, never stored)
+//   pixel P  = sum over its rebin x rebin focal samples of |F|^2, in a fixed
+//              order; then the centre of gravity of the n_pix x n_pix pixels.
+// W[u][x] = exp(-2 pi i (u - M/2 + 1/2)(x - (b-1)/2) / M) puts the focal
+// samples at half-integer frequencies (a flat wavefront's spot sits on the
+// corner of the four central samples).  A 2-D DFT of a b x b block onto
+// M x M samples as two small products costs 2 b M (b + M) real multiply-adds
+// (per complex term 4): for b << M (8 vs 56, 7 vs 240) that is less than a
+// zero-padded M-point FFT, and it needs no radix plan for M = 56 or 240.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pwfs.h"
+#include "pwfs_internal.hpp"
+
+namespace pwfs {
+namespace {
+
+constexpr int kShBlock = 256;
+constexpr double kPiSh = 3.14159265358979323846264338327950288;
+
+int sfail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  set_last_error(buf);
+  return code;
+}
+
+struct ShArgs {
+  const float* opd;        // [frames][D][D]
+  const float* amp;        // [D][D]
+  const float2* W;         // [M][b]
+  const uint8_t* valid;    // [n][n]
+  float* pixels;           // [frames][n][n][k][k] or nullptr
+  float* slopes;           // [frames][2][n][n]
+  int D, n, b, M, r, k;
+  float norm;              // 1 / (M^2 sum A^2)
+  double two_pi_over_lam;
+};
+
+// BB: the subaperture width b at compile time (its row of DFT coefficients
+// then stays in registers while a thread sweeps a row of focal samples:
+// one LDS load per complex multiply-add), 0 for a run-time b.
+template <int BB>
+__global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
+  extern __shared__ float2 sh_mem[];
+  const int tid = threadIdx.x;
+  const int sub = blockIdx.x % (p.n * p.n), f = blockIdx.x / (p.n * p.n);
+  const int si = sub / p.n, sj = sub % p.n;
+  const int b = p.b, M = p.M, r = p.r, k = p.k;
+  const int kk = k * k;
+  float* pix_out = p.pixels ? p.pixels + ((size_t)f * p.n * p.n + sub) * kk : nullptr;
+  float* sl = p.slopes + (size_t)f * 2 * p.n * p.n;
+  if (!p.valid[sub]) {   // invalid subaperture: zero slopes (and pixels)
+    if (tid == 0) {
+      sl[sub] = 0.f;
+      sl[p.n * p.n + sub] = 0.f;
+    }
+    if (pix_out)
+      for (int i = tid; i < kk; i += kShBlock) pix_out[i] = 0.f;
+    return;
+  }
+  float2* sW = sh_mem;                 // [M][b]
+  float2* sE = sW + M * b;             // [b][b]
+  float2* sT = sE + b * b;             // [b][M]
+  float* sP = (float*)(sT + b * M);    // [kk] pixel values, then [kShBlock] partials
+  float* sR = sP + kk;
+
+  for (int i = tid; i < M * b; i += kShBlock) sW[i] = p.W[i];
+  const float* opd = p.opd + (size_t)f * p.D * p.D;
+  for (int i = tid; i < b * b; i += kShBlock) {
+    const int y = i / b, x = i % b;
+    const size_t g = (size_t)(si * b + y) * p.D + sj * b + x;
+    const double ph = (double)opd[g] * p.two_pi_over_lam;
+    const double nn = rint(ph * 0.15915494309189533577);
+    const float rr = (float)fma(-nn, 6.283185307179586477, ph);
+    float sn, cs;
+    sincosf(rr, &sn, &cs);
+    const float a = p.amp[g];
+    sE[i] = make_float2(a * cs, a * sn);
+  }
+  __syncthreads();
+  // T[y][u] = sum_x E[y][x] W[u][x]
+  for (int i = tid; i < b * M; i += kShBlock) {
+    const int y = i / M, u = i % M;
+    float re = 0.f, im = 0.f;
+    for (int x = 0; x < b; ++x) {
+      const float2 e = sE[y * b + x], w = sW[u * b + x];
+      re = fmaf(e.x, w.x, fmaf(-e.y, w.y, re));
+      im = fmaf(e.x, w.y, fmaf(e.y, w.x, im));
+    }
+    sT[i] = make_float2(re, im);
+  }
+  __syncthreads();
+  // pixels: TPP threads per pixel share its r rows of focal samples (fixed order)
+  int tpp = 1;
+  while (tpp * 2 * kk <= kShBlock && tpp * 2 <= r) tpp *= 2;
+  for (int base = 0; base < kk * tpp; base += kShBlock) {
+    const int slot = base + tid;
+    const int P = slot / tpp, s = slot % tpp;
+    float acc = 0.f;
+    if (P < kk) {
+      const int pr = P / k, pc = P % k;
+      for (int vv = s; vv < r; vv += tpp) {
+        const int v = pr * r + vv;
+        if constexpr (BB > 0) {
+          float2 wv[BB];
+#pragma unroll
+          for (int y = 0; y < BB; ++y) wv[y] = sW[v * BB + y];
+          for (int uu = 0; uu < r; ++uu) {
+            const int u = pc * r + uu;
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int y = 0; y < BB; ++y) {
+              const float2 t = sT[y * M + u];
+              re = fmaf(wv[y].x, t.x, fmaf(-wv[y].y, t.y, re));
+              im = fmaf(wv[y].x, t.y, fmaf(wv[y].y, t.x, im));
+            }
+            acc = fmaf(re, re, fmaf(im, im, acc));
+          }
+        } else {
+          for (int uu = 0; uu < r; ++uu) {
+            const int u = pc * r + uu;
+            float re = 0.f, im = 0.f;
+            for (int y = 0; y < b; ++y) {
+              const float2 w = sW[v * b + y], t = sT[y * M + u];
+              re = fmaf(w.x, t.x, fmaf(-w.y, t.y, re));
+              im = fmaf(w.x, t.y, fmaf(w.y, t.x, im));
+            }
+            acc = fmaf(re, re, fmaf(im, im, acc));
+          }
+        }
+      }
+    }
+    sR[tid] = acc;
+    __syncthreads();
+    if (s == 0 && P < kk) {
+      float v = sR[tid];
+      for (int q = 1; q < tpp; ++q) v += sR[tid + q];
+      sP[P] = v * p.norm;
+    }
+    __syncthreads();
+  }
+  // centre of gravity (fixed-order tree over the pixels)
+  float t0 = 0.f, tx = 0.f, ty = 0.f;
+  const float c0 = 0.5f * (float)(k - 1);
+  for (int P = tid; P < kk; P += kShBlock) {
+    const float v = sP[P];
+    t0 += v;
+    tx = fmaf(v, (float)(P % k) - c0, tx);
+    ty = fmaf(v, (float)(P / k) - c0, ty);
+    if (pix_out) pix_out[P] = v;
+  }
+  __shared__ float red[3][kShBlock];
+  red[0][tid] = t0;
+  red[1][tid] = tx;
+  red[2][tid] = ty;
+  __syncthreads();
+  for (int w = kShBlock / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+      red[2][tid] += red[2][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const float tot = red[0][0];
+    sl[sub] = tot > 0.f ? red[1][0] / tot : 0.f;
+    sl[p.n * p.n + sub] = tot > 0.f ? red[2][0] / tot : 0.f;
+  }
+}
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+}  // namespace pwfs
+
+using namespace pwfs;
+
+struct pwfs_sh_s {
+  pwfs_sh_desc d;
+  int D, n, b, M, r, k, max_frames, n_valid;
+  float norm;
+  float* amp = nullptr;
+  float2* W = nullptr;
+  uint8_t* valid = nullptr;
+  size_t lds = 0;
+};
+
+extern "C" int pwfs_sh_validate(const pwfs_sh_desc* d) {
+  if (!d) return sfail(PWFS_EINVAL, "NULL description");
+  if (d->reserved != 0 || d->pad_ != 0) return sfail(PWFS_EINVAL, "reserved fields must be 0");
+  if (d->n_pupil < 2 || d->n_subap < 1 || d->n_pupil % d->n_subap)
+    return sfail(PWFS_EINVAL, "n_pupil must be a positive multiple of n_subap");
+  const int b = d->n_pupil / d->n_subap;
+  if (b > 32) return sfail(PWFS_EUNSUPPORTED, "subaperture of %d px (> 32) not supported", b);
+  if (d->n_fft < 2 || d->n_fft > 512) return sfail(PWFS_EINVAL, "n_fft must be in [2, 512]");
+  if (d->rebin < 1 || d->n_fft % d->rebin) return sfail(PWFS_EINVAL, "rebin must divide n_fft");
+  if (!(d->obstruction >= 0.0 && d->obstruction < 1.0)) return sfail(PWFS_EINVAL, "obstruction must be in [0, 1)");
+  if (!(d->lambda_nm > 0.0) || !std::isfinite(d->lambda_nm)) return sfail(PWFS_EINVAL, "lambda_nm must be > 0");
+  const int k = d->n_fft / d->rebin;
+  const size_t lds = sizeof(float2) * ((size_t)d->n_fft * b * 2 + (size_t)b * b) + sizeof(float) * ((size_t)k * k + kShBlock);
+  if (lds > 150 * 1024) return sfail(PWFS_EUNSUPPORTED, "subaperture tables exceed the LDS (n_fft x b too large)");
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_sh_workspace_size(const pwfs_sh_desc* d, int max_frames, size_t* bytes) {
+  int rc = pwfs_sh_validate(d);
+  if (rc) return rc;
+  if (!bytes || max_frames < 1) return sfail(PWFS_EINVAL, "bad arguments");
+  const int D = d->n_pupil, n = d->n_subap, b = D / n;
+  *bytes = a256(sizeof(float) * D * D) + a256(sizeof(float2) * d->n_fft * b) + a256((size_t)n * n);
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_sh_plan(const pwfs_sh_desc* d, int max_frames, void* ws, size_t ws_bytes, void* stream,
+                            pwfs_sh_t* out) {
+  size_t need = 0;
+  int rc = pwfs_sh_workspace_size(d, max_frames, &need);
+  if (rc) return rc;
+  if (!out) return sfail(PWFS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return sfail(PWFS_EWORKSPACE, "workspace missing, small or misaligned");
+  const int D = d->n_pupil, n = d->n_subap, b = D / n, M = d->n_fft;
+  // pupil (pixel centres at i - (D-1)/2, inside if eps R <= r <= R) and valid map (>= half lit)
+  std::vector<float> A((size_t)D * D);
+  const double R = D / 2.0, Ro = d->obstruction * R;
+  double sA2 = 0.0;
+  for (int y = 0; y < D; ++y)
+    for (int x = 0; x < D; ++x) {
+      const double cy = y - (D - 1) / 2.0, cx = x - (D - 1) / 2.0, r2 = cx * cx + cy * cy;
+      A[(size_t)y * D + x] = (r2 <= R * R && r2 >= Ro * Ro) ? 1.f : 0.f;
+      sA2 += A[(size_t)y * D + x];
+    }
+  std::vector<uint8_t> V((size_t)n * n);
+  int nv = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      int c = 0;
+      for (int y = 0; y < b; ++y)
+        for (int x = 0; x < b; ++x) c += A[(size_t)(i * b + y) * D + j * b + x] != 0.f;
+      V[(size_t)i * n + j] = 2 * c >= b * b;
+      nv += V[(size_t)i * n + j];
+    }
+  if (nv == 0) return sfail(PWFS_EINVAL, "no valid subaperture");
+  std::vector<float2> W((size_t)M * b);
+  for (int u = 0; u < M; ++u)
+    for (int x = 0; x < b; ++x) {
+      const double a = -2.0 * kPiSh * (u - M / 2.0 + 0.5) * (x - (b - 1) / 2.0) / M;
+      W[(size_t)u * b + x] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+  pwfs_sh_s* s = new (std::nothrow) pwfs_sh_s();
+  if (!s) return sfail(PWFS_EINVAL, "out of host memory");
+  s->d = *d;
+  s->D = D;
+  s->n = n;
+  s->b = b;
+  s->M = M;
+  s->r = d->rebin;
+  s->k = M / d->rebin;
+  s->max_frames = max_frames;
+  s->n_valid = nv;
+  s->norm = (float)(1.0 / ((double)M * M * sA2));
+  char* p = (char*)ws;
+  s->amp = (float*)p;
+  p += a256(sizeof(float) * D * D);
+  s->W = (float2*)p;
+  p += a256(sizeof(float2) * M * b);
+  s->valid = (uint8_t*)p;
+  s->lds = sizeof(float2) * ((size_t)M * b * 2 + (size_t)b * b) + sizeof(float) * ((size_t)s->k * s->k + kShBlock);
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(s->amp, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(s->W, W.data(), W.size() * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(s->valid, V.data(), V.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    delete s;
+    return sfail(PWFS_EHIP, "uploading the sensor tables failed");
+  }
+  static bool lds_set = false;
+  if (!lds_set) {
+    const void* fns[] = {(const void*)k_sh<0>, (const void*)k_sh<4>, (const void*)k_sh<7>, (const void*)k_sh<8>,
+                         (const void*)k_sh<16>};
+    for (const void* fn : fns)
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+        (void)hipGetLastError();
+    lds_set = true;
+  }
+  *out = s;
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_sh_forward(pwfs_sh_t s, const float* opd, int nf, float* pixels, float* slopes, void* stream) {
+  if (!s) return sfail(PWFS_EINVAL, "plan is NULL");
+  if (!opd || !slopes) return sfail(PWFS_EINVAL, "NULL device pointer");
+  if (nf < 1 || nf > s->max_frames) return sfail(PWFS_ESTATE, "n_frames %d outside [1, max_frames]", nf);
+  ShArgs a{};
+  a.opd = opd;
+  a.amp = s->amp;
+  a.W = s->W;
+  a.valid = s->valid;
+  a.pixels = pixels;
+  a.slopes = slopes;
+  a.D = s->D;
+  a.n = s->n;
+  a.b = s->b;
+  a.M = s->M;
+  a.r = s->r;
+  a.k = s->k;
+  a.norm = s->norm;
+  a.two_pi_over_lam = 2.0 * kPiSh / s->d.lambda_nm;
+  const unsigned grid = (unsigned)((long long)nf * s->n * s->n);
+  hipStream_t st = (hipStream_t)stream;
+  switch (s->b) {
+    case 4: hipLaunchKernelGGL(k_sh<4>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 7: hipLaunchKernelGGL(k_sh<7>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 8: hipLaunchKernelGGL(k_sh<8>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 16: hipLaunchKernelGGL(k_sh<16>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    default: hipLaunchKernelGGL(k_sh<0>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return sfail(PWFS_EHIP, "launch k_sh: %s", hipGetErrorString(e));
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_sh_query(pwfs_sh_t s, int32_t* n_valid, int32_t* n_pix) {
+  if (!s || !n_valid || !n_pix) return sfail(PWFS_EINVAL, "NULL argument");
+  *n_valid = s->n_valid;
+  *n_pix = s->k;
+  return PWFS_OK;
+}
+
+extern "C" void pwfs_sh_destroy(pwfs_sh_t s) { delete s; }

@@ -80,6 +80,12 @@ class CCcdDesc(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class CShDesc(ctypes.Structure):
+    _fields_ = [("n_pupil", ctypes.c_int32), ("n_subap", ctypes.c_int32), ("n_fft", ctypes.c_int32),
+                ("rebin", ctypes.c_int32), ("reserved", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("obstruction", ctypes.c_double), ("lambda_nm", ctypes.c_double)]
+
+
 class CLayer(ctypes.Structure):
     _fields_ = [("weight", ctypes.c_double), ("origin_x", ctypes.c_double), ("origin_y", ctypes.c_double),
                 ("vel_x", ctypes.c_double), ("vel_y", ctypes.c_double)]
@@ -131,6 +137,13 @@ def lib() -> ctypes.CDLL:
     L.pwfs_layers.argtypes = [vp, i32, i32, i32, P(CLayer), i32, vp, vp, vp]
     L.pwfs_integrator.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
     L.pwfs_gemv.argtypes = [vp, ctypes.c_longlong, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, vp]
+    L.pwfs_sh_validate.argtypes = [P(CShDesc)]
+    L.pwfs_sh_workspace_size.argtypes = [P(CShDesc), i32, P(ctypes.c_size_t)]
+    L.pwfs_sh_plan.argtypes = [P(CShDesc), i32, vp, ctypes.c_size_t, vp, P(vp)]
+    L.pwfs_sh_forward.argtypes = [vp, vp, i32, vp, vp, vp]
+    L.pwfs_sh_query.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int32)]
+    L.pwfs_sh_destroy.argtypes = [vp]
+    L.pwfs_sh_destroy.restype = None
     L.pwfs_get_tuning.argtypes = [vp, P(CTuning)]
     L.pwfs_set_tuning.argtypes = [vp, P(CTuning)]
     ll = ctypes.c_longlong
@@ -152,7 +165,8 @@ def lib() -> ctypes.CDLL:
                  "pwfs_query", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
                  "pwfs_gemm_workspace_size", "pwfs_gemm", "pwfs_row_rms", "pwfs_mlp_workspace_size",
                  "pwfs_mlp_create", "pwfs_mlp_param_count", "pwfs_mlp_set_params", "pwfs_mlp_get_params",
-                 "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam", "pwfs_ccd", "pwfs_ccd_slopes", "pwfs_layers", "pwfs_integrator", "pwfs_gemv"):
+                 "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam", "pwfs_ccd", "pwfs_ccd_slopes", "pwfs_layers", "pwfs_integrator", "pwfs_gemv", "pwfs_sh_validate",
+                 "pwfs_sh_workspace_size", "pwfs_sh_plan", "pwfs_sh_forward", "pwfs_sh_query"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -462,6 +476,60 @@ def row_rms(x, out=None, stream=None):
     check(lib().pwfs_row_rms(_dev_ptr(x, "x", torch.float32), x.stride(0), rows, cols,
                              _dev_ptr(out, "out", torch.float32), _stream_ptr(stream)))
     return out
+
+
+def sh_desc(n_pupil: int, n_subap: int, n_fft: int, rebin: int, obstruction: float = 0.0,
+            lambda_nm: float = 750.0) -> CShDesc:
+    return CShDesc(int(n_pupil), int(n_subap), int(n_fft), int(rebin), 0, 0, float(obstruction), float(lambda_nm))
+
+
+class SH:
+    """A Shack-Hartmann sensor plan on the library's kernel (see pwfs_sh_* in
+    include/pwfs.h)."""
+
+    def __init__(self, desc: CShDesc, max_frames: int, device=None, stream=None):
+        import torch
+        self.desc = desc
+        self.device = torch.device(device if device is not None else "cuda")
+        self.max_frames = int(max_frames)
+        n = ctypes.c_size_t()
+        check(lib().pwfs_sh_workspace_size(ctypes.byref(desc), self.max_frames, ctypes.byref(n)))
+        self.workspace, ptr = _aligned_workspace(n.value, self.device)
+        h = ctypes.c_void_p()
+        check(lib().pwfs_sh_plan(ctypes.byref(desc), self.max_frames, ctypes.c_void_p(ptr), n.value,
+                                 _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        nv, npx = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().pwfs_sh_query(self._h, ctypes.byref(nv), ctypes.byref(npx)))
+        self.n_valid, self.n_pix = nv.value, npx.value
+        self.n = int(desc.n_subap)
+
+    def forward(self, opd, slopes=None, pixels=None, want_pixels: bool = False, stream=None):
+        """OPD [F, D, D] -> (slopes [F, 2, n, n], pixels [F, n, n, n_pix, n_pix] or None)."""
+        import torch
+        F = int(opd.shape[0])
+        D = int(self.desc.n_pupil)
+        if slopes is None:
+            slopes = torch.empty((F, 2, self.n, self.n), dtype=torch.float32, device=self.device)
+        if pixels is None and want_pixels:
+            pixels = torch.empty((F, self.n, self.n, self.n_pix, self.n_pix), dtype=torch.float32, device=self.device)
+        pp = ctypes.c_void_p(None) if pixels is None else \
+            _dev_ptr(pixels, "pixels", torch.float32, F * self.n * self.n * self.n_pix ** 2)
+        check(lib().pwfs_sh_forward(self._h, _dev_ptr(opd, "opd", torch.float32, F * D * D), F, pp,
+                                    _dev_ptr(slopes, "slopes", torch.float32, F * 2 * self.n * self.n),
+                                    _stream_ptr(stream)))
+        return slopes, pixels
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pwfs_sh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class MLP:

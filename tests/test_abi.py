@@ -100,7 +100,7 @@ def test_ctypes_structs_match_header_layout(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = {"pwfs_sensor_desc": P.CSensorDesc, "pwfs_sensor_info": P.CSensorInfo, "pwfs_tuning": P.CTuning,
-               "pwfs_ccd_desc": P.CCcdDesc, "pwfs_layer": P.CLayer}
+               "pwfs_ccd_desc": P.CCcdDesc, "pwfs_layer": P.CLayer, "pwfs_sh_desc": P.CShDesc}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pwfs.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
@@ -118,3 +118,19 @@ def test_ctypes_structs_match_header_layout(tmp_path):
         assert got[(name, "size")] == ctypes.sizeof(cls), name
         for f, _ in cls._fields_:
             assert got[(name, f)] == getattr(cls, f).offset, (name, f)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_pupil=160, n_subap=21), P.PWFS_EINVAL),        # D % n
+    (dict(n_fft=56, rebin=5), P.PWFS_EINVAL),             # rebin does not divide n_fft
+    (dict(n_pupil=660, n_subap=20), P.PWFS_EUNSUPPORTED),  # b = 33 > 32
+    (dict(n_fft=600), P.PWFS_EINVAL),
+    (dict(obstruction=1.0), P.PWFS_EINVAL),
+    (dict(lambda_nm=0.0), P.PWFS_EINVAL),
+    (dict(n_pupil=512, n_subap=16, n_fft=512, rebin=8), P.PWFS_EUNSUPPORTED),   # tables beyond the LDS
+])
+def test_sh_validate_rejects(kw, code):
+    base = dict(n_pupil=160, n_subap=20, n_fft=56, rebin=7, obstruction=0.0, lambda_nm=750.0)
+    base.update(kw)
+    assert P.lib().pwfs_sh_validate(ctypes.byref(P.sh_desc(**base))) == code
+    assert P.lib().pwfs_sh_validate(ctypes.byref(P.sh_desc(160, 20, 56, 7))) == P.PWFS_OK
