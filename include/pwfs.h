@@ -69,7 +69,11 @@ enum {
   PWFS_F_LOCAL_NORM = 4   /* normalise by per-subaperture flux, not mean    */
 };
 
-#define PWFS_MAX_LAMBDA 4
+/* Wavelengths per sensor.  A polychromatic sensor (Table 4: PolyCromPyramid)
+ * is a weighted sum of monochromatic ones; 16 samples cover a broad sensing
+ * band (e.g. the 300 nm bandwidth of the SOUL detector) finely.  Cost grows
+ * linearly with the count. */
+#define PWFS_MAX_LAMBDA 16
 
 /*
  * One sensor.  Pixel conventions: pupil pixel centres at i - (D-1)/2; the

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include "fft_device.hpp"
+#include "pwfs.h"
 #include "pwfs_geom.hpp"
 
 namespace pwfs {
@@ -52,7 +53,7 @@ struct FieldArgs {
   float2* field;           // [frames][n_lam][D][D]
   long long opd_stride;
   int D, n_lam;
-  double two_pi_over_lam[4];
+  double two_pi_over_lam[PWFS_MAX_LAMBDA];
 };
 
 struct RowArgs {
@@ -115,7 +116,7 @@ struct FftPair {
     s_tw = twiddles;
     if constexpr (PAL) tw.load(t, twiddles);
   }
-  // mask values of this lane's frequency slots (mask table in LDS)
+  // mask values of this lane's frequency slots
   __device__ __forceinline__ void set_mask(const float2* mask) {
 #pragma unroll
     for (int s = 0; s < V; ++s) m[s] = mask[freq_index<N>(t, s)];
@@ -319,13 +320,13 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
   constexpr int QM = QM_ < R0 ? QM_ : R0;
   constexpr int BL = BufLen<N>::value, NL = NB0 * QM;
 
-  // palindromic plans: twiddles and mask straight into registers, LDS only
-  // for the exchange buffers; the others keep both tables in LDS
+  // palindromic plans: twiddles straight into registers, LDS only for the
+  // exchange buffers; the others keep the twiddle table in LDS.  The mask of
+  // each wavelength goes from the table to registers as it starts.
   constexpr bool PAL = Palindromic<N>::value;
   float2* s_tw = smem;
-  float2* s_m = s_tw + (PAL ? 0 : N);                    // [n_lam][N]
-  float2* s_buf = s_m + (PAL ? 0 : p.n_lam * N);
-  float* s_part = (float*)(s_buf + G * BL);              // SPLIT: [n_lam][G][V][T]
+  float2* s_buf = s_tw + (PAL ? 0 : N);
+  float* s_part = (float*)(s_buf + G * BL);              // SPLIT: [G][V][T]
 
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
   int xc, f;
@@ -339,16 +340,13 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
   const bool live = xc < p.Nc;
   const int xcl = live ? xc : 0;
 
-  const float2* masks = p.mcol;
   FftPair<N, QM> fp;
   if constexpr (PAL) {
     fp.init(t, s_buf + g * BL, p.tw);
   } else {
     for (int i = tid; i < N; i += kBlock) s_tw[i] = p.tw[i];
-    for (int i = tid; i < p.n_lam * N; i += kBlock) s_m[i] = p.mcol[i];
     __syncthreads();
     fp.init(t, s_buf + g * BL, s_tw);
-    masks = s_m;
   }
 
   // this lane's input rows and whether they hold pupil data
@@ -371,7 +369,7 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
   const int it1 = SPLIT ? kgroup_lo(g + 1, p.n_mod, G) : p.n_mod;
   const size_t frame_base = (size_t)f * p.n_lam * p.n_a;
   for (int lam = 0; lam < p.n_lam; ++lam) {
-    fp.set_mask(masks + lam * N);
+    fp.set_mask(p.mcol + lam * N);
     const float2* rbl = p.rbuf + ((frame_base + (size_t)lam * p.n_a) * p.Nc + xcl) * p.Dp;
     const float2* ryl = p.ry + (size_t)lam * p.n_mod * p.D;
     float2 cn[NL], rn[NL];
@@ -430,22 +428,21 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
         }
       }
     }
-    if constexpr (SPLIT) {
+    if constexpr (SPLIT) {   // lane group 0 adds this wavelength's G partials in group order
 #pragma unroll
-      for (int s = 0; s < V; ++s) s_part[(((size_t)lam * G + g) * V + s) * T + t] = part[s];
+      for (int s = 0; s < V; ++s) s_part[((size_t)g * V + s) * T + t] = part[s];
+      __syncthreads();
+      if (g == 0)
+        for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+          for (int s = 0; s < V; ++s) acc[s] += s_part[((size_t)gg * V + s) * T + t];
+      __syncthreads();
     } else {
 #pragma unroll
       for (int s = 0; s < V; ++s) acc[s] += part[s];     // the last group
     }
   }
-  if constexpr (SPLIT) {
-    __syncthreads();
-    if (g != 0) return;
-    for (int lam = 0; lam < p.n_lam; ++lam)
-      for (int gg = 0; gg < G; ++gg)
-#pragma unroll
-        for (int s = 0; s < V; ++s) acc[s] += s_part[(((size_t)lam * G + gg) * V + s) * T + t];
-  }
+  if (SPLIT && g != 0) return;
   if (!live) return;
   const int X = p.full ? xc : window_coord(xc, p.D, p.win_lo, p.win_hi);
   float* out = p.out + (long long)f * p.out_stride;

@@ -73,7 +73,7 @@ int validate_one(const pwfs_sensor_desc& d, int idx) {
   if ((d.n_fft - d.n_pupil) & 1) return bad("n_fft - n_pupil must be even");
   if (d.n_subap < 1 || d.n_pupil % d.n_subap) return bad("n_pupil must be a multiple of n_subap");
   if (d.n_mod < 1 || d.n_mod > 4096) return bad("n_mod must be in [1, 4096]");
-  if (d.n_lambda < 1 || d.n_lambda > PWFS_MAX_LAMBDA) return bad("n_lambda must be in [1, 4]");
+  if (d.n_lambda < 1 || d.n_lambda > PWFS_MAX_LAMBDA) return bad("n_lambda must be in [1, 16]");
   if (!(d.diameter_m > 0.0) || !std::isfinite(d.diameter_m)) return bad("diameter_m must be > 0");
   if (!(d.obstruction >= 0.0 && d.obstruction < 1.0)) return bad("obstruction must be in [0, 1)");
   if (!(d.mod_radius_lod >= 0.0) || !std::isfinite(d.mod_radius_lod)) return bad("mod_radius_lod must be >= 0");
@@ -487,11 +487,11 @@ static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd
   ca.win_lo = g.win_lo;
   ca.win_hi = g.win_hi;
   ca.full = g.full;
-  pa.lds_cols = sizeof(float2) * ((PAL ? 0 : (size_t)N + (size_t)g.n_lam * N) + (size_t)G * BufLen<N>::value);
+  pa.lds_cols = sizeof(float2) * ((PAL ? 0 : (size_t)N) + (size_t)G * BufLen<N>::value);
   pa.grid_cols = (unsigned)(nf * ca.colblocks);
   // split column pass (one column per workgroup): its lane groups' partial sums meet in LDS
   pa.grid_cols_split = (unsigned)(nf * g.Nc);
-  pa.lds_cols_split = pa.lds_cols + sizeof(float) * (size_t)g.n_lam * G * N;
+  pa.lds_cols_split = pa.lds_cols + sizeof(float) * (size_t)G * N;
   return pa;
 }
 

@@ -115,7 +115,7 @@ struct SplitFieldArgs {
   uint16_t* out;          // plane 0 [n_lam][F][D][Kp], plane 1 follows at +plane
   long long opd_stride, plane;
   int D, Kp, F, n_lam, planes;
-  double two_pi_over_lam[4];
+  double two_pi_over_lam[PWFS_MAX_LAMBDA];
 };
 
 template <bool F16>
@@ -218,7 +218,7 @@ struct G2Args {
   float* out;             // first frame of the pass, frame stride out_stride
   long long a_plane, t_plane, out_stride;
   int M, Nc, N, D, Kp, n_a, n_lam, n_mod, mtiles, ntiles, win_lo, win_hi, full;
-  float scale[4];
+  float scale[PWFS_MAX_LAMBDA];
 };
 
 template <int NPL, bool F16>

@@ -8,7 +8,7 @@ import os
 import pytest
 
 from paper_2602_06688_amd import pwfs as P
-from workloads import tiny_sensor, workload
+from workloads import band_sampling, tiny_sensor, workload
 
 
 def test_library_exports_header_symbols():
@@ -40,6 +40,8 @@ def _bad(**kw):
     (dict(n_mod=0), P.PWFS_EINVAL),
     (dict(lambdas_nm=(0.0,)), P.PWFS_EINVAL),
     (dict(lambdas_nm=(600.0, 900.0), lambda_weights=(0.5, 0.6)), P.PWFS_EINVAL),
+    (dict(lambdas_nm=band_sampling(750.0, 300.0, 17)[0],                    # > 16 wavelengths
+          lambda_weights=band_sampling(750.0, 300.0, 17)[1]), P.PWFS_EINVAL),
     (dict(obstruction=1.0), P.PWFS_EINVAL),
     (dict(mod_radius_lod=-1.0), P.PWFS_EINVAL),
     (dict(n_fft=160, pupil_sep_px=64.0), P.PWFS_EUNSUPPORTED),   # no radix plan
@@ -59,7 +61,10 @@ def test_validate_accepts_edge_sensors():
     ok = [tiny_sensor(n_pupil=32, n_fft=64, n_subap=4, pupil_sep_px=32.0),
           tiny_sensor(n_pupil=40, n_fft=128, n_subap=5, pupil_sep_px=48.0, n_mod=1, mod_radius_lod=0.0),
           tiny_sensor(n_pupil=64, n_fft=128, n_subap=16, pupil_sep_px=64.0, n_mod=5,
-                      lambdas_nm=(600.0, 750.0, 900.0, 1000.0), lambda_weights=(0.1, 0.2, 0.3, 0.4))]
+                      lambdas_nm=(600.0, 750.0, 900.0, 1000.0), lambda_weights=(0.1, 0.2, 0.3, 0.4)),
+          tiny_sensor(n_pupil=64, n_fft=128, n_subap=16, pupil_sep_px=64.0, n_mod=5,
+                      lambdas_nm=band_sampling(750.0, 300.0, 16)[0],
+                      lambda_weights=band_sampling(750.0, 300.0, 16)[1])]
     for s in ok:
         assert P.validate([s]) == P.PWFS_OK, P.lib().pwfs_last_error()
 

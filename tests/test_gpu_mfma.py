@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import pwfs as O
-from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16X3, tiny_sensor, workload, workload_opd
+from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16X3, band_sampling, tiny_sensor, workload, workload_opd
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -58,7 +58,11 @@ def test_edge_sensors_mfma(prec):
              tiny_sensor(n_pupil=48, n_fft=128, n_subap=12, pupil_sep_px=56.0, n_mod=8, precision=prec,
                          lambdas_nm=(600.0, 750.0, 900.0), lambda_weights=(0.2, 0.3, 0.5), flags=3),
              tiny_sensor(n_pupil=80, n_fft=256, n_subap=20, pupil_sep_px=96.0, n_mod=16, obstruction=0.28,
-                         mod_radius_lod=2.0, precision=prec)]
+                         mod_radius_lod=2.0, precision=prec),
+             # a 300 nm band in 16 samples
+             tiny_sensor(n_pupil=48, n_fft=128, n_subap=12, pupil_sep_px=56.0, n_mod=8, precision=prec,
+                         lambdas_nm=band_sampling(750.0, 300.0, 16)[0],
+                         lambda_weights=band_sampling(750.0, 300.0, 16)[1])]
     for s in cases:
         opd = von_karman_opd(3, s.n_pupil, 8.0, 0.5, 25.0, seed=7)
         print(f"[gpu] mfma {NAMES[prec]} D={s.n_pupil} N={s.n_fft} flags={s.flags}", flush=True)

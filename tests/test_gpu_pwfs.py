@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import pwfs as O
-from workloads import tiny_sensor, workload, workload_opd
+from workloads import band_sampling, tiny_sensor, workload, workload_opd
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -108,6 +108,14 @@ EDGE = {
                                mod_radius_lod=2.0, src_rings=1, src_radius_lod=1.5),
     "extended_r2_unmod": tiny_sensor(n_pupil=48, n_fft=128, n_subap=12, pupil_sep_px=56.0, n_mod=1,
                                      mod_radius_lod=0.0, src_rings=2, src_radius_lod=2.0, obstruction=0.2),
+    # finely sampled bands: 16 wavelengths over 300 nm (palindromic plan, full
+    # plane) and 7 on the radix-3 plan
+    "poly16_full": tiny_sensor(n_pupil=64, n_fft=128, n_subap=16, pupil_sep_px=64.0, n_mod=8,
+                               mod_radius_lod=2.0, lambdas_nm=band_sampling(750.0, 300.0, 16)[0],
+                               lambda_weights=band_sampling(750.0, 300.0, 16)[1], flags=3),
+    "poly7_N384": tiny_sensor(n_pupil=120, n_fft=384, n_subap=30, pupil_sep_px=144.0, n_mod=4,
+                              obstruction=0.28, mod_radius_lod=3.0, lambdas_nm=band_sampling(750.0, 300.0, 7)[0],
+                              lambda_weights=band_sampling(750.0, 300.0, 7)[1]),
     "extended_poly_N256": tiny_sensor(n_pupil=80, n_fft=256, n_subap=20, pupil_sep_px=96.0, n_mod=6,
                                       mod_radius_lod=2.0, src_rings=1, src_radius_lod=1.0,
                                       lambdas_nm=(650.0, 850.0), lambda_weights=(0.5, 0.5), flags=3),
@@ -246,3 +254,23 @@ def test_extended_source_persistent_equals_launches():
     I1, S1, _ = plan.step(x)
     torch.cuda.synchronize()
     assert torch.equal(I0, I1) and torch.equal(S0, S1)
+
+
+def test_polychromatic_batched_path_and_persistent():
+    """48 frames of a 10-wavelength sensor: enough column workgroups for the
+    batched column pass (the edge cases above run the split pass); the
+    persistent launch gives the same bits."""
+    P = _P()
+    lams, ws = band_sampling(750.0, 300.0, 10)
+    s = tiny_sensor(n_pupil=80, n_fft=256, n_subap=20, pupil_sep_px=96.0, n_mod=8, mod_radius_lod=2.0,
+                    obstruction=0.2, lambdas_nm=lams, lambda_weights=ws)
+    from workloads import von_karman_opd
+    opd = von_karman_opd(48, s.n_pupil, 8.0, 0.5, 25.0, seed=29)
+    plan, I0, S0 = _check(s, opd, label="10 wavelengths, 48 frames")
+    x = torch.from_numpy(np.ascontiguousarray(opd, dtype=np.float32)).cuda()
+    _say("[gpu] 10 wavelengths: launches vs persistent")
+    plan.set_tuning(mode=P.MODE_PERSISTENT)
+    I1, S1, _ = plan.step(x)
+    torch.cuda.synchronize()
+    assert np.array_equal(I0, I1.cpu().numpy().astype(np.float64))
+    assert np.array_equal(S0, S1.cpu().numpy().astype(np.float64))

@@ -168,6 +168,15 @@ def workload(name: str) -> Workload:
     return WORKLOADS[name]()
 
 
+def band_sampling(center_nm: float, width_nm: float, n: int):
+    """n wavelengths sampling a flat band by the midpoint rule: centres of n
+    equal sub-bands, equal weights (a polychromatic sensor, Table 4's
+    PolyCromPyramid; the weighting of the band is a reading, the paper gives
+    none)."""
+    lams = tuple(center_nm - width_nm / 2.0 + (i + 0.5) * width_nm / n for i in range(n))
+    return lams, tuple([1.0 / n] * n)
+
+
 def tiny_sensor(**kw) -> SensorDesc:
     """A sensor small enough for brute-force checks: D=8, N=16, 4 points, 2x2."""
     base = dict(n_pupil=8, n_fft=16, n_subap=2, n_mod=4, pupil_sep_px=8.0,
