@@ -223,6 +223,60 @@ def detector_form(P, torch, dev, stream, x, plan, I, s, steps: int):
                          "avg_launch_ms": round(ccd_ms / max(1, ccd_n), 4), "traffic": None}}
 
 
+def soul_form(P, torch, dev, stream, steps: int, frames: int = 1000, distinct: int = 200):
+    """The SOUL pyramid of Appendix B as one chain: 220 px pupil (8.22 m),
+    40 x 40 subapertures of 5.5 px, pupils 48 subapertures apart, 3 lambda/D
+    modulation at 750 nm sampled by 24 points (Table 2: 24 transforms per
+    step) on a 768 grid (the paper pads to 660); a 120 x 120 detector of 5.5
+    transform pixels per pixel with photon and readout noise (magnitude 8,
+    300 nm, 0.588 ms, QE 0.32, 0.4 e-); slopes on detector pixels.
+    frames/s of the chain over `frames` frames (`distinct` screens at 0.8
+    arcsec seeing, repeated)."""
+    import numpy as np
+    from fractions import Fraction
+    from workloads import FLAG_REF_SLOPES, tiny_sensor, von_karman_opd
+    from workloads.configs import photo_electrons
+    s = tiny_sensor(n_pupil=220, n_fft=768, n_subap=40, pupil_sep_px=264.0, n_mod=24, mod_radius_lod=3.0,
+                    diameter_m=8.222, flags=FLAG_REF_SLOPES)
+    scr = von_karman_opd(distinct, 220, 8.222, 0.126, 40.0, seed=70, grid=512)
+    x = torch.from_numpy(np.ascontiguousarray(np.tile(scr, (frames // distinct, 1, 1)))).to(dev)
+    plan = P.Plan([s], max_frames=frames, device=dev)
+    el = photo_electrons(8.0, 8.222, 0.0, 300.0, 0.000588, 0.32)
+    d = P.ccd_desc(120, Fraction(11, 2), el, P.CCD_PHOTON | P.CCD_READOUT, 0.4, seed=12)
+    I = plan.forward(x, stream=stream)
+    pix = torch.empty((frames, 120, 120), dtype=torch.float32, device=dev)
+    sl = torch.empty((frames, 2, 40, 40), dtype=torch.float32, device=dev)
+    fl = torch.zeros(frames, dtype=torch.float32, device=dev)
+
+    def one(k):
+        plan.forward(x, I, stream=stream)
+        plan.ccd(I, d, frame0=k * frames, out=pix, stream=stream)
+        plan.ccd_slopes(pix, d, out=sl, flux=fl, stream=stream)
+
+    one(0)
+    torch.cuda.synchronize(dev)
+    plan.profile(4096)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        one(k + 1)
+    torch.cuda.synchronize(dev)
+    dt = (time.perf_counter() - t0) / steps
+    kms = {k: round(plan.profile_read(k)[0] / steps, 3) for k in ("field", "rows", "cols", "ccd", "slopes")}
+    plan.profile(0)
+    assert bool(torch.isfinite(sl).all())
+    fs = frames / dt
+    fl_frame = nominal_flops(s)["path"]
+    a = fl_frame * fs / 1e12
+    print(f"# SOUL chain: {fs:.0f} frames/s ({a:.1f} TFLOP/s nominal), ms per step {kms}", file=sys.stderr,
+          flush=True)
+    return {"value": round(fs, 1), "unit": "frames/s", "ms_per_step": round(dt * 1e3, 4),
+            "workload": "SOUL pyramid: 220 px, 40x40 subap (5.5 px), 24 points at 3 lambda/D, N=768; "
+                        "120 px detector at 11/2 transform px per px, photon + readout noise; detector slopes",
+            "frames_per_step": frames, "electrons_per_frame": round(el, 1), "kernel_ms_per_step": kms,
+            "roofline_path": {"bound": "alu", "achieved": round(a, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(a / FP32_PEAK_TFLOPS, 4), "flops_per_frame": fl_frame}}
+
+
 def loop_form(torch, dev, steps: int = 2000):
     """Closed AO loop of the SOUL configuration around the 160 px sensor
     (500 KL modes, four frozen-flow layers, the listing's integrator and
@@ -442,6 +496,7 @@ def main() -> int:
     ap.add_argument("--no-sh", action="store_true", help="skip the Shack-Hartmann sensor")
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous six-sensor batch")
     ap.add_argument("--no-poly", action="store_true", help="skip the 16-wavelength sensor")
+    ap.add_argument("--no-soul", action="store_true", help="skip the SOUL pyramid + detector chain")
     ap.add_argument("--surrogate-train", type=int, default=200_000)
     ap.add_argument("--surrogate-epochs", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -540,6 +595,8 @@ def main() -> int:
         forms["surrogate"] = surrogate_form(torch, dev, args.surrogate_train, 20_000, args.surrogate_epochs, 5)
     if not args.no_sh:
         forms["shack_hartmann"] = sh_form(P, torch, dev, x, max(2, args.steps // 2))
+    if not args.no_soul:
+        forms["soul_chain"] = soul_form(P, torch, dev, stream, max(2, args.steps // 4))
     if not args.no_poly:
         forms["polychromatic16"] = poly_form(P, torch, dev, x, s, max(2, args.steps // 4))
     if not args.no_loop:

@@ -84,7 +84,12 @@ enum {
 typedef struct {
   int32_t n_pupil;        /* D, even, >= 4                                     */
   int32_t n_fft;          /* N: 128, 256, 384, 512 or 768                      */
-  int32_t n_subap;        /* subapertures across; D % n_subap == 0, <= 64       */
+  int32_t n_subap;        /* subapertures across, 1 .. min(D, 64); D / n_subap
+                             need not be whole (SOUL: 220 / 40 = 5.5): pixels
+                             cut by subaperture edges then count with their
+                             area fraction, in binning and in the valid map
+                             (valid: at least half the subaperture's area on
+                             lit pupil pixels)                                 */
   int32_t n_mod;          /* modulation points, >= 1                           */
   int32_t n_lambda;       /* 1 .. PWFS_MAX_LAMBDA                              */
   int32_t precision;      /* pwfs_precision                                    */
@@ -113,7 +118,7 @@ typedef struct {
 
 /*
  * Checks sensor descriptions on the host; touches no device.  Returns
- * PWFS_EINVAL for a malformed description (N < D, odd N - D, D % n_subap,
+ * PWFS_EINVAL for a malformed description (N < D, odd N - D, n_subap > D,
  * pupil images outside the grid, n_mod <= 0, wavelength <= 0, weights not
  * summing to 1, ...) and PWFS_EUNSUPPORTED for a valid one whose FFT size
  * has no radix plan here.
@@ -206,9 +211,16 @@ int pwfs_profile_read(pwfs_plan_t plan, int kernel, double* total_ms, int* launc
  * noise switches, readout level; the source flux, integration time,
  * bandwidth and quantum efficiency enter through `electrons`.
  *
+ * Detector pixels are r = rebin / rebin_den transform pixels wide (SOUL
+ * reads 660 transform pixels onto a 120 px detector: r = 11/2); the
+ * detector covers the central (n_det r) square of the plane, which must be
+ * whole transform pixels.
+ *
  * Per detector pixel p and frame f (global frame index frame0 + f):
- *   lam = electrons * sum of the rebin x rebin block of the intensity plane
- *         over its central rebin*n_det square (float64, row-major order);
+ *   lam = electrons * sum over the transform pixels the detector pixel
+ *         overlaps, in row-major order and float64, of w * I with
+ *         w = (overlap_y * overlap_x) / rebin_den^2, overlaps in units of
+ *         1/rebin_den pixel (an integer rebin gives w = 1: block sums);
  *         without PWFS_F_FULL_PLANE only pixels inside the four pupil images
  *         count (the rest of the plane is not written by pwfs_forward);
  *   photon noise: n ~ Poisson(lam) (else the value is lam);
@@ -223,9 +235,9 @@ enum { PWFS_CCD_PHOTON = 1, PWFS_CCD_READOUT = 2, PWFS_CCD_EXCESS = 4 };
 
 typedef struct {
   int32_t n_det;      /* detector pixels per side */
-  int32_t rebin;      /* transform pixels per detector pixel, per side */
+  int32_t rebin;      /* transform pixels per detector pixel, per side: rebin / rebin_den */
   uint32_t flags;     /* PWFS_CCD_* (excess noise needs photon noise) */
-  int32_t reserved;   /* must be 0 */
+  int32_t rebin_den;  /* 0 or 1: whole transform pixels; else 2 .. 64, rebin >= rebin_den */
   double electrons;   /* expected photo-electrons per frame over the whole normalised plane, >= 0 */
   double readout_e;   /* readout noise RMS [electrons / pixel / frame], >= 0 */
   uint64_t seed;      /* key of the random draws */
@@ -235,7 +247,7 @@ typedef struct {
  * Detector frames of one sensor: d_intensity as written by pwfs_forward
  * ([n_frames][intensity_stride], the sensor's plane at its intensity
  * offset) -> d_pixels [n_frames][n_det][n_det] float32 electrons.
- * Requires rebin * n_det <= N with N - rebin * n_det even; without
+ * Requires n_det r whole and <= N with N - n_det r even; without
  * PWFS_F_FULL_PLANE also that the pupil images fall on whole detector
  * pixels.  PWFS_EINVAL for a bad description, PWFS_ESTATE for n_frames
  * outside [1, max_frames].  Asynchronous on hip_stream.
@@ -245,9 +257,10 @@ int pwfs_ccd(pwfs_plan_t plan, int sensor, const pwfs_ccd_desc* ccd, const float
 
 /*
  * Slope stage on detector frames: the sensor's slope definition applied to
- * the four pupil images on the detector (D / rebin pixels each, binned
- * D / (rebin * n_subap) per subaperture), minus the sensor's reference
- * slopes when PWFS_F_REF_SLOPES is set.  d_slopes [n_frames][2][n][n],
+ * the four pupil images on the detector (D / r pixels each, binned
+ * D / (r n_subap) per subaperture), minus the sensor's reference slopes when
+ * PWFS_F_REF_SLOPES is set (the subapertures then cover the same areas of
+ * the plane as the sensor's own, so the reference carries over).  d_slopes [n_frames][2][n][n],
  * d_flux [n_frames] or NULL.  Requires the pupil images to fall on whole
  * detector pixels tiled by the subapertures (PWFS_EINVAL otherwise).
  * Asynchronous on hip_stream.

@@ -13,7 +13,10 @@ does not write the model down, so the readings here are the textbook ones:
   1. expected photo-electrons per detector pixel: lam = n_e * (sum of the
      rebin x rebin block of the normalised intensity), the block sum taken
      in float64 in row-major order over the central rebin * n_det square of
-     the N x N plane;
+     the N x N plane.  The detector pitch need not be a whole number of
+     transform pixels (the SOUL sensor reads 660 transform pixels onto 120
+     detector pixels, Appendix B: 5.5 each): a transform pixel cut by a
+     detector pixel edge then counts with its area fraction;
   2. photon noise: a Poisson draw of mean lam;
   3. excess noise (electron-multiplying register at high gain): the output
      of n electrons is Gamma(n, 1) distributed (mean n, variance n);
@@ -34,6 +37,7 @@ method (ACM TOMS 2000).
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 
 import numpy as np
 
@@ -188,21 +192,60 @@ def gamma_mt(n: np.ndarray, pix: np.ndarray, frame: int, key) -> np.ndarray:
 
 # ------------------------------------------------------------- detector ---
 
-def expected_electrons(I: np.ndarray, n_det: int, rebin: int, electrons: float) -> np.ndarray:
-    """lam [n_det][n_det]: electrons * float64 row-major block sums of the
-    float32 intensity I [N][N] over its central rebin * n_det square."""
+def _ratio(rebin) -> tuple:
+    r = Fraction(rebin)
+    return r.numerator, r.denominator
+
+
+def pixel_spans(n_det: int, num: int, den: int):
+    """Per detector pixel p along one axis: the transform pixels y it covers
+    (relative to the detector square) and their overlap lengths in units of
+    1/den pixel.  Pixel p spans [p num / den, (p + 1) num / den)."""
+    out = []
+    for p in range(n_det):
+        lo, hi = p * num, (p + 1) * num                 # in 1/den pixel
+        ys = list(range(lo // den, -(-hi // den)))
+        ov = [min((y + 1) * den, hi) - max(y * den, lo) for y in ys]
+        out.append((ys, ov))
+    return out
+
+
+def expected_electrons(I: np.ndarray, n_det: int, rebin, electrons: float) -> np.ndarray:
+    """lam [n_det][n_det] over the central (n_det rebin) square of the float32
+    intensity I [N][N], rebin = transform pixels per detector pixel (an
+    integer or a fraction num/den; the square must be whole pixels).  Each
+    detector pixel sums, in float64 and row-major order over the transform
+    pixels it overlaps, w * I with w = (overlap_y overlap_x) / den^2 (one
+    division of integers: the area fraction), then multiplies by electrons.
+    For an integer rebin every w is 1 and this is the plain block sum."""
+    num, den = _ratio(rebin)
     N = I.shape[-1]
-    w = rebin * n_det
+    if (n_det * num) % den:
+        raise ValueError("the detector square must be whole transform pixels")
+    w = n_det * num // den
     off = (N - w) // 2
-    win = np.asarray(I[off:off + w, off:off + w], np.float32)
+    win = np.asarray(I[off:off + w, off:off + w], np.float32).astype(np.float64)
+    spans = pixel_spans(n_det, num, den)
+    K = max(len(ys) for ys, _ in spans)
+    # per axis: index, overlap and presence of the k-th covered pixel of each detector pixel
+    idx = np.zeros((n_det, K), np.int64)
+    ovl = np.zeros((n_det, K), np.int64)
+    has = np.zeros((n_det, K), bool)
+    for p, (ys, ov) in enumerate(spans):
+        idx[p, :len(ys)] = ys
+        ovl[p, :len(ys)] = ov
+        has[p, :len(ys)] = True
     s = np.zeros((n_det, n_det), np.float64)
-    for i in range(rebin):
-        for j in range(rebin):
-            s = s + win[i::rebin, j::rebin].astype(np.float64)
+    dd = float(den * den)
+    for a in range(K):                       # row-major over the covered pixels
+        for b in range(K):
+            wgt = (ovl[:, a, None] * ovl[None, :, b]).astype(np.float64) / dd
+            val = wgt * win[idx[:, a, None], idx[None, :, b]]
+            s = np.where(has[:, a, None] & has[None, :, b], s + val, s)
     return s * float(electrons)
 
 
-def detector_frame(I: np.ndarray, n_det: int, rebin: int, electrons: float, flags: int, readout_e: float,
+def detector_frame(I: np.ndarray, n_det: int, rebin, electrons: float, flags: int, readout_e: float,
                    seed: int, frame: int) -> np.ndarray:
     """Detector pixels [n_det][n_det] (electrons, float64) of one frame of
     normalised intensity I [N][N] (float32); `frame` is the global frame
@@ -225,7 +268,7 @@ def detector_frame(I: np.ndarray, n_det: int, rebin: int, electrons: float, flag
     return val.reshape(n_det, n_det)
 
 
-def detector(I: np.ndarray, n_det: int, rebin: int, electrons: float, flags: int, readout_e: float, seed: int,
+def detector(I: np.ndarray, n_det: int, rebin, electrons: float, flags: int, readout_e: float, seed: int,
              frame0: int = 0) -> np.ndarray:
     """detector_frame over frames I [F][N][N]; frame f uses index frame0 + f."""
     return np.stack([detector_frame(I[f], n_det, rebin, electrons, flags, readout_e, seed, frame0 + f)
@@ -234,26 +277,30 @@ def detector(I: np.ndarray, n_det: int, rebin: int, electrons: float, flags: int
 
 # ---------------------------------------------------------- detector slopes --
 
-def detector_geometry(s, n_det: int, rebin: int):
+def detector_geometry(s, n_det: int, rebin):
     """(image origins in detector pixels, image size, detector pixels per
-    subaperture) for sensor s read out on an n_det detector of rebin x rebin
-    FFT pixels; raises if the pupil images do not fall on whole detector
-    pixels."""
+    subaperture) for sensor s read out on an n_det detector whose pixels are
+    rebin (integer or fraction) transform pixels wide; raises if the pupil
+    images do not fall on whole detector pixels tiled by the subapertures."""
     from . import pwfs as O
+    num, den = _ratio(rebin)
     N, D = s.n_fft, s.n_pupil
-    off2 = N - rebin * n_det
-    if off2 < 0 or off2 % 2 or D % rebin or (D // rebin) % s.n_subap:
+    if (n_det * num) % den or (D * den) % num:
+        raise ValueError("detector does not tile the pupil images")
+    off2 = N - n_det * num // den
+    img = D * den // num
+    if off2 < 0 or off2 % 2 or img % s.n_subap:
         raise ValueError("detector does not tile the pupil images")
     off = off2 // 2
     org = []
     for r0, c0 in O.image_origins(s):
-        if (r0 - off) % rebin or (c0 - off) % rebin or r0 < off or c0 < off:
+        if ((r0 - off) * den) % num or ((c0 - off) * den) % num or r0 < off or c0 < off:
             raise ValueError("pupil image not aligned with detector pixels")
-        org.append(((r0 - off) // rebin, (c0 - off) // rebin))
-    return org, D // rebin, D // rebin // s.n_subap
+        org.append(((r0 - off) * den // num, (c0 - off) * den // num))
+    return org, img, img // s.n_subap
 
 
-def detector_quadrants(P: np.ndarray, s, n_det: int, rebin: int) -> np.ndarray:
+def detector_quadrants(P: np.ndarray, s, n_det: int, rebin) -> np.ndarray:
     """Q [F][4][n][n]: the four pupil images of detector frames P [F][n_det][n_det]
     summed over b_det x b_det blocks."""
     org, Dd, b = detector_geometry(s, n_det, rebin)
@@ -265,7 +312,7 @@ def detector_quadrants(P: np.ndarray, s, n_det: int, rebin: int) -> np.ndarray:
     return Q
 
 
-def detector_slopes(P: np.ndarray, s, n_det: int, rebin: int):
+def detector_slopes(P: np.ndarray, s, n_det: int, rebin):
     """(slopes [F][2][n][n], flux [F]) of detector frames: the sensor's slope
     definition on detector pixels, minus the raw slopes of the noise-free
     detector frame of a flat wavefront (when reference subtraction is on)."""

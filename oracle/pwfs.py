@@ -226,29 +226,47 @@ def forward_frame_separable(opd_nm: np.ndarray, s) -> np.ndarray:
 
 # ------------------------------------------------------ binning and slopes --
 
+def subaperture_overlaps(D: int, n: int) -> np.ndarray:
+    """W [n][D]: the length of pixel y's overlap with subaperture i along one
+    axis, in units of 1/n pixel (integers).  Subaperture i spans pixels
+    [i D / n, (i + 1) D / n), which need not be whole pixels: a pixel cut by a
+    subaperture edge is shared in proportion to area."""
+    W = np.zeros((n, D))
+    for i in range(n):
+        for y in range(D):
+            W[i, y] = max(0, min((y + 1) * n, (i + 1) * D) - max(y * n, i * D))
+    return W
+
+
 def bin_images(I: np.ndarray, s) -> np.ndarray:
-    """Sum each of the four D x D pupil images over b x b blocks:
-    Q[f][q][i][j], b = D / n_subap."""
+    """Sum each of the four D x D pupil images over the subapertures:
+    Q[f][q][i][j].  With b = D / n_subap whole, plain b x b block sums;
+    otherwise pixels cut by subaperture edges count with their area
+    fraction (Q = W I W^T, W the overlaps / n)."""
     I = np.asarray(I, dtype=np.float64)
     if I.ndim == 2:
         I = I[None]
     D, n = s.n_pupil, s.n_subap
-    b = D // n
     Q = np.zeros((I.shape[0], 4, n, n), np.float64)
+    W = subaperture_overlaps(D, n) / n
     for q, (r0, c0) in enumerate(image_origins(s)):
         win = I[:, r0:r0 + D, c0:c0 + D]
-        Q[:, q] = win.reshape(I.shape[0], n, b, n, b).sum(axis=(2, 4))
+        if D % n == 0:
+            b = D // n
+            Q[:, q] = win.reshape(I.shape[0], n, b, n, b).sum(axis=(2, 4))
+        else:
+            Q[:, q] = W @ win @ W.T
     return Q
 
 
 def valid_subapertures(s) -> np.ndarray:
     """Geometric valid map: a subaperture is valid when at least half of its
-    b x b pixels are inside the pupil stop."""
+    area lies on pixels inside the pupil stop (decided exactly: areas in
+    units of 1/n_subap^2 pixel are integers, the subaperture's is D^2)."""
     A = pupil_amplitude(s.n_pupil, s.obstruction)
-    n = s.n_subap
-    b = s.n_pupil // n
-    frac = A.reshape(n, b, n, b).sum(axis=(1, 3)) / (b * b)
-    return frac >= 0.5
+    W = subaperture_overlaps(s.n_pupil, s.n_subap)
+    lit = W @ A @ W.T
+    return 2.0 * lit >= float(s.n_pupil) ** 2
 
 
 def raw_slopes(Q: np.ndarray, valid: np.ndarray, local_norm: bool = False):

@@ -135,7 +135,8 @@ struct CcdArgs {
   const float* in;          // sensor's intensity plane of the first frame
   long long in_stride;      // floats between frames
   float* out;               // [frames][n_det][n_det]
-  int N, n_det, rebin, off; // plane size, detector size, pixels per detector pixel, window offset
+  int N, n_det, off;        // plane size, detector size, offset of the detector square
+  int num, den;             // detector pitch num / den transform pixels
   int windows;              // count only detector pixels inside the four pupil images
   int img_r[2], img_c[2];   // image starts in detector pixels (two rows x two columns)
   int img;                  // image size in detector pixels
@@ -160,9 +161,19 @@ __global__ __launch_bounds__(256) void k_ccd(CcdArgs p) {
   }
   double s = 0.0;
   if (inside) {
-    const float* I = p.in + (long long)f * p.in_stride + (long long)(p.off + r * p.rebin) * p.N + p.off + c * p.rebin;
-    for (int i = 0; i < p.rebin; ++i)
-      for (int j = 0; j < p.rebin; ++j) s = s + (double)I[(long long)i * p.N + j];
+    // the transform pixels this detector pixel overlaps, row-major; overlaps
+    // in units of 1/den pixel, weight = area fraction (1 when den = 1)
+    const float* I = p.in + (long long)f * p.in_stride + (long long)p.off * p.N + p.off;
+    const int ylo = r * p.num, yhi = ylo + p.num, xlo = c * p.num, xhi = xlo + p.num;
+    const double dd = (double)p.den * (double)p.den;
+    for (int y = ylo / p.den; y * p.den < yhi; ++y) {
+      const int oy = min((y + 1) * p.den, yhi) - max(y * p.den, ylo);
+      for (int x = xlo / p.den; x * p.den < xhi; ++x) {
+        const int ox = min((x + 1) * p.den, xhi) - max(x * p.den, xlo);
+        const double w = (double)(oy * ox) / dd;
+        s = s + w * (double)I[(long long)y * p.N + x];
+      }
+    }
   }
   const double lam = s * p.electrons;
   const uint64_t frame = (uint64_t)(p.frame0 + f);
@@ -198,32 +209,40 @@ int cfail(int code, const char* fmt, ...) {
 // detector geometry of sensor sp; `aligned` also requires the pupil images
 // to fall on whole detector pixels and to be tiled by the subapertures
 struct DetGeom {
-  int off, img, b, img_r[2], img_c[2];
+  int off, num, den, img, b, img_r[2], img_c[2];
 };
 
 int det_geometry(const SensorPlan& sp, const pwfs_ccd_desc* d, bool aligned, DetGeom& out) {
   const Geometry& g = sp.g;
-  if (d->n_det < 1 || d->rebin < 1 || d->reserved != 0) return cfail(PWFS_EINVAL, "bad detector size or rebin");
+  if (d->n_det < 1 || d->rebin < 1 || d->rebin_den < 0 || d->rebin_den > 64)
+    return cfail(PWFS_EINVAL, "bad detector size or rebin");
+  const int num = d->rebin, den = d->rebin_den ? d->rebin_den : 1;
+  if (num < den) return cfail(PWFS_EINVAL, "detector pixels smaller than transform pixels (rebin < rebin_den)");
+  out.num = num;
+  out.den = den;
   if (d->flags & ~(uint32_t)(PWFS_CCD_PHOTON | PWFS_CCD_READOUT | PWFS_CCD_EXCESS))
     return cfail(PWFS_EINVAL, "unknown detector flags");
   if ((d->flags & PWFS_CCD_EXCESS) && !(d->flags & PWFS_CCD_PHOTON))
     return cfail(PWFS_EINVAL, "excess noise needs photon noise");
   if (!(d->electrons >= 0.0) || !(d->readout_e >= 0.0) || !std::isfinite(d->electrons))
     return cfail(PWFS_EINVAL, "electrons and readout noise must be finite and >= 0");
-  const long long w = (long long)d->rebin * d->n_det;
-  if (w > g.N || (g.N - w) % 2) return cfail(PWFS_EINVAL, "rebin * n_det must be <= N with N - rebin * n_det even");
+  const long long wn = (long long)num * d->n_det;    // detector square, in 1/den pixel
+  if (wn % den) return cfail(PWFS_EINVAL, "the detector square (n_det * rebin / rebin_den) must be whole pixels");
+  const long long w = wn / den;
+  if (w > g.N || (g.N - w) % 2)
+    return cfail(PWFS_EINVAL, "the detector square must be <= N pixels with N minus it even");
   out.off = (int)((g.N - w) / 2);
   if (!aligned && g.full) return PWFS_OK;
-  if (g.D % d->rebin || (g.D / d->rebin) % g.n)
+  if (((long long)g.D * den) % num || ((long long)g.D * den / num) % g.n)
     return cfail(PWFS_EINVAL, "the pupil images must be whole detector pixels tiled by the subapertures");
-  out.img = g.D / d->rebin;
+  out.img = (int)((long long)g.D * den / num);
   out.b = out.img / g.n;
   for (int q = 0; q < 2; ++q) {
     const int sgn = q ? 1 : -1;
-    const int o = g.N / 2 + sgn * g.S / 2 - g.D / 2 - out.off;
-    if (o < 0 || o % d->rebin || o / d->rebin + out.img > d->n_det)
+    const long long o = (long long)(g.N / 2 + sgn * g.S / 2 - g.D / 2 - out.off) * den;
+    if (o < 0 || o % num || o / num + out.img > d->n_det)
       return cfail(PWFS_EINVAL, "pupil image not aligned with the detector pixels");
-    out.img_r[q] = out.img_c[q] = o / d->rebin;
+    out.img_r[q] = out.img_c[q] = (int)(o / num);
   }
   return PWFS_OK;
 }
@@ -250,7 +269,8 @@ extern "C" int pwfs_ccd(pwfs_plan_t p, int sensor, const pwfs_ccd_desc* d, const
   a.out = out;
   a.N = sp.g.N;
   a.n_det = d->n_det;
-  a.rebin = d->rebin;
+  a.num = dg.num;
+  a.den = dg.den;
   a.off = dg.off;
   a.windows = sp.g.full ? 0 : 1;
   for (int q = 0; q < 2; ++q) {
@@ -288,6 +308,6 @@ extern "C" int pwfs_ccd_slopes(pwfs_plan_t p, int sensor, const pwfs_ccd_desc* d
   const int org_c[4] = {dg.img_c[0], dg.img_c[1], dg.img_c[0], dg.img_c[1]};
   const float* ref = (sp.desc.flags & PWFS_F_REF_SLOPES) ? (const float*)sp.dev[R_REF] : nullptr;
   const int nn = d->n_det * d->n_det;
-  return slopes_launch_at(sp, pixels, nn, slopes, 2LL * sp.g.n * sp.g.n, flux, 1, ref, nf, d->n_det, dg.b, org_r,
+  return slopes_launch_at(sp, pixels, nn, slopes, 2LL * sp.g.n * sp.g.n, flux, 1, ref, nf, d->n_det, dg.img, org_r,
                           org_c, (hipStream_t)stream, &p->prof);
 }

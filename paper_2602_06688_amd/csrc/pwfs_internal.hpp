@@ -101,12 +101,14 @@ struct pwfs_plan_s {
 };
 
 namespace pwfs {
-// slope stage on an n_in x n_in input whose four pupil images start at
-// (org_r[q], org_c[q]) and are binned b x b (the intensity plane, or the
-// detector pixels of the detector stage)
+// slope stage on an n_in x n_in input whose four img x img pupil images start
+// at (org_r[q], org_c[q]) and are cut into the sensor's n x n subapertures
+// (the intensity plane, or the detector pixels of the detector stage); when
+// img is not a multiple of n, pixels cut by subaperture edges count with
+// their area fraction
 int slopes_launch_at(const SensorPlan& sp, const float* in, long long in_stride, float* slopes,
                      long long slope_stride, float* flux, long long flux_stride, const float* ref, int nf, int n_in,
-                     int b, const int* org_r, const int* org_c, hipStream_t st, Prof* prof);
+                     int img, const int* org_r, const int* org_c, hipStream_t st, Prof* prof);
 int forward_sensor(pwfs_plan_s* p, int i, const float* opd, long long opd_stride, float* out, long long out_stride,
                    int nf, hipStream_t st);
 }

@@ -85,7 +85,7 @@ struct SlopeArgs {
   const uint8_t* valid;    // [n][n]
   const float* ref;        // [2][n][n] or nullptr
   long long in_stride, slope_stride, flux_stride;
-  int N, n, b, n_valid, local_norm;
+  int N, n, b, img, n_valid, local_norm;   // b = img / n (whole subapertures)
   int org_r[4], org_c[4];  // image origins
 };
 
@@ -466,7 +466,8 @@ __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
 // a pixel row.  NT = 1024 serves small frame counts, where the frame's own
 // latency is the cost.
 // BB: the block size b when known at compile time (its loads are then issued
-// together), 0 for a run-time b.
+// together), 0 for a run-time b, -1 when subapertures are not whole pixels
+// (pixels cut by a subaperture edge count with their area fraction).
 template <int NT, int BB>
 __global__ __launch_bounds__(NT) void k_slopes(SlopeArgs p) {
   extern __shared__ float s_q[];        // [4][n*n]
@@ -474,14 +475,30 @@ __global__ __launch_bounds__(NT) void k_slopes(SlopeArgs p) {
   const int tid = threadIdx.x, f = blockIdx.x;
   const int nn = p.n * p.n;
   const float* I = p.in + (long long)f * p.in_stride;
-  const int b = BB ? BB : p.b;
+  const int b = BB > 0 ? BB : p.b;
 
   for (int it = tid; it < 4 * nn; it += NT) {
     const int q = it / nn, s = it % nn;
     const int i = s / p.n, j = s % p.n;
-    const float* blk = I + (size_t)(p.org_r[q] + i * b) * p.N + p.org_c[q] + j * b;
     float acc = 0.f;
-    if constexpr (BB > 0) {
+    if constexpr (BB < 0) {
+      // subaperture i spans pixels [i img / n, (i + 1) img / n): integer
+      // overlaps in units of 1/n pixel, the sum scaled by 1/n^2 at the end
+      const int n = p.n, D = p.img;
+      const int ylo = i * D, yhi = ylo + D, xlo = j * D, xhi = xlo + D;
+      const float* im = I + (size_t)p.org_r[q] * p.N + p.org_c[q];
+      for (int y = ylo / n; y * n < yhi; ++y) {
+        const int oy = min((y + 1) * n, yhi) - max(y * n, ylo);
+        float row = 0.f;
+        for (int x = xlo / n; x * n < xhi; ++x) {
+          const int ox = min((x + 1) * n, xhi) - max(x * n, xlo);
+          row += (float)ox * im[(size_t)y * p.N + x];
+        }
+        acc += (float)oy * row;
+      }
+      acc *= 1.0f / (float)(n * n);
+    } else if constexpr (BB > 0) {
+      const float* blk = I + (size_t)(p.org_r[q] + i * b) * p.N + p.org_c[q] + j * b;
       float v[BB * BB];
 #pragma unroll
       for (int r = 0; r < BB; ++r)
@@ -490,6 +507,7 @@ __global__ __launch_bounds__(NT) void k_slopes(SlopeArgs p) {
 #pragma unroll
       for (int e = 0; e < BB * BB; ++e) acc += v[e];
     } else {
+      const float* blk = I + (size_t)(p.org_r[q] + i * b) * p.N + p.org_c[q] + j * b;
       for (int r = 0; r < b; ++r)
         for (int c = 0; c < b; ++c) acc += blk[(size_t)r * p.N + c];
     }

@@ -71,7 +71,7 @@ int validate_one(const pwfs_sensor_desc& d, int idx) {
   if (d.n_pupil < 4 || (d.n_pupil & 1)) return bad("n_pupil must be even and >= 4");
   if (d.n_fft < d.n_pupil) return bad("n_fft must be >= n_pupil");
   if ((d.n_fft - d.n_pupil) & 1) return bad("n_fft - n_pupil must be even");
-  if (d.n_subap < 1 || d.n_pupil % d.n_subap) return bad("n_pupil must be a multiple of n_subap");
+  if (d.n_subap < 1 || d.n_subap > d.n_pupil) return bad("n_subap must be in [1, n_pupil]");
   if (d.n_mod < 1 || d.n_mod > 4096) return bad("n_mod must be in [1, 4096]");
   if (d.n_lambda < 1 || d.n_lambda > PWFS_MAX_LAMBDA) return bad("n_lambda must be in [1, 16]");
   if (!(d.diameter_m > 0.0) || !std::isfinite(d.diameter_m)) return bad("diameter_m must be > 0");
@@ -107,8 +107,14 @@ int validate_one(const pwfs_sensor_desc& d, int idx) {
   return PWFS_OK;
 }
 
+// overlap of pixel y with subaperture i along one axis, in units of 1/n pixel:
+// subaperture i spans pixels [i D / n, (i + 1) D / n)
+static inline int subap_overlap(int y, int i, int D, int n) {
+  return std::max(0, std::min((y + 1) * n, (i + 1) * D) - std::max(y * n, i * D));
+}
+
 void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vector<uint8_t>& V) {
-  const int D = d.n_pupil, n = d.n_subap, b = D / n;
+  const int D = d.n_pupil, n = d.n_subap;
   A.assign((size_t)D * D, 0.f);
   const double R = D / 2.0, Ro = d.obstruction * R;
   for (int y = 0; y < D; ++y)
@@ -117,13 +123,16 @@ void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vect
       const double r2 = cx * cx + cy * cy;
       A[(size_t)y * D + x] = (r2 <= R * R && r2 >= Ro * Ro) ? 1.f : 0.f;
     }
+  // valid: at least half of the subaperture's area on lit pixels (areas in
+  // units of 1/n^2 pixel are integers; the subaperture's is D^2)
   V.assign((size_t)n * n, 0);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
-      int cnt = 0;
-      for (int r = 0; r < b; ++r)
-        for (int c = 0; c < b; ++c) cnt += A[(size_t)(i * b + r) * D + j * b + c] != 0.f;
-      V[(size_t)i * n + j] = (2 * cnt >= b * b) ? 1 : 0;
+      long long lit = 0;
+      for (int y = i * D / n; y * n < (i + 1) * D; ++y)
+        for (int x = j * D / n; x * n < (j + 1) * D; ++x)
+          if (A[(size_t)y * D + x] != 0.f) lit += (long long)subap_overlap(y, i, D, n) * subap_overlap(x, j, D, n);
+      V[(size_t)i * n + j] = (2 * lit >= (long long)D * D) ? 1 : 0;
     }
 }
 
@@ -634,6 +643,8 @@ int prepare_kernels() {
   if ((rc = set_lds_limits_q<384>())) return rc;
   if ((rc = set_lds_limits_q<512>())) return rc;
   if ((rc = set_lds_limits_q<768>())) return rc;
+  lds_limit((const void*)k_slopes<kBlock, -1>);
+  lds_limit((const void*)k_slopes<1024, -1>);
   lds_limit((const void*)k_slopes<kBlock, 0>);
   lds_limit((const void*)k_slopes<kBlock, 1>);
   lds_limit((const void*)k_slopes<kBlock, 2>);
@@ -654,7 +665,7 @@ constexpr int kSlopesWideBelow = 64;
 
 int slopes_launch_at(const SensorPlan& sp, const float* in, long long in_stride, float* slopes,
                      long long slope_stride, float* flux, long long flux_stride, const float* ref, int nf, int n_in,
-                     int b, const int* org_r, const int* org_c, hipStream_t st, Prof* prof) {
+                     int img, const int* org_r, const int* org_c, hipStream_t st, Prof* prof) {
   const Geometry& g = sp.g;
   SlopeArgs a{};
   a.in = in;
@@ -667,7 +678,9 @@ int slopes_launch_at(const SensorPlan& sp, const float* in, long long in_stride,
   a.flux_stride = flux_stride;
   a.N = n_in;
   a.n = g.n;
-  a.b = b;
+  a.img = img;
+  a.b = img / g.n;
+  const int b = (img % g.n) ? -1 : a.b;     // -1: subapertures cut pixels
   a.n_valid = sp.n_valid;
   a.local_norm = (sp.desc.flags & PWFS_F_LOCAL_NORM) ? 1 : 0;
   for (int q = 0; q < 4; ++q) {
@@ -678,7 +691,9 @@ int slopes_launch_at(const SensorPlan& sp, const float* in, long long in_stride,
   const int slot = prof ? prof->begin(st) : -1;
   const bool wide = nf < kSlopesWideBelow;
   const dim3 grid((unsigned)nf), block(wide ? 1024 : kBlock);
-  switch ((wide ? 100 : 0) + (b == 1 || b == 2 || b == 4 || b == 8 ? b : 0)) {
+  switch ((wide ? 100 : 0) + (b == 1 || b == 2 || b == 4 || b == 8 || b == -1 ? b : 0)) {
+    case -1: hipLaunchKernelGGL((k_slopes<kBlock, -1>), grid, block, lds, st, a); break;
+    case 99: hipLaunchKernelGGL((k_slopes<1024, -1>), grid, block, lds, st, a); break;
     case 1: hipLaunchKernelGGL((k_slopes<kBlock, 1>), grid, block, lds, st, a); break;
     case 2: hipLaunchKernelGGL((k_slopes<kBlock, 2>), grid, block, lds, st, a); break;
     case 4: hipLaunchKernelGGL((k_slopes<kBlock, 4>), grid, block, lds, st, a); break;
@@ -705,7 +720,7 @@ int slopes_launch(const SensorPlan& sp, const float* in, long long in_stride, fl
       org_r[q] = g.N / 2 + sy * g.S / 2 - g.D / 2;
       org_c[q] = g.N / 2 + sx * g.S / 2 - g.D / 2;
     }
-  return slopes_launch_at(sp, in, in_stride, slopes, slope_stride, flux, flux_stride, ref, nf, g.N, g.b, org_r, org_c,
+  return slopes_launch_at(sp, in, in_stride, slopes, slope_stride, flux, flux_stride, ref, nf, g.N, g.D, org_r, org_c,
                           st, prof);
 }
 

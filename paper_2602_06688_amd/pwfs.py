@@ -76,7 +76,7 @@ CCD_EXCESS = 4
 
 class CCcdDesc(ctypes.Structure):
     _fields_ = [("n_det", ctypes.c_int32), ("rebin", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32), ("electrons", ctypes.c_double), ("readout_e", ctypes.c_double),
+                ("rebin_den", ctypes.c_int32), ("electrons", ctypes.c_double), ("readout_e", ctypes.c_double),
                 ("seed", ctypes.c_uint64)]
 
 
@@ -91,11 +91,14 @@ class CLayer(ctypes.Structure):
                 ("vel_x", ctypes.c_double), ("vel_y", ctypes.c_double)]
 
 
-def ccd_desc(n_det: int, rebin: int, electrons: float, flags: int = CCD_PHOTON, readout_e: float = 0.0,
+def ccd_desc(n_det: int, rebin, electrons: float, flags: int = CCD_PHOTON, readout_e: float = 0.0,
              seed: int = 0) -> CCcdDesc:
-    """A detector description (see pwfs_ccd_desc in include/pwfs.h)."""
-    return CCcdDesc(int(n_det), int(rebin), int(flags), 0, float(electrons), float(readout_e),
-                    int(seed) & ((1 << 64) - 1))
+    """A detector description (see pwfs_ccd_desc in include/pwfs.h); rebin is
+    an integer or a fractions.Fraction (transform pixels per detector pixel)."""
+    from fractions import Fraction
+    r = Fraction(rebin)
+    return CCcdDesc(int(n_det), int(r.numerator), int(flags), int(r.denominator) if r.denominator > 1 else 0,
+                    float(electrons), float(readout_e), int(seed) & ((1 << 64) - 1))
 
 _lib = None
 

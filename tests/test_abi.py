@@ -33,7 +33,7 @@ def _bad(**kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(n_fft=60), P.PWFS_EINVAL),                   # N < D
     (dict(n_fft=129), P.PWFS_EINVAL),                  # N - D odd
-    (dict(n_subap=15), P.PWFS_EINVAL),                 # D % n_subap
+    (dict(n_subap=65), P.PWFS_EINVAL),                 # n_subap > D
     (dict(pupil_sep_px=66.0, n_fft=128), P.PWFS_EINVAL),   # images outside the grid
     (dict(pupil_sep_px=62.0), P.PWFS_EINVAL),          # images overlap
     (dict(pupil_sep_px=64.5), P.PWFS_EINVAL),          # non-integer separation

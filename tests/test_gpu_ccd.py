@@ -5,6 +5,8 @@ Gamma draws to float tolerance, slopes on detector pixels; batching
 invariance in the benchmark's launch configuration; the noise-free detector
 reproduces the intensity slopes; argument errors."""
 
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -156,9 +158,85 @@ def test_errors():
         plan.ccd(I, P.ccd_desc(130, 4, 1e4, P.CCD_PHOTON))          # larger than the plane
     assert e.value.code == P.PWFS_EINVAL
     bad = P.ccd_desc(120, 4, 1e4, P.CCD_PHOTON)
-    bad.reserved = 1
+    bad.rebin_den = 65
     with pytest.raises(P.PwfsError):
         plan.ccd(I, bad)
     with pytest.raises(P.PwfsError) as e:
+        plan.ccd(I, P.ccd_desc(120, Fraction(3, 4), 1e4, P.CCD_PHOTON))   # pixels finer than the plane's
+    assert e.value.code == P.PWFS_EINVAL
+    with pytest.raises(P.PwfsError) as e:
+        plan.ccd(I, P.ccd_desc(121, Fraction(7, 2), 1e4, P.CCD_PHOTON))   # 423.5 px: not whole pixels
+    assert e.value.code == P.PWFS_EINVAL
+    with pytest.raises(P.PwfsError) as e:
         plan.ccd(torch.zeros((3, 512, 512), device="cuda"), P.ccd_desc(120, 4, 1e4, P.CCD_PHOTON))
     assert e.value.code == P.PWFS_ESTATE
+
+
+def _soul_like(full):
+    # 44 px pupil, 8 subapertures of 5.5 px, images 66 px apart on a 128 grid;
+    # a 20 px detector of 5.5 transform pixels: one detector pixel per subaperture
+    return tiny_sensor(n_pupil=44, n_fft=128, n_subap=8, pupil_sep_px=66.0, n_mod=8, mod_radius_lod=2.0,
+                       flags=FLAG_REF_SLOPES | (FLAG_FULL_PLANE if full else 0))
+
+
+@pytest.mark.parametrize("full", [True, False])
+@pytest.mark.parametrize("label,flags", FLAGS)
+def test_fractional_pitch_matches_oracle(label, flags, full):
+    P = _P()
+    s = _soul_like(full)
+    r = Fraction(11, 2)
+    rng = np.random.default_rng(23)
+    I = O.forward(rng.normal(0.0, 80.0, (3, 44, 44)), s).astype(np.float32)
+    Iw = I if full else I * _window_mask(s)[None]
+    plan = P.Plan([s], max_frames=3)
+    d = P.ccd_desc(20, r, 3.0e4, flags, readout_e=0.7, seed=99)
+    print(f"[gpu] ccd pitch 11/2 {label} full={full}", flush=True)
+    got = plan.ccd(torch.from_numpy(I).cuda(), d, frame0=2)
+    want = C.detector(Iw, 20, r, 3.0e4, flags, 0.7, 99, frame0=2)
+    if flags & 2 or flags & 4:
+        np.testing.assert_allclose(got.cpu().numpy(), want.astype(np.float32), rtol=1e-6, atol=1e-5)
+    else:
+        np.testing.assert_array_equal(got.cpu().numpy(), want.astype(np.float32))
+    sl, fl = plan.ccd_slopes(got, d)
+    ws, wf = C.detector_slopes(want, s, 20, r)
+    valid = O.valid_subapertures(s)
+    np.testing.assert_allclose(sl.cpu().numpy(), ws, atol=2e-5 if flags else 1e-5)
+    np.testing.assert_allclose(fl.cpu().numpy(), wf, rtol=1e-5)
+    assert (sl.cpu().numpy()[:, :, ~valid] == 0).all()
+
+
+def test_soul_geometry_chain():
+    """The SOUL pyramid of Appendix B: 220 px pupil, 40 subapertures of 5.5 px,
+    pupils 48 subapertures apart, 3 lambda/D modulation at 750 nm with 24
+    points (Table 2: 24 transforms per step), read out on a 120 x 120
+    detector of 5.5 transform pixels (on a 768 grid here).  Two frames:
+    intensity, the sensor's own slopes (fractional subapertures), detector
+    pixels and detector slopes, all against the oracle."""
+    P = _P()
+    from workloads import von_karman_opd
+    s = tiny_sensor(n_pupil=220, n_fft=768, n_subap=40, pupil_sep_px=264.0, n_mod=24, mod_radius_lod=3.0,
+                    diameter_m=8.222, flags=FLAG_REF_SLOPES)
+    opd = von_karman_opd(2, 220, 8.222, 0.126, 40.0, seed=31)
+    x = torch.from_numpy(opd.astype(np.float32)).cuda()
+    plan = P.Plan([s], max_frames=2)
+    print("[gpu] SOUL geometry: forward + slopes", flush=True)
+    I, sl, fl = plan.step(x)
+    I_ref = O.forward(opd.astype(np.float32).astype(np.float64), s)
+    m = _window_mask(s)
+    Ig = I.cpu().numpy().astype(np.float64) * m[None]
+    e = np.linalg.norm((Ig - I_ref * m[None]).reshape(2, -1), axis=1) / np.linalg.norm((I_ref * m[None]).reshape(2, -1), axis=1)
+    assert e.max() < 1e-5
+    s_ref, f_ref = O.slopes(I_ref, s)
+    valid = O.valid_subapertures(s)
+    assert np.array_equal(plan.valid_map(0), valid)
+    assert O.slope_rel_rms(sl.cpu().numpy(), s_ref, valid) < 1e-4
+    r = Fraction(11, 2)
+    d = P.ccd_desc(120, r, 2.0e5, P.CCD_PHOTON | P.CCD_READOUT, readout_e=0.4, seed=8)
+    print("[gpu] SOUL geometry: detector 120 px, pitch 11/2", flush=True)
+    Iin = I_ref.astype(np.float32)
+    got = plan.ccd(torch.from_numpy(Iin).cuda(), d)
+    want = C.detector(Iin * m[None], 120, r, 2.0e5, 3, 0.4, 8)
+    np.testing.assert_allclose(got.cpu().numpy(), want.astype(np.float32), rtol=1e-6, atol=1e-5)
+    dsl, dfl = plan.ccd_slopes(got, d)
+    ws, wf = C.detector_slopes(want, s, 120, r)
+    assert O.slope_rel_rms(dsl.cpu().numpy(), ws, valid) < 1e-5

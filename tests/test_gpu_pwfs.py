@@ -108,6 +108,10 @@ EDGE = {
                                mod_radius_lod=2.0, src_rings=1, src_radius_lod=1.5),
     "extended_r2_unmod": tiny_sensor(n_pupil=48, n_fft=128, n_subap=12, pupil_sep_px=56.0, n_mod=1,
                                      mod_radius_lod=0.0, src_rings=2, src_radius_lod=2.0, obstruction=0.2),
+    # subapertures that are not whole pixels: 5.5 px (the SOUL ratio) and 64 / 15
+    "subap_5p5": tiny_sensor(n_pupil=44, n_fft=128, n_subap=8, pupil_sep_px=66.0, n_mod=8, mod_radius_lod=2.0),
+    "subap_64_over_15": tiny_sensor(n_pupil=64, n_fft=128, n_subap=15, pupil_sep_px=64.0, n_mod=6,
+                                    obstruction=0.25, mod_radius_lod=2.0, flags=5),
     # finely sampled bands: 16 wavelengths over 300 nm (palindromic plan, full
     # plane) and 7 on the radix-3 plan
     "poly16_full": tiny_sensor(n_pupil=64, n_fft=128, n_subap=16, pupil_sep_px=64.0, n_mod=8,

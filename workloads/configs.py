@@ -142,15 +142,16 @@ def soul_loop(s: SensorDesc) -> dict:
     sensor.  From the listing: 500 modes, integrator gains / forgetting
     factors per mode group of 30 / 70 / 100 / 300 modes, total delay 2,
     four layers with Cn2 fractions 0.70 / 0.06 / 0.14 / 0.10, L0 = 40 m,
-    0.8 arcsec seeing on the line of sight (Fig. 9 caption), 0.588 ms steps.
-    Readings (not in the paper): wind 8 / 10 / 15 / 20 m/s towards 0 / 90 /
-    180 / 270 degrees; layers as 1024 x 1024 periodic screens at the pupil's
+    0.8 arcsec seeing on the line of sight (Fig. 9 caption), 0.588 ms steps,
+    wind 2 / 4 / 6 / 25 m/s along 0 / 30 / -30 / 45 degrees.  Readings (not
+    in the paper): the direction is that of the layer's motion, counted from
+    +x towards +y; layers as 1024 x 1024 periodic screens at the pupil's
     pixel size (an on-axis source sees every layer unshifted by height)."""
     pixel_m = s.diameter_m / s.n_pupil
     r0 = 0.98 * 500e-9 / (0.8 / 206264.806)          # Fried parameter at 500 nm for 0.8"
     dt = 0.000588
-    speeds = (8.0, 10.0, 15.0, 20.0)
-    dirs = (0.0, 90.0, 180.0, 270.0)
+    speeds = (2.0, 4.0, 6.0, 25.0)
+    dirs = (0.0, 30.0, -30.0, 45.0)
     vel = [(v * dt / pixel_m * math.cos(math.radians(a)), v * dt / pixel_m * math.sin(math.radians(a)))
            for v, a in zip(speeds, dirs)]
     return dict(n_modes=500, groups=(30, 70, 100, 300), gains=(0.55, 0.45, 0.40, 0.35),
