@@ -33,6 +33,11 @@ import numpy as np
 FLAG_REF_SLOPES = 1
 FLAG_FULL_PLANE = 2
 FLAG_LOCAL_NORM = 4
+FLAG_DOUBLE_ROOF = 8
+
+
+def is_double_roof(s) -> bool:
+    return bool(int(getattr(s, "flags", 0)) & FLAG_DOUBLE_ROOF)
 
 
 # ---------------------------------------------------------------- geometry --
@@ -116,8 +121,15 @@ def tilt_ramp(n_pupil: int, tx_lod: float, ty_lod: float) -> np.ndarray:
 
 def image_origins(s) -> list:
     """Top-left corner (row, col) of the four pupil images, quadrant order
-    q = 2*iy + ix with iy, ix = 0 for the image at N/2 - S/2 and 1 for N/2 + S/2."""
+    q = 2*iy + ix with iy, ix = 0 for the image at N/2 - S/2 and 1 for N/2 + S/2.
+    For a double roof: (plane, row, col) of arm x's images at x = N/2 -/+ S/2
+    (q = 0, 1; plane 0, centred in y) and arm y's at y = N/2 -/+ S/2 (q = 2, 3;
+    plane 1, centred in x)."""
     N, D, S = s.n_fft, s.n_pupil, int(round(s.pupil_sep_px))
+    if is_double_roof(s):
+        c = N // 2 - D // 2
+        return [(0, c, N // 2 - S // 2 - D // 2), (0, c, N // 2 + S // 2 - D // 2),
+                (1, N // 2 - S // 2 - D // 2, c), (1, N // 2 + S // 2 - D // 2, c)]
     out = []
     for sy in (-1, 1):
         for sx in (-1, 1):
@@ -139,24 +151,40 @@ def focal_field(E_pupil: np.ndarray, n_fft: int) -> np.ndarray:
     return np.fft.fft2(E)
 
 
-def pyramid_image(E_pupil: np.ndarray, n_fft: int, m: np.ndarray) -> np.ndarray:
-    """Complex field after the pyramid: IDFT2(DFT2(pad(E) h h) (m m)), with
-    the inverse carrying 1/N^2."""
+def pyramid_image(E_pupil: np.ndarray, n_fft: int, m: np.ndarray, m_y: np.ndarray | None = None) -> np.ndarray:
+    """Complex field after the pyramid: IDFT2(DFT2(pad(E) h h) (m_y m)), with
+    the inverse carrying 1/N^2 (m_y = m: the four faces)."""
     F = focal_field(E_pupil, n_fft)
-    return np.fft.ifft2(F * (m[:, None] * m[None, :]))
+    my = m if m_y is None else m_y
+    return np.fft.ifft2(F * (my[:, None] * m[None, :]))
 
 
 def forward_frame(opd_nm: np.ndarray, s, mask: np.ndarray | None = None) -> np.ndarray:
-    """Normalised modulated intensity of one frame, float64 [N][N].
+    """Normalised modulated intensity of one frame, float64 [N][N] ([2][N][N]
+    for a double roof).
 
     I = sum_l w_l (1/(n_mod P)) sum_k sum_p |e_{l,k,p}|^2 / sum(A^2) over the
     modulation points k and the P source points p; phase 2 pi OPD / lambda,
     modulation radius and source offsets scaled by lambda_ref / lambda (fixed
-    angles on the sky), mask in pixel units independent of lambda."""
+    angles on the sky), mask in pixel units independent of lambda.
+
+    Double roof (Table 4: ModulatedDoubleRoof; the geometry is a reading): a
+    50/50 beam splitter feeds two roof prisms, one with the pyramid's edge
+    along x only (mask m(u), 1 along v), one along y only; each arm gets half
+    the light and forms two pupil images S apart along its own axis, on a
+    plane of its own."""
+    N = s.n_fft
+    m = mask_vector(N, s.pupil_sep_px) if mask is None else mask
+    if is_double_roof(s):
+        one = np.ones(N, np.complex128)
+        return np.stack([0.5 * _modulated(opd_nm, s, m, one), 0.5 * _modulated(opd_nm, s, one, m)])
+    return _modulated(opd_nm, s, m, m)
+
+
+def _modulated(opd_nm: np.ndarray, s, m_x: np.ndarray, m_y: np.ndarray) -> np.ndarray:
     D, N = s.n_pupil, s.n_fft
     A = pupil_amplitude(D, s.obstruction)
     sA2 = float((A * A).sum())
-    m = mask_vector(N, s.pupil_sep_px) if mask is None else mask
     th = modulation_angles(s.n_mod)
     src = source_points(s)
     opd = np.asarray(opd_nm, dtype=np.float64)
@@ -170,7 +198,7 @@ def forward_frame(opd_nm: np.ndarray, s, mask: np.ndarray | None = None) -> np.n
             Em = E0 * modulation_ramp(D, r, t)
             for dx, dy in src:
                 Ep = Em if (dx == 0.0 and dy == 0.0) else Em * tilt_ramp(D, sc * dx, sc * dy)
-                e = pyramid_image(Ep, N, m)
+                e = pyramid_image(Ep, N, m_x, m_y)
                 acc += e.real ** 2 + e.imag ** 2
         I += w * acc / (s.n_mod * len(src) * sA2)
     return I
@@ -205,8 +233,8 @@ def separable_operator(n_fft: int, n_pupil: int, pupil_sep: float) -> np.ndarray
 def forward_frame_separable(opd_nm: np.ndarray, s) -> np.ndarray:
     """The same intensity as ``forward_frame`` through e_k = P (E o R_k) P^T
     (point sources only)."""
-    if int(getattr(s, "src_rings", 0)) > 0:
-        raise ValueError("the separable form is written for a point source")
+    if int(getattr(s, "src_rings", 0)) > 0 or is_double_roof(s):
+        raise ValueError("the separable form is written for a four-face pyramid and a point source")
     D, N = s.n_pupil, s.n_fft
     A = pupil_amplitude(D, s.obstruction)
     sA2 = float((A * A).sum())
@@ -244,13 +272,18 @@ def bin_images(I: np.ndarray, s) -> np.ndarray:
     otherwise pixels cut by subaperture edges count with their area
     fraction (Q = W I W^T, W the overlaps / n)."""
     I = np.asarray(I, dtype=np.float64)
-    if I.ndim == 2:
+    if I.ndim == (3 if is_double_roof(s) else 2):
         I = I[None]
     D, n = s.n_pupil, s.n_subap
     Q = np.zeros((I.shape[0], 4, n, n), np.float64)
     W = subaperture_overlaps(D, n) / n
-    for q, (r0, c0) in enumerate(image_origins(s)):
-        win = I[:, r0:r0 + D, c0:c0 + D]
+    for q, org in enumerate(image_origins(s)):
+        if is_double_roof(s):
+            pl, r0, c0 = org
+            win = I[:, pl, r0:r0 + D, c0:c0 + D]
+        else:
+            r0, c0 = org
+            win = I[:, r0:r0 + D, c0:c0 + D]
         if D % n == 0:
             b = D // n
             Q[:, q] = win.reshape(I.shape[0], n, b, n, b).sum(axis=(2, 4))
@@ -267,6 +300,28 @@ def valid_subapertures(s) -> np.ndarray:
     W = subaperture_overlaps(s.n_pupil, s.n_subap)
     lit = W @ A @ W.T
     return 2.0 * lit >= float(s.n_pupil) ** 2
+
+
+def raw_slopes_roof(Q: np.ndarray, valid: np.ndarray, local_norm: bool = False):
+    """Double-roof slope computer (Table 4: DoubleRoofSlopec; the form is a
+    reading): each axis from its own arm, s_x = (Q0 - Q1) / T_x with T_x the
+    mean over valid subapertures of Q0 + Q1 (arm x), s_y = (Q2 - Q3) / T_y
+    likewise (arm y); with ``local_norm`` each subaperture's own arm flux.
+    Signs as for the pyramid (the image at N/2 - S/2 minus the one at
+    N/2 + S/2).  flux = sum over valid subapertures of all four images."""
+    Q = np.asarray(Q, dtype=np.float64)
+    Tx = Q[:, 0] + Q[:, 1]
+    Ty = Q[:, 2] + Q[:, 3]
+    nv = valid.sum()
+    if local_norm:
+        nx = np.where(valid[None], Tx, 1.0)
+        ny = np.where(valid[None], Ty, 1.0)
+    else:
+        nx = (Tx[:, valid].sum(axis=1) / nv)[:, None, None]
+        ny = (Ty[:, valid].sum(axis=1) / nv)[:, None, None]
+    s = np.stack([(Q[:, 0] - Q[:, 1]) / nx, (Q[:, 2] - Q[:, 3]) / ny], axis=1)
+    s[:, :, ~valid] = 0.0
+    return s, (Tx + Ty)[:, valid].sum(axis=1)
 
 
 def raw_slopes(Q: np.ndarray, valid: np.ndarray, local_norm: bool = False):
@@ -292,11 +347,17 @@ def raw_slopes(Q: np.ndarray, valid: np.ndarray, local_norm: bool = False):
     return s, flux
 
 
+def sensor_raw_slopes(Q: np.ndarray, s, valid: np.ndarray):
+    """The slope computer of sensor s: the pyramid's or the double roof's."""
+    rs = raw_slopes_roof if is_double_roof(s) else raw_slopes
+    return rs(Q, valid, bool(s.flags & FLAG_LOCAL_NORM))
+
+
 def reference_slopes(s) -> np.ndarray:
     """Raw slopes of a flat wavefront, [2][n][n]."""
     D = s.n_pupil
     I = forward(np.zeros((1, D, D)), s)
-    return raw_slopes(bin_images(I, s), valid_subapertures(s), bool(s.flags & FLAG_LOCAL_NORM))[0][0]
+    return sensor_raw_slopes(bin_images(I, s), s, valid_subapertures(s))[0][0]
 
 
 def slopes(I: np.ndarray, s, ref: np.ndarray | None = None):
@@ -304,7 +365,7 @@ def slopes(I: np.ndarray, s, ref: np.ndarray | None = None):
     flat-wavefront reference when the sensor asks for it, zero outside the
     valid map.  Returns (slopes [F][2][n][n], flux [F])."""
     valid = valid_subapertures(s)
-    sl, flux = raw_slopes(bin_images(I, s), valid, bool(s.flags & FLAG_LOCAL_NORM))
+    sl, flux = sensor_raw_slopes(bin_images(I, s), s, valid)
     if s.flags & FLAG_REF_SLOPES:
         if ref is None:
             ref = reference_slopes(s)

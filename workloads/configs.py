@@ -20,6 +20,7 @@ from typing import Optional, Tuple
 FLAG_REF_SLOPES = 1   # subtract flat-wavefront reference slopes
 FLAG_FULL_PLANE = 2   # compute and write every pixel of the N x N plane
 FLAG_LOCAL_NORM = 4   # normalise slopes by per-subaperture flux
+FLAG_DOUBLE_ROOF = 8  # two-arm double-roof sensor instead of the four-face pyramid
 
 # precision of the forward transform (mirrored by the C header)
 PREC_FP32 = 0
