@@ -223,6 +223,33 @@ def detector_form(P, torch, dev, stream, x, plan, I, s, steps: int):
                          "avg_launch_ms": round(ccd_ms / max(1, ccd_n), 4), "traffic": None}}
 
 
+def roof_form(P, torch, dev, x, s, steps: int):
+    """The 160 px sensor as a double roof (two arms, one roof edge each) over
+    the same 1000 frames: forward + slopes.  Nominal flops: each arm needs a
+    1-D transform pair along its roof axis over the N x N plane per point,
+    so the two arms together count as one 2-D pair, the pyramid's figure
+    (the kernels also run the flat-mask axis, which is work the method does
+    not need)."""
+    from workloads import FLAG_DOUBLE_ROOF, FLAG_REF_SLOPES
+    sr = s.with_(flags=FLAG_DOUBLE_ROOF | FLAG_REF_SLOPES)
+    F = int(x.shape[0])
+    plan = P.Plan([sr], max_frames=F, device=dev)
+    out = plan.step(x)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.step(x, *out)
+    torch.cuda.synchronize(dev)
+    fs = F * steps / (time.perf_counter() - t0)
+    fl = nominal_flops(s)["path"]
+    a = fl * fs / 1e12
+    print(f"# double roof: {fs:.0f} frames/s ({a:.1f} TFLOP/s nominal)", file=sys.stderr, flush=True)
+    return {"value": round(fs, 1), "unit": "frames/s",
+            "workload": "160 px double roof, N=512, 48 points, 40x40, 1000 frames per step",
+            "roofline_path": {"bound": "alu", "achieved": round(a, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(a / FP32_PEAK_TFLOPS, 4), "flops_per_frame": fl}}
+
+
 def soul_form(P, torch, dev, stream, steps: int, frames: int = 1000, distinct: int = 200):
     """The SOUL pyramid of Appendix B as one chain: 220 px pupil (8.22 m),
     40 x 40 subapertures of 5.5 px, pupils 48 subapertures apart, 3 lambda/D
@@ -497,6 +524,7 @@ def main() -> int:
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous six-sensor batch")
     ap.add_argument("--no-poly", action="store_true", help="skip the 16-wavelength sensor")
     ap.add_argument("--no-soul", action="store_true", help="skip the SOUL pyramid + detector chain")
+    ap.add_argument("--no-roof", action="store_true", help="skip the double-roof sensor")
     ap.add_argument("--surrogate-train", type=int, default=200_000)
     ap.add_argument("--surrogate-epochs", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -595,6 +623,8 @@ def main() -> int:
         forms["surrogate"] = surrogate_form(torch, dev, args.surrogate_train, 20_000, args.surrogate_epochs, 5)
     if not args.no_sh:
         forms["shack_hartmann"] = sh_form(P, torch, dev, x, max(2, args.steps // 2))
+    if not args.no_roof:
+        forms["double_roof"] = roof_form(P, torch, dev, x, s, max(2, args.steps // 4))
     if not args.no_soul:
         forms["soul_chain"] = soul_form(P, torch, dev, stream, max(2, args.steps // 4))
     if not args.no_poly:

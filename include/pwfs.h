@@ -66,7 +66,19 @@ enum {
   PWFS_F_FULL_PLANE = 2,  /* compute every pixel of the N x N plane; without
                              it only the four D x D pupil images are written
                              and the other pixels are left untouched        */
-  PWFS_F_LOCAL_NORM = 4   /* normalise by per-subaperture flux, not mean    */
+  PWFS_F_LOCAL_NORM = 4,  /* normalise by per-subaperture flux, not mean    */
+  PWFS_F_DOUBLE_ROOF = 8  /* double-roof sensor (Table 4: ModulatedDoubleRoof)
+                             instead of the four-face pyramid: a 50/50 splitter
+                             feeds two roof prisms, the first with its edge
+                             along x (two images S apart in x, centred in y),
+                             the second along y; each arm has half the light
+                             and a plane of its own, so the sensor's intensity
+                             block is two N x N planes (arm x, then arm y).
+                             Slopes: s_x from arm x's images, s_y from arm y's,
+                             each over its own arm's mean flux (or the
+                             subaperture's, with PWFS_F_LOCAL_NORM).  FP32
+                             precision, per-sensor launches only; not with the
+                             detector stage                                  */
 };
 
 /* Wavelengths per sensor.  A polychromatic sensor (Table 4: PolyCromPyramid)

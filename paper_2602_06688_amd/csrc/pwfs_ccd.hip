@@ -214,6 +214,7 @@ struct DetGeom {
 
 int det_geometry(const SensorPlan& sp, const pwfs_ccd_desc* d, bool aligned, DetGeom& out) {
   const Geometry& g = sp.g;
+  if (sp.arms != 1) return cfail(PWFS_EUNSUPPORTED, "the detector stage takes four-face pyramid sensors");
   if (d->n_det < 1 || d->rebin < 1 || d->rebin_den < 0 || d->rebin_den > 64)
     return cfail(PWFS_EINVAL, "bad detector size or rebin");
   const int num = d->rebin, den = d->rebin_den ? d->rebin_den : 1;

@@ -19,7 +19,9 @@ enum Region {
 
 struct Geometry {
   int D, N, n, b, S, o;   // pupil, transform, subapertures, block, separation, pad offset
-  int win_lo, win_hi;     // first row/column of the two image windows
+  int Sx, Sy;             // image separation along x and y (S and S; a roof arm has 0 on one axis)
+  int win_lo, win_hi;     // first column of the two image windows (one window when Sx = 0)
+  int wy_lo, wy_hi;       // first row of the two image windows (one window when Sy = 0)
   int full, Nc, Dp;       // full-plane mode, columns kept by the row pass, padded D
   int n_mod, n_lam, n_a;  // modulation points, wavelengths, distinct cosines
   int qmax;               // non-zero first-stage inputs per butterfly
@@ -28,6 +30,8 @@ struct Geometry {
 struct SensorPlan {
   pwfs_sensor_desc desc;
   Geometry g;
+  int arms = 1;           // 2 for a double roof: arm x, then arm y, one plane each
+  Geometry arm_g[2];
   void* dev[kRegions];
   int n_valid;
   double sumA2;
@@ -49,6 +53,8 @@ struct TiltPoint {
 };
 void tilt_points(const pwfs_sensor_desc& d, std::vector<TiltPoint>& pts, std::vector<double>& key_tx);
 Geometry geometry(const pwfs_sensor_desc& d);
+Geometry arm_geometry(const pwfs_sensor_desc& d, int arm);
+inline int sensor_arms(const pwfs_sensor_desc& d) { return (d.flags & PWFS_F_DOUBLE_ROOF) ? 2 : 1; }
 void set_last_error(const char* msg);   // message returned by pwfs_last_error
 void pupil_and_valid(const pwfs_sensor_desc& d, std::vector<float>& A, std::vector<uint8_t>& V);
 int fft_lanes(int N);

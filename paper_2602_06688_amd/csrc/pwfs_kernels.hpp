@@ -75,7 +75,8 @@ struct ColArgs {
   float* out;              // sensor's first frame of the chunk; frame stride out_stride
   long long out_stride;
   int D, Dp, Nc, n_a, n_lam, n_mod, colblocks;
-  int win_lo, win_hi, full;
+  int win_lo, win_hi, full;   // column windows (as in the row pass)
+  int wy_lo, wy_hi;           // row windows
 };
 
 struct SlopeArgs {
@@ -86,6 +87,7 @@ struct SlopeArgs {
   const float* ref;        // [2][n][n] or nullptr
   long long in_stride, slope_stride, flux_stride;
   int N, n, b, img, n_valid, local_norm;   // b = img / n (whole subapertures)
+  int roof;                // double roof: s_x from images 0, 1, s_y from 2, 3, each over its arm's flux
   int org_r[4], org_c[4];  // image origins
 };
 
@@ -449,7 +451,7 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
 #pragma unroll
   for (int s = 0; s < V; ++s) {
     const int Y = space_index<N>(t, s);
-    const bool keep = p.full || window_index(Y, p.D, p.win_lo, p.win_hi) >= 0;
+    const bool keep = p.full || window_index(Y, p.D, p.wy_lo, p.wy_hi) >= 0;
     if (keep) out[(size_t)Y * N + X] = acc[s];
   }
 }
@@ -472,6 +474,7 @@ template <int NT, int BB>
 __global__ __launch_bounds__(NT) void k_slopes(SlopeArgs p) {
   extern __shared__ float s_q[];        // [4][n*n]
   __shared__ double s_red[NT];
+  __shared__ double s_red2[NT];
   const int tid = threadIdx.x, f = blockIdx.x;
   const int nn = p.n * p.n;
   const float* I = p.in + (long long)f * p.in_stride;
@@ -514,25 +517,44 @@ __global__ __launch_bounds__(NT) void k_slopes(SlopeArgs p) {
     s_q[it] = acc;
   }
   __syncthreads();
-  double tsum = 0.0;
+  // valid-subaperture flux in float64: all four images (pyramid), or arm x
+  // (images 0, 1) and arm y (images 2, 3) apart (double roof)
+  double tsum = 0.0, tsum2 = 0.0;
   for (int s = tid; s < nn; s += NT)
-    if (p.valid[s]) tsum += (double)(((s_q[s] + s_q[nn + s]) + s_q[2 * nn + s]) + s_q[3 * nn + s]);
+    if (p.valid[s]) {
+      if (p.roof) {
+        tsum += (double)(s_q[s] + s_q[nn + s]);
+        tsum2 += (double)(s_q[2 * nn + s] + s_q[3 * nn + s]);
+      } else {
+        tsum += (double)(((s_q[s] + s_q[nn + s]) + s_q[2 * nn + s]) + s_q[3 * nn + s]);
+      }
+    }
   s_red[tid] = tsum;
+  s_red2[tid] = tsum2;
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
-    if (tid < w) s_red[tid] += s_red[tid + w];
+    if (tid < w) {
+      s_red[tid] += s_red[tid + w];
+      s_red2[tid] += s_red2[tid + w];
+    }
     __syncthreads();
   }
-  const double flux = s_red[0];
-  const float gnorm = (float)(flux / (double)p.n_valid);
+  const double flux = p.roof ? s_red[0] + s_red2[0] : s_red[0];
+  const float gnorm = (float)((p.roof ? s_red[0] : flux) / (double)p.n_valid);
+  const float gnorm_y = p.roof ? (float)(s_red2[0] / (double)p.n_valid) : gnorm;
   float* out = p.slopes + (long long)f * p.slope_stride;
   for (int s = tid; s < nn; s += NT) {
     float sx = 0.f, sy = 0.f;
     if (p.valid[s]) {
       const float q0 = s_q[s], q1 = s_q[nn + s], q2 = s_q[2 * nn + s], q3 = s_q[3 * nn + s];
-      const float den = p.local_norm ? (q0 + q1 + q2 + q3) : gnorm;
-      sx = ((q0 + q2) - (q1 + q3)) / den;
-      sy = ((q0 + q1) - (q2 + q3)) / den;
+      if (p.roof) {
+        sx = (q0 - q1) / (p.local_norm ? (q0 + q1) : gnorm);
+        sy = (q2 - q3) / (p.local_norm ? (q2 + q3) : gnorm_y);
+      } else {
+        const float den = p.local_norm ? (q0 + q1 + q2 + q3) : gnorm;
+        sx = ((q0 + q2) - (q1 + q3)) / den;
+        sy = ((q0 + q1) - (q2 + q3)) / den;
+      }
       if (p.ref) {
         sx -= p.ref[s];
         sy -= p.ref[nn + s];

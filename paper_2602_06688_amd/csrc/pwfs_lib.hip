@@ -66,7 +66,7 @@ int validate_one(const pwfs_sensor_desc& d, int idx) {
     if ((long long)d.n_mod * (1 + 3LL * d.src_rings * (d.src_rings + 1)) > 8192)
       return bad("modulation points x source points must be <= 8192");
   }
-  if (d.flags & ~uint32_t(PWFS_F_REF_SLOPES | PWFS_F_FULL_PLANE | PWFS_F_LOCAL_NORM))
+  if (d.flags & ~uint32_t(PWFS_F_REF_SLOPES | PWFS_F_FULL_PLANE | PWFS_F_LOCAL_NORM | PWFS_F_DOUBLE_ROOF))
     return bad("unknown flag bits");
   if (d.n_pupil < 4 || (d.n_pupil & 1)) return bad("n_pupil must be even and >= 4");
   if (d.n_fft < d.n_pupil) return bad("n_fft must be >= n_pupil");
@@ -95,6 +95,8 @@ int validate_one(const pwfs_sensor_desc& d, int idx) {
   if (d.n_subap > 64) return fail(PWFS_EUNSUPPORTED, "sensor %d: n_subap > 64 not supported", idx);
   if (!supported_fft(d.n_fft))
     return fail(PWFS_EUNSUPPORTED, "sensor %d: n_fft %d has no radix plan (64,128,256,384,512,768)", idx, d.n_fft);
+  if ((d.flags & PWFS_F_DOUBLE_ROOF) && d.precision != PWFS_FP32)
+    return fail(PWFS_EUNSUPPORTED, "sensor %d: the double roof runs in FP32 precision only", idx);
   if (d.precision != PWFS_FP32 && !mfma_supported(d))
     return fail(PWFS_EUNSUPPORTED, "sensor %d: this precision is not supported for these sizes", idx);
   // at least one valid subaperture
@@ -199,9 +201,12 @@ Geometry geometry(const pwfs_sensor_desc& d) {
   g.n = d.n_subap;
   g.b = g.D / g.n;
   g.S = (int)std::lround(d.pupil_sep_px);
+  g.Sx = g.Sy = g.S;
   g.o = (g.N - g.D) / 2;
   g.win_lo = g.N / 2 - g.S / 2 - g.D / 2;
   g.win_hi = g.N / 2 + g.S / 2 - g.D / 2;
+  g.wy_lo = g.win_lo;
+  g.wy_hi = g.win_hi;
   g.full = (d.flags & PWFS_F_FULL_PLANE) ? 1 : 0;
   g.Nc = g.full ? g.N : 2 * g.D;
   g.Dp = (g.D + 15) & ~15;
@@ -218,6 +223,21 @@ Geometry geometry(const pwfs_sensor_desc& d) {
   return g;
 }
 
+// one arm of a double roof: arm 0 splits along x (images S apart in x, one
+// window in y), arm 1 along y; a zero separation on an axis leaves that
+// axis's transform pair the identity and its single window at the centre
+Geometry arm_geometry(const pwfs_sensor_desc& d, int arm) {
+  Geometry g = geometry(d);
+  g.Sx = arm == 0 ? g.S : 0;
+  g.Sy = arm == 0 ? 0 : g.S;
+  g.win_lo = g.N / 2 - g.Sx / 2 - g.D / 2;
+  g.win_hi = g.N / 2 + g.Sx / 2 - g.D / 2;
+  g.wy_lo = g.N / 2 - g.Sy / 2 - g.D / 2;
+  g.wy_hi = g.N / 2 + g.Sy / 2 - g.D / 2;
+  if (!g.full) g.Nc = g.Sx ? 2 * g.D : g.D;
+  return g;
+}
+
 // bytes of each per-sensor region, in workspace order
 static void sensor_regions(const pwfs_sensor_desc& d, size_t out[kRegions]) {
   const Geometry g = geometry(d);
@@ -226,12 +246,13 @@ static void sensor_regions(const pwfs_sensor_desc& d, size_t out[kRegions]) {
   out[R_RX] = sizeof(float2) * g.n_lam * g.n_a * g.D;
   out[R_RY] = sizeof(float2) * g.n_lam * g.n_mod * g.D;
   out[R_AK] = sizeof(int) * 2 * g.n_mod;
-  out[R_MROW] = sizeof(float2) * g.N;
-  out[R_MCOL] = sizeof(float2) * g.n_lam * g.N;
+  const int arms = sensor_arms(d);
+  out[R_MROW] = sizeof(float2) * arms * g.N;
+  out[R_MCOL] = sizeof(float2) * arms * g.n_lam * g.N;
   out[R_TW] = sizeof(float2) * g.N;
   out[R_VALID] = (size_t)g.n * g.n;
   out[R_REF] = sizeof(float) * 2 * g.n * g.n;
-  out[R_REFINT] = ref ? sizeof(float) * g.N * g.N : 0;
+  out[R_REFINT] = ref ? sizeof(float) * arms * g.N * g.N : 0;
   out[R_ZERO] = ref ? sizeof(float) * g.D * g.D : 0;
   out[R_MFMA] = mfma_table_bytes(d);
 }
@@ -327,9 +348,9 @@ int layout(const pwfs_sensor_desc* s, int n, int max_frames, Layout* L) {
 static std::complex<double> cis(double a) { return {std::cos(a), std::sin(a)}; }
 
 // exp(i pi S |u_bar| / N) exp(-2 pi i u o / N) / N, phases reduced exactly
-static std::vector<double> mask_table(const Geometry& g, double extra_scale) {
+static std::vector<double> mask_table(const Geometry& g, int sep, double extra_scale) {
   std::vector<double> m(2 * (size_t)g.N);
-  const long long N = g.N, S = g.S;
+  const long long N = g.N, S = sep;
   for (long long u = 0; u < N; ++u) {
     // |u_bar| * 2 = |2u + 1| below N/2, |2u + 1 - 2N| above
     const long long twice = (u < N / 2) ? (2 * u + 1) : (2 * N - 2 * u - 1);
@@ -387,17 +408,22 @@ int upload_tables(const pwfs_sensor_desc& d, char* ws, const size_t* off, hipStr
     ak.push_back(k);
     ak.push_back(pts[k].key);
   }
-  std::vector<float> mrow(2 * (size_t)g.N), mcol(2 * (size_t)g.n_lam * g.N), tw(2 * (size_t)g.N);
-  {
-    const std::vector<double> m = mask_table(g, 1.0);
-    for (size_t i = 0; i < m.size(); ++i) mrow[i] = (float)m[i];
+  // masks per arm: the pyramid has one (S on both axes); a double roof has
+  // arm x (S along x, 0 along y) then arm y (0, S), each with half the light
+  const int arms = sensor_arms(d);
+  std::vector<float> mrow(2 * (size_t)arms * g.N), mcol(2 * (size_t)arms * g.n_lam * g.N), tw(2 * (size_t)g.N);
+  for (int a = 0; a < arms; ++a) {
+    const Geometry ga = arms == 2 ? arm_geometry(d, a) : g;
+    const double share = arms == 2 ? 0.5 : 1.0;
+    const std::vector<double> m = mask_table(ga, ga.Sx, 1.0);
+    for (size_t i = 0; i < m.size(); ++i) mrow[(size_t)a * 2 * g.N + i] = (float)m[i];
     for (int l = 0; l < g.n_lam; ++l) {
-      const double sc = std::sqrt(d.lambda_weight[l] / ((double)g.n_mod * sumA2));
-      const std::vector<double> mc = mask_table(g, sc);
-      for (size_t i = 0; i < mc.size(); ++i) mcol[(size_t)l * 2 * g.N + i] = (float)mc[i];
+      const double sc = std::sqrt(share * d.lambda_weight[l] / ((double)g.n_mod * sumA2));
+      const std::vector<double> mc = mask_table(ga, ga.Sy, sc);
+      for (size_t i = 0; i < mc.size(); ++i) mcol[((size_t)a * g.n_lam + l) * 2 * g.N + i] = (float)mc[i];
     }
-    for (int i = 0; i < g.N; ++i) put_c(tw, i, cis(-2.0 * kPi * i / g.N));
   }
+  for (int i = 0; i < g.N; ++i) put_c(tw, i, cis(-2.0 * kPi * i / g.N));
   auto up = [&](int region, const void* src, size_t bytes) -> int {
     if (!bytes) return PWFS_OK;
     keep.emplace_back((const char*)src, (const char*)src + bytes);
@@ -495,6 +521,8 @@ static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd
   ca.colblocks = (g.Nc + G - 1) / G;
   ca.win_lo = g.win_lo;
   ca.win_hi = g.win_hi;
+  ca.wy_lo = g.wy_lo;
+  ca.wy_hi = g.wy_hi;
   ca.full = g.full;
   pa.lds_cols = sizeof(float2) * ((PAL ? 0 : (size_t)N) + (size_t)G * BufLen<N>::value);
   pa.grid_cols = (unsigned)(nf * ca.colblocks);
@@ -544,7 +572,7 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
 
 // ------------------------------------------- persistent heterogeneous pass --
 bool hetero_eligible(const SensorPlan& sp) {
-  return sp.desc.precision == PWFS_FP32 && sp.g.qmax <= 3 && sp.g.N >= 256;
+  return sp.desc.precision == PWFS_FP32 && sp.g.qmax <= 3 && sp.g.N >= 256 && sp.arms == 1;
 }
 
 int forward_hetero(pwfs_plan_s* p, const float* opd, int f0, int nf, float* out, hipStream_t st) {
@@ -683,6 +711,7 @@ int slopes_launch_at(const SensorPlan& sp, const float* in, long long in_stride,
   const int b = (img % g.n) ? -1 : a.b;     // -1: subapertures cut pixels
   a.n_valid = sp.n_valid;
   a.local_norm = (sp.desc.flags & PWFS_F_LOCAL_NORM) ? 1 : 0;
+  a.roof = sp.arms == 2 ? 1 : 0;
   for (int q = 0; q < 4; ++q) {
     a.org_r[q] = org_r[q];
     a.org_c[q] = org_c[q];
@@ -714,12 +743,25 @@ int slopes_launch(const SensorPlan& sp, const float* in, long long in_stride, fl
                   float* flux, long long flux_stride, const float* ref, int nf, hipStream_t st, Prof* prof) {
   const Geometry& g = sp.g;
   int org_r[4], org_c[4];
-  int q = 0;
-  for (int sy = -1; sy <= 1; sy += 2)
-    for (int sx = -1; sx <= 1; sx += 2, ++q) {
-      org_r[q] = g.N / 2 + sy * g.S / 2 - g.D / 2;
-      org_c[q] = g.N / 2 + sx * g.S / 2 - g.D / 2;
+  if (sp.arms == 2) {
+    // the two planes as one 2N x N array: arm x's images left and right of
+    // centre in plane 0, arm y's above and below in plane 1
+    const int c = g.N / 2 - g.D / 2;
+    for (int q = 0; q < 2; ++q) {
+      const int sgn = q ? 1 : -1;
+      org_r[q] = c;
+      org_c[q] = g.N / 2 + sgn * g.S / 2 - g.D / 2;
+      org_r[2 + q] = g.N + g.N / 2 + sgn * g.S / 2 - g.D / 2;
+      org_c[2 + q] = c;
     }
+  } else {
+    int q = 0;
+    for (int sy = -1; sy <= 1; sy += 2)
+      for (int sx = -1; sx <= 1; sx += 2, ++q) {
+        org_r[q] = g.N / 2 + sy * g.S / 2 - g.D / 2;
+        org_c[q] = g.N / 2 + sx * g.S / 2 - g.D / 2;
+      }
+  }
   return slopes_launch_at(sp, in, in_stride, slopes, slope_stride, flux, flux_stride, ref, nf, g.N, g.D, org_r, org_c,
                           st, prof);
 }
@@ -797,6 +839,8 @@ int pwfs_plan(const pwfs_sensor_desc* s, int n, int max_frames, void* ws, size_t
     SensorPlan sp;
     sp.desc = s[i];
     sp.g = geometry(s[i]);
+    sp.arms = sensor_arms(s[i]);
+    for (int a = 0; a < sp.arms; ++a) sp.arm_g[a] = arm_geometry(s[i], a);
     for (int r = 0; r < kRegions; ++r) sp.dev[r] = (char*)ws + L.offsets[(size_t)i * kRegions + r];
     sp.rbuf = (float2*)((char*)ws + L.sensor_rbuf[i]);
     std::vector<float> A;
@@ -809,7 +853,7 @@ int pwfs_plan(const pwfs_sensor_desc* s, int n, int max_frames, void* ws, size_t
     sp.int_offset = inten;
     sp.slope_offset = sl;
     opd += (size_t)sp.g.D * sp.g.D;
-    inten += (size_t)sp.g.N * sp.g.N;
+    inten += (size_t)sp.arms * sp.g.N * sp.g.N;
     sl += 2 * (size_t)sp.g.n * sp.g.n;
     if ((rc = upload_tables(s[i], (char*)ws, &L.offsets[(size_t)i * kRegions], st, keep, &sp.sumA2))) {
       (void)hipStreamSynchronize(st);
@@ -883,7 +927,8 @@ int pwfs_set_tuning(pwfs_plan_t p, const pwfs_tuning* t) {
     if ((int)p->s.size() > kMaxHetero) return fail(PWFS_EUNSUPPORTED, "persistent mode takes at most 8 sensors");
     for (const SensorPlan& sp : p->s)
       if (!hetero_eligible(sp))
-        return fail(PWFS_EUNSUPPORTED, "persistent mode needs FP32 sensors with N >= 256 and few non-zero first-stage inputs");
+        return fail(PWFS_EUNSUPPORTED,
+                    "persistent mode needs FP32 pyramid sensors with N >= 256 and few non-zero first-stage inputs");
   }
   p->tune = *t;
   p->tune.max_chunk = p->max_chunk;
@@ -995,6 +1040,20 @@ int forward_sensor(pwfs_plan_s* p, int i, const float* opd, long long opd_stride
     const float* o = opd + (long long)f0 * opd_stride;
     float* r = out + (long long)f0 * out_stride;
     int rc;
+    if (sp.arms == 2) {
+      // double roof: each arm is a pass of its own with its masks and windows,
+      // into its own plane; the two share the pass scratch in stream order
+      for (int a = 0; a < 2; ++a) {
+        SensorPlan arm = sp;
+        arm.g = sp.arm_g[a];
+        arm.dev[R_MROW] = (char*)sp.dev[R_MROW] + sizeof(float2) * (size_t)a * sp.g.N;
+        arm.dev[R_MCOL] = (char*)sp.dev[R_MCOL] + sizeof(float2) * (size_t)a * sp.g.n_lam * sp.g.N;
+        rc = forward_fp32(arm, o, opd_stride, r + (size_t)a * sp.g.N * sp.g.N, out_stride, n, sp.rbuf, st,
+                          &p->prof);
+        if (rc) return rc;
+      }
+      continue;
+    }
     if (sp.desc.precision == PWFS_FP32)
       rc = forward_fp32(sp, o, opd_stride, r, out_stride, n, sp.rbuf, st, &p->prof);
     else

@@ -27,6 +27,7 @@ PWFS_ESTATE = -5
 F_REF_SLOPES = 1
 F_FULL_PLANE = 2
 F_LOCAL_NORM = 4
+F_DOUBLE_ROOF = 8
 
 FP32, BF16, BF16X3, FP16X3 = 0, 1, 2, 3
 MAX_LAMBDA = 16
@@ -289,7 +290,9 @@ class Plan:
         import torch
         if self._single():
             N = self.info[0].n_fft
-            return torch.zeros((n_frames, N, N), dtype=torch.float32, device=self.device)
+            planes = self.intensity_stride // (N * N)      # 2 for a double roof
+            shape = (n_frames, N, N) if planes == 1 else (n_frames, planes, N, N)
+            return torch.zeros(shape, dtype=torch.float32, device=self.device)
         return torch.zeros((n_frames, self.intensity_stride), dtype=torch.float32, device=self.device)
 
     def new_slopes(self, n_frames: int):

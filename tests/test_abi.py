@@ -51,6 +51,8 @@ def _bad(**kw):
     (dict(src_rings=2, src_radius_lod=-0.5), P.PWFS_EINVAL),
     (dict(src_rings=8, src_radius_lod=1.0, n_mod=64), P.PWFS_EINVAL),         # > 8192 points
     (dict(src_rings=1, src_radius_lod=1.0, precision=2), P.PWFS_EUNSUPPORTED),  # matrix-core form
+    (dict(flags=9, precision=2), P.PWFS_EUNSUPPORTED),                           # double roof: FP32 only
+    (dict(flags=16), P.PWFS_EINVAL),
 ])
 def test_validate_rejects(kw, code):
     assert P.validate([_bad(**kw)]) == code
@@ -64,7 +66,8 @@ def test_validate_accepts_edge_sensors():
                       lambdas_nm=(600.0, 750.0, 900.0, 1000.0), lambda_weights=(0.1, 0.2, 0.3, 0.4)),
           tiny_sensor(n_pupil=64, n_fft=128, n_subap=16, pupil_sep_px=64.0, n_mod=5,
                       lambdas_nm=band_sampling(750.0, 300.0, 16)[0],
-                      lambda_weights=band_sampling(750.0, 300.0, 16)[1])]
+                      lambda_weights=band_sampling(750.0, 300.0, 16)[1]),
+          tiny_sensor(n_pupil=64, n_fft=128, n_subap=16, pupil_sep_px=64.0, n_mod=8, flags=9)]
     for s in ok:
         assert P.validate([s]) == P.PWFS_OK, P.lib().pwfs_last_error()
 
