@@ -181,6 +181,23 @@ def forward_frame(opd_nm: np.ndarray, s, mask: np.ndarray | None = None) -> np.n
     return _modulated(opd_nm, s, m, m)
 
 
+def field_stop(s, lam: float) -> np.ndarray:
+    """Transmission of the square field stop along one focal axis at
+    wavelength lam (1 everywhere without one).  The stop is a fixed sky
+    angle, fov_lod lambda/D at lambda_ref; at lam its side in samples is
+    side = ((fov_lod * (lambda_ref / lam)) * N) / D, and sample u passes when
+    2 |u_bar| <= side (the square is centred on the apex, at the corner of the
+    four central samples).  The paper names a field of view (Appendix B,
+    'fov') but not the stop's shape; square is the reading, which keeps the
+    mask separable."""
+    N, D = s.n_fft, s.n_pupil
+    fov = float(getattr(s, "fov_lod", 0.0))
+    if fov <= 0.0:
+        return np.ones(N)
+    side = ((fov * (s.lambda_ref_nm / lam)) * N) / D
+    return (2.0 * np.abs(focal_coords(N)) <= side).astype(np.float64)
+
+
 def _modulated(opd_nm: np.ndarray, s, m_x: np.ndarray, m_y: np.ndarray) -> np.ndarray:
     D, N = s.n_pupil, s.n_fft
     A = pupil_amplitude(D, s.obstruction)
@@ -193,12 +210,14 @@ def _modulated(opd_nm: np.ndarray, s, m_x: np.ndarray, m_y: np.ndarray) -> np.nd
         E0 = A * np.exp(1j * 2.0 * np.pi * opd / lam)
         sc = s.lambda_ref_nm / lam
         r = s.mod_radius_lod * sc
+        stop = field_stop(s, lam)
+        mx, my = m_x * stop, m_y * stop
         acc = np.zeros((N, N), np.float64)
         for t in th:
             Em = E0 * modulation_ramp(D, r, t)
             for dx, dy in src:
                 Ep = Em if (dx == 0.0 and dy == 0.0) else Em * tilt_ramp(D, sc * dx, sc * dy)
-                e = pyramid_image(Ep, N, m_x, m_y)
+                e = pyramid_image(Ep, N, mx, my)
                 acc += e.real ** 2 + e.imag ** 2
         I += w * acc / (s.n_mod * len(src) * sA2)
     return I
@@ -233,7 +252,7 @@ def separable_operator(n_fft: int, n_pupil: int, pupil_sep: float) -> np.ndarray
 def forward_frame_separable(opd_nm: np.ndarray, s) -> np.ndarray:
     """The same intensity as ``forward_frame`` through e_k = P (E o R_k) P^T
     (point sources only)."""
-    if int(getattr(s, "src_rings", 0)) > 0 or is_double_roof(s):
+    if int(getattr(s, "src_rings", 0)) > 0 or is_double_roof(s) or float(getattr(s, "fov_lod", 0.0)) > 0.0:
         raise ValueError("the separable form is written for a four-face pyramid and a point source")
     D, N = s.n_pupil, s.n_fft
     A = pupil_amplitude(D, s.obstruction)

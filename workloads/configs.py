@@ -47,6 +47,7 @@ class SensorDesc:
     flags: int = FLAG_REF_SLOPES
     src_rings: int = 0           # extended source: rings sampling a uniform disk (0 = point source)
     src_radius_lod: float = 0.0  # extended-source radius in lambda/D at lambda_ref
+    fov_lod: float = 0.0         # square field stop, side in lambda/D at lambda_ref (0 = none)
 
     @property
     def n_lambda(self) -> int:
