@@ -254,7 +254,8 @@ def soul_form(P, torch, dev, stream, steps: int, frames: int = 1000, distinct: i
     """The SOUL pyramid of Appendix B as one chain: 220 px pupil (8.22 m),
     40 x 40 subapertures of 5.5 px, pupils 48 subapertures apart, 3 lambda/D
     modulation at 750 nm sampled by 24 points (Table 2: 24 transforms per
-    step) on a 768 grid (the paper pads to 660); a 120 x 120 detector of 5.5
+    step), a 2.0 arcsec field stop, on a 768 grid (the paper pads to 660); a
+    120 x 120 detector of 5.5
     transform pixels per pixel with photon and readout noise (magnitude 8,
     300 nm, 0.588 ms, QE 0.32, 0.4 e-); slopes on detector pixels.
     frames/s of the chain over `frames` frames (`distinct` screens at 0.8
@@ -263,8 +264,10 @@ def soul_form(P, torch, dev, stream, steps: int, frames: int = 1000, distinct: i
     from fractions import Fraction
     from workloads import FLAG_REF_SLOPES, tiny_sensor, von_karman_opd
     from workloads.configs import photo_electrons
+    # field stop: the listing's 2.0 arcsec as lambda/D at 750 nm on 8.222 m
+    fov = 2.0 / (750e-9 / 8.222 * 206264.806)
     s = tiny_sensor(n_pupil=220, n_fft=768, n_subap=40, pupil_sep_px=264.0, n_mod=24, mod_radius_lod=3.0,
-                    diameter_m=8.222, flags=FLAG_REF_SLOPES)
+                    diameter_m=8.222, fov_lod=fov, flags=FLAG_REF_SLOPES)
     scr = von_karman_opd(distinct, 220, 8.222, 0.126, 40.0, seed=70, grid=512)
     x = torch.from_numpy(np.ascontiguousarray(np.tile(scr, (frames // distinct, 1, 1)))).to(dev)
     plan = P.Plan([s], max_frames=frames, device=dev)
@@ -297,7 +300,8 @@ def soul_form(P, torch, dev, stream, steps: int, frames: int = 1000, distinct: i
     print(f"# SOUL chain: {fs:.0f} frames/s ({a:.1f} TFLOP/s nominal), ms per step {kms}", file=sys.stderr,
           flush=True)
     return {"value": round(fs, 1), "unit": "frames/s", "ms_per_step": round(dt * 1e3, 4),
-            "workload": "SOUL pyramid: 220 px, 40x40 subap (5.5 px), 24 points at 3 lambda/D, N=768; "
+            "workload": "SOUL pyramid: 220 px, 40x40 subap (5.5 px), 24 points at 3 lambda/D, 2.0 arcsec "
+                        "square field stop, N=768; "
                         "120 px detector at 11/2 transform px per px, photon + readout noise; detector slopes",
             "frames_per_step": frames, "electrons_per_frame": round(el, 1), "kernel_ms_per_step": kms,
             "roofline_path": {"bound": "alu", "achieved": round(a, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -117,6 +117,12 @@ typedef struct {
   double lambda_nm[PWFS_MAX_LAMBDA];      /* sensing wavelengths, > 0          */
   double lambda_weight[PWFS_MAX_LAMBDA];  /* >= 0, summing to 1 (to 1e-9)      */
   double src_radius_lod;  /* extended-source radius in lambda/D at lambda_ref  */
+  double fov_lod;         /* field stop: a square of side fov_lod lambda/D at
+                             lambda_ref (a fixed sky angle) centred on the apex,
+                             0 = none.  At wavelength l its side in focal samples
+                             is side = ((fov_lod * (lambda_ref / l)) * N) / D
+                             (float64, in that order); sample u passes when
+                             2 |u_bar| <= side, on both axes.  FP32 only       */
 } pwfs_sensor_desc;
 
 /* What a plan reports about one of its sensors. */

@@ -59,7 +59,7 @@ struct FieldArgs {
 struct RowArgs {
   const float2* field;     // [frames][n_lam][D][D] pupil field A exp(i phi)
   const float2* rx;        // [n_lam][n_a][D] row tilt (modulation x-part, half-pixel tilt)
-  const float2* mrow;      // [N] row mask with pupil-offset phase and 1/N
+  const float2* mrow;      // [n_lam][N] row mask with pupil-offset phase and 1/N
   const float2* tw;        // [N] exp(-2 pi i n / N)
   float2* rbuf;            // [frames][n_lam][n_a][Nc][Dp]
   int D, Dp, Nc, n_a, n_lam, n_la, ag, n_agroups, rowblocks;
@@ -169,12 +169,12 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
   constexpr int RW = RowTile<N>::RW, RPG = RW / G, BL = BufLen<N>::value, NL = NB0 * QM;
   static_assert(RPG >= 1 && RW % G == 0, "row tile");
 
-  // palindromic plans take twiddles and mask straight into registers; the
-  // others keep both tables in LDS
+  // palindromic plans take twiddles straight into registers; the others keep
+  // the twiddle table in LDS.  The row mask of each wavelength goes from its
+  // table to registers as the wavelength starts.
   constexpr bool PAL = Palindromic<N>::value;
   float2* s_tw = smem;
-  float2* s_m = s_tw + (PAL ? 0 : N);
-  float2* s_buf = s_m + (PAL ? 0 : N);
+  float2* s_buf = s_tw + (PAL ? 0 : N);
   float2* s_tile = s_buf + G * BL;
 
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
@@ -189,16 +189,12 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
   FftPair<N, QM> fp;
   if constexpr (PAL) {
     fp.init(t, s_buf + g * BL, p.tw);
-    fp.set_mask(p.mrow);
   } else {
-    for (int i = tid; i < N; i += kBlock) {
-      s_tw[i] = p.tw[i];
-      s_m[i] = p.mrow[i];
-    }
+    for (int i = tid; i < N; i += kBlock) s_tw[i] = p.tw[i];
     __syncthreads();
     fp.init(t, s_buf + g * BL, s_tw);
-    fp.set_mask(s_m);
   }
+  int lam_mask = -1;
 
   // this lane's input columns
   int xx[NL];
@@ -233,6 +229,10 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
 
   for (int la = la0; la < la1; ++la) {
     const int lam = la / p.n_a, a = la % p.n_a;
+    if (lam != lam_mask) {
+      fp.set_mask(p.mrow + (size_t)lam * N);
+      lam_mask = lam;
+    }
     const float2* e0 = p.field + ((size_t)f * p.n_lam + lam) * p.D * p.D;
     if (!HOLD || lam != lam_loaded) {
 #pragma unroll

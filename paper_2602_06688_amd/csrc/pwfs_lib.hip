@@ -66,6 +66,7 @@ int validate_one(const pwfs_sensor_desc& d, int idx) {
     if ((long long)d.n_mod * (1 + 3LL * d.src_rings * (d.src_rings + 1)) > 8192)
       return bad("modulation points x source points must be <= 8192");
   }
+  if (!(d.fov_lod >= 0.0) || !std::isfinite(d.fov_lod)) return bad("fov_lod must be finite and >= 0");
   if (d.flags & ~uint32_t(PWFS_F_REF_SLOPES | PWFS_F_FULL_PLANE | PWFS_F_LOCAL_NORM | PWFS_F_DOUBLE_ROOF))
     return bad("unknown flag bits");
   if (d.n_pupil < 4 || (d.n_pupil & 1)) return bad("n_pupil must be even and >= 4");
@@ -95,6 +96,8 @@ int validate_one(const pwfs_sensor_desc& d, int idx) {
   if (d.n_subap > 64) return fail(PWFS_EUNSUPPORTED, "sensor %d: n_subap > 64 not supported", idx);
   if (!supported_fft(d.n_fft))
     return fail(PWFS_EUNSUPPORTED, "sensor %d: n_fft %d has no radix plan (64,128,256,384,512,768)", idx, d.n_fft);
+  if (d.fov_lod > 0.0 && d.precision != PWFS_FP32)
+    return fail(PWFS_EUNSUPPORTED, "sensor %d: the field stop runs in FP32 precision only", idx);
   if ((d.flags & PWFS_F_DOUBLE_ROOF) && d.precision != PWFS_FP32)
     return fail(PWFS_EUNSUPPORTED, "sensor %d: the double roof runs in FP32 precision only", idx);
   if (d.precision != PWFS_FP32 && !mfma_supported(d))
@@ -247,7 +250,7 @@ static void sensor_regions(const pwfs_sensor_desc& d, size_t out[kRegions]) {
   out[R_RY] = sizeof(float2) * g.n_lam * g.n_mod * g.D;
   out[R_AK] = sizeof(int) * 2 * g.n_mod;
   const int arms = sensor_arms(d);
-  out[R_MROW] = sizeof(float2) * arms * g.N;
+  out[R_MROW] = sizeof(float2) * arms * g.n_lam * g.N;
   out[R_MCOL] = sizeof(float2) * arms * g.n_lam * g.N;
   out[R_TW] = sizeof(float2) * g.N;
   out[R_VALID] = (size_t)g.n * g.n;
@@ -347,13 +350,18 @@ int layout(const pwfs_sensor_desc* s, int n, int max_frames, Layout* L) {
 // ------------------------------------------------------ float64 tables ---
 static std::complex<double> cis(double a) { return {std::cos(a), std::sin(a)}; }
 
-// exp(i pi S |u_bar| / N) exp(-2 pi i u o / N) / N, phases reduced exactly
-static std::vector<double> mask_table(const Geometry& g, int sep, double extra_scale) {
+// exp(i pi S |u_bar| / N) exp(-2 pi i u o / N) / N, phases reduced exactly;
+// zero where 2 |u_bar| > stop (the field stop's side in samples, < 0: none)
+static std::vector<double> mask_table(const Geometry& g, int sep, double extra_scale, double stop) {
   std::vector<double> m(2 * (size_t)g.N);
   const long long N = g.N, S = sep;
   for (long long u = 0; u < N; ++u) {
     // |u_bar| * 2 = |2u + 1| below N/2, |2u + 1 - 2N| above
     const long long twice = (u < N / 2) ? (2 * u + 1) : (2 * N - 2 * u - 1);
+    if (stop >= 0.0 && (double)twice > stop) {
+      m[2 * u] = m[2 * u + 1] = 0.0;
+      continue;
+    }
     // mask phase pi S twice / (2N) = 2 pi (S twice) / (4N)
     const long long pm = (S * twice) % (4 * N);
     // offset phase -2 pi u o / N = -2 pi (4 u o) / (4N)
@@ -410,17 +418,22 @@ int upload_tables(const pwfs_sensor_desc& d, char* ws, const size_t* off, hipStr
   }
   // masks per arm: the pyramid has one (S on both axes); a double roof has
   // arm x (S along x, 0 along y) then arm y (0, S), each with half the light
+  // (the field stop, a fixed sky angle, is narrower in samples at longer
+  // wavelengths, so both tables are per wavelength)
   const int arms = sensor_arms(d);
-  std::vector<float> mrow(2 * (size_t)arms * g.N), mcol(2 * (size_t)arms * g.n_lam * g.N), tw(2 * (size_t)g.N);
+  std::vector<float> mrow(2 * (size_t)arms * g.n_lam * g.N), mcol(2 * (size_t)arms * g.n_lam * g.N);
+  std::vector<float> tw(2 * (size_t)g.N);
   for (int a = 0; a < arms; ++a) {
     const Geometry ga = arms == 2 ? arm_geometry(d, a) : g;
     const double share = arms == 2 ? 0.5 : 1.0;
-    const std::vector<double> m = mask_table(ga, ga.Sx, 1.0);
-    for (size_t i = 0; i < m.size(); ++i) mrow[(size_t)a * 2 * g.N + i] = (float)m[i];
     for (int l = 0; l < g.n_lam; ++l) {
+      const double stop = d.fov_lod > 0.0 ? ((d.fov_lod * (d.lambda_ref_nm / d.lambda_nm[l])) * g.N) / g.D : -1.0;
+      const size_t at = ((size_t)a * g.n_lam + l) * 2 * g.N;
+      const std::vector<double> m = mask_table(ga, ga.Sx, 1.0, stop);
+      for (size_t i = 0; i < m.size(); ++i) mrow[at + i] = (float)m[i];
       const double sc = std::sqrt(share * d.lambda_weight[l] / ((double)g.n_mod * sumA2));
-      const std::vector<double> mc = mask_table(ga, ga.Sy, sc);
-      for (size_t i = 0; i < mc.size(); ++i) mcol[((size_t)a * g.n_lam + l) * 2 * g.N + i] = (float)mc[i];
+      const std::vector<double> mc = mask_table(ga, ga.Sy, sc, stop);
+      for (size_t i = 0; i < mc.size(); ++i) mcol[at + i] = (float)mc[i];
     }
   }
   for (int i = 0; i < g.N; ++i) put_c(tw, i, cis(-2.0 * kPi * i / g.N));
@@ -501,7 +514,7 @@ static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd
   ra.win_hi = g.win_hi;
   ra.full = g.full;
   constexpr bool PAL = Palindromic<N>::value;   // tables in registers, not LDS
-  pa.lds_rows = sizeof(float2) * ((PAL ? 0 : 2 * N) + G * BufLen<N>::value + (size_t)g.Nc * RW + T);
+  pa.lds_rows = sizeof(float2) * ((PAL ? 0 : N) + G * BufLen<N>::value + (size_t)g.Nc * RW + T);
   pa.grid_rows = (unsigned)((long long)nf * ra.rowblocks * ra.n_agroups);
 
   ColArgs& ca = pa.ca;
@@ -1046,7 +1059,7 @@ int forward_sensor(pwfs_plan_s* p, int i, const float* opd, long long opd_stride
       for (int a = 0; a < 2; ++a) {
         SensorPlan arm = sp;
         arm.g = sp.arm_g[a];
-        arm.dev[R_MROW] = (char*)sp.dev[R_MROW] + sizeof(float2) * (size_t)a * sp.g.N;
+        arm.dev[R_MROW] = (char*)sp.dev[R_MROW] + sizeof(float2) * (size_t)a * sp.g.n_lam * sp.g.N;
         arm.dev[R_MCOL] = (char*)sp.dev[R_MCOL] + sizeof(float2) * (size_t)a * sp.g.n_lam * sp.g.N;
         rc = forward_fp32(arm, o, opd_stride, r + (size_t)a * sp.g.N * sp.g.N, out_stride, n, sp.rbuf, st,
                           &p->prof);

@@ -48,7 +48,7 @@ class CSensorDesc(ctypes.Structure):
         ("pupil_sep_px", ctypes.c_double), ("mod_radius_lod", ctypes.c_double),
         ("lambda_ref_nm", ctypes.c_double),
         ("lambda_nm", ctypes.c_double * MAX_LAMBDA), ("lambda_weight", ctypes.c_double * MAX_LAMBDA),
-        ("src_radius_lod", ctypes.c_double),
+        ("src_radius_lod", ctypes.c_double), ("fov_lod", ctypes.c_double),
     ]
 
 
@@ -195,6 +195,7 @@ def to_c(s) -> CSensorDesc:
     d.flags = int(getattr(s, "flags", F_REF_SLOPES))
     d.src_rings = int(getattr(s, "src_rings", 0))
     d.src_radius_lod = float(getattr(s, "src_radius_lod", 0.0))
+    d.fov_lod = float(getattr(s, "fov_lod", 0.0))
     d.diameter_m = float(getattr(s, "diameter_m", 8.0))
     d.obstruction = float(s.obstruction)
     d.pupil_sep_px = float(s.pupil_sep_px)

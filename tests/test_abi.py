@@ -52,6 +52,8 @@ def _bad(**kw):
     (dict(src_rings=8, src_radius_lod=1.0, n_mod=64), P.PWFS_EINVAL),         # > 8192 points
     (dict(src_rings=1, src_radius_lod=1.0, precision=2), P.PWFS_EUNSUPPORTED),  # matrix-core form
     (dict(flags=9, precision=2), P.PWFS_EUNSUPPORTED),                           # double roof: FP32 only
+    (dict(fov_lod=20.0, precision=2), P.PWFS_EUNSUPPORTED),                      # field stop: FP32 only
+    (dict(fov_lod=-1.0), P.PWFS_EINVAL),
     (dict(flags=16), P.PWFS_EINVAL),
 ])
 def test_validate_rejects(kw, code):

@@ -205,17 +205,22 @@ def test_fractional_pitch_matches_oracle(label, flags, full):
     assert (sl.cpu().numpy()[:, :, ~valid] == 0).all()
 
 
+# the listing's 2.0 arcsec field of view as lambda/D at 750 nm on the 8.222 m pupil
+SOUL_FOV_LOD = 2.0 / (750e-9 / 8.222 * 206264.806)
+
+
 def test_soul_geometry_chain():
     """The SOUL pyramid of Appendix B: 220 px pupil, 40 subapertures of 5.5 px,
     pupils 48 subapertures apart, 3 lambda/D modulation at 750 nm with 24
-    points (Table 2: 24 transforms per step), read out on a 120 x 120
-    detector of 5.5 transform pixels (on a 768 grid here).  Two frames:
+    points (Table 2: 24 transforms per step) behind a 2.0 arcsec square
+    field stop, read out on a 120 x 120 detector of 5.5 transform pixels (on
+    a 768 grid here).  Two frames:
     intensity, the sensor's own slopes (fractional subapertures), detector
     pixels and detector slopes, all against the oracle."""
     P = _P()
     from workloads import von_karman_opd
     s = tiny_sensor(n_pupil=220, n_fft=768, n_subap=40, pupil_sep_px=264.0, n_mod=24, mod_radius_lod=3.0,
-                    diameter_m=8.222, flags=FLAG_REF_SLOPES)
+                    diameter_m=8.222, fov_lod=SOUL_FOV_LOD, flags=FLAG_REF_SLOPES)
     opd = von_karman_opd(2, 220, 8.222, 0.126, 40.0, seed=31)
     x = torch.from_numpy(opd.astype(np.float32)).cuda()
     plan = P.Plan([s], max_frames=2)

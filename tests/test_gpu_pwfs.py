@@ -54,7 +54,7 @@ def _check(s, opd, plan_frames=None, label=""):
     valid = O.valid_subapertures(s)
     if s.flags & P.F_FULL_PLANE:
         e = O.intensity_rel_error(I, I_ref)
-        assert np.abs(I.sum(axis=(1, 2)) - 1.0).max() < 1e-5
+        assert np.abs(I.sum(axis=(1, 2)) - I_ref.sum(axis=(1, 2))).max() < 1e-5   # 1 without a field stop
     else:
         e = O.intensity_rel_error(_windows(I, s), _windows(I_ref, s))
     se = O.slope_rel_rms(sl, s_ref, valid) if np.linalg.norm(s_ref[:, :, valid]) > 0 else \
@@ -112,6 +112,12 @@ EDGE = {
     "subap_5p5": tiny_sensor(n_pupil=44, n_fft=128, n_subap=8, pupil_sep_px=66.0, n_mod=8, mod_radius_lod=2.0),
     "subap_64_over_15": tiny_sensor(n_pupil=64, n_fft=128, n_subap=15, pupil_sep_px=64.0, n_mod=6,
                                     obstruction=0.25, mod_radius_lod=2.0, flags=5),
+    # square field stops (a fixed sky angle: per-wavelength masks on both axes)
+    "stop_full": tiny_sensor(n_pupil=48, n_fft=128, n_subap=12, pupil_sep_px=56.0, n_mod=8, mod_radius_lod=3.0,
+                             fov_lod=7.0, flags=3),
+    "stop_poly_N384": tiny_sensor(n_pupil=120, n_fft=384, n_subap=30, pupil_sep_px=144.0, n_mod=4,
+                                  obstruction=0.28, mod_radius_lod=3.0, fov_lod=20.0,
+                                  lambdas_nm=(600.0, 750.0, 900.0), lambda_weights=(0.3, 0.4, 0.3)),
     # finely sampled bands: 16 wavelengths over 300 nm (palindromic plan, full
     # plane) and 7 on the radix-3 plan
     "poly16_full": tiny_sensor(n_pupil=64, n_fft=128, n_subap=16, pupil_sep_px=64.0, n_mod=8,
@@ -261,13 +267,13 @@ def test_extended_source_persistent_equals_launches():
 
 
 def test_polychromatic_batched_path_and_persistent():
-    """48 frames of a 10-wavelength sensor: enough column workgroups for the
-    batched column pass (the edge cases above run the split pass); the
-    persistent launch gives the same bits."""
+    """48 frames of a 10-wavelength sensor behind a field stop: enough column
+    workgroups for the batched column pass (the edge cases above run the
+    split pass); the persistent launch gives the same bits."""
     P = _P()
     lams, ws = band_sampling(750.0, 300.0, 10)
     s = tiny_sensor(n_pupil=80, n_fft=256, n_subap=20, pupil_sep_px=96.0, n_mod=8, mod_radius_lod=2.0,
-                    obstruction=0.2, lambdas_nm=lams, lambda_weights=ws)
+                    obstruction=0.2, lambdas_nm=lams, lambda_weights=ws, fov_lod=30.0)
     from workloads import von_karman_opd
     opd = von_karman_opd(48, s.n_pupil, 8.0, 0.5, 25.0, seed=29)
     plan, I0, S0 = _check(s, opd, label="10 wavelengths, 48 frames")
