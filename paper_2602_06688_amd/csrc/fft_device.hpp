@@ -281,15 +281,20 @@ struct StageTw {
   using SI = StageInfo<N, S, false>;
   static constexpr int T = FftPlan<N>::T;
   static constexpr int R = SI::R, L = SI::L, NB = (N / T) / SI::R;
-  float2 w[NB][R - 1];
+  // butterfly i of lane t uses k = (t + T i) mod L: the same k for every i
+  // when L divides T, so one set of twiddles serves all of them
+  static constexpr bool SAME = (T % L) == 0;
+  static constexpr int NW = SAME ? 1 : NB;
+  float2 w[NW][R - 1];
   __device__ __forceinline__ void load(int t, const float2* tw) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
+    for (int i = 0; i < NW; ++i) {
       const int k = (t + T * i) % L;
 #pragma unroll
       for (int q = 1; q < R; ++q) w[i][q - 1] = tw[k * q * (N / (L * R))];
     }
   }
+  __device__ __forceinline__ float2 at(int i, int q) const { return w[SAME ? 0 : i][q - 1]; }
 };
 
 template <int N>
@@ -318,7 +323,7 @@ __device__ __forceinline__ void stage_compute_reg(float2* v, const TW& tw) {
   for (int i = 0; i < NB; ++i) {
     if constexpr (S > 0) {
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[i * R + q] = twmul<INV>(v[i * R + q], tw.w[i][q - 1]);
+      for (int q = 1; q < R; ++q) v[i * R + q] = twmul<INV>(v[i * R + q], tw.at(i, q));
     }
     dftp<R, NZ, INV>(&v[i * R]);
   }

@@ -278,7 +278,7 @@ int choose_chunk(const pwfs_sensor_desc* s, int n, int max_frames) {
   // enough frames per pass that the column pass launches >= ~16384 workgroups
   // (16 rounds of the chip's resident workgroups, so a launch's tail is a
   // small part of it), with the scratch of one pass (all sensors) capped at
-  // 2 GiB
+  // 12 GiB (of the 288 GB of HBM)
   size_t per = 0;
   int want = 1;
   for (int i = 0; i < n; ++i) {
@@ -293,7 +293,7 @@ int choose_chunk(const pwfs_sensor_desc* s, int n, int max_frames) {
     }
     want = std::max(want, (16384 + colwg - 1) / colwg);
   }
-  const size_t cap = (size_t)2 << 30;
+  const size_t cap = (size_t)12 << 30;
   int c = std::min(want, max_frames);
   if (per > 0) c = (int)std::min<size_t>((size_t)c, std::max<size_t>(1, cap / per));
   return std::max(1, c);
