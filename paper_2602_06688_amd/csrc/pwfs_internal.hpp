@@ -32,6 +32,7 @@ struct SensorPlan {
   Geometry g;
   int arms = 1;           // 2 for a double roof: arm x, then arm y, one plane each
   Geometry arm_g[2];
+  int ident = 0;          // an arm's flat axis as the identity: 1 = columns (arm x), 2 = rows (arm y)
   void* dev[kRegions];
   int n_valid;
   double sumA2;

@@ -462,6 +462,81 @@ __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
   cols_body<N, QM, SPLIT>(p, blockIdx.x, smem);
 }
 
+// ------------------------------------------- double roof, flat-axis passes --
+// An arm of a double roof with no field stop has a flat mask on one axis, and
+// there the transform pair is the identity up to the pupil offset: the row
+// output at plane column o + x is the modulated field itself, and the column
+// output at plane row o + y is the column input times the wavelength's scale.
+// These two kernels replace those passes (same layouts as k_rows / k_cols).
+struct IdentArgs {
+  const float2* field;     // [frames][n_lam][D][D]
+  const float2* rx;        // [n_lam][n_a][D]
+  float2* rbuf;            // [frames][n_lam][n_a][Nc][Dp]
+  const int2* kord;        // [n_mod] (point, key), keys ascending
+  float* out;              // intensity of the chunk's first frame, frame stride out_stride
+  long long out_stride;
+  int nf, D, Dp, Nc, N, n_a, n_lam, n_mod, o, full, win_lo, win_hi;
+  float w2[PWFS_MAX_LAMBDA];   // per-wavelength intensity scale (share * weight / (n_mod sum A^2))
+};
+
+// arm y: R[f][lam][a][xc][y] = E[f][lam][y][x] rx[lam][a][x] at the compact
+// column xc of plane column o + x (xc = x in window mode, where the single
+// window starts at o), zero in the other columns of full-plane mode; one
+// thread per element, y fastest (the scratch is column-major)
+__global__ __launch_bounds__(kBlock) void k_rows_ident(IdentArgs p) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long total = (long long)p.nf * p.n_lam * p.n_a * p.Nc * p.D;
+  if (i >= total) return;
+  const int y = (int)(i % p.D);
+  long long r = i / p.D;
+  const int xc = (int)(r % p.Nc);
+  r /= p.Nc;
+  const int a = (int)(r % p.n_a);
+  r /= p.n_a;
+  const int lam = (int)(r % p.n_lam);
+  const long long f = r / p.n_lam;
+  const int x = p.full ? xc - p.o : xc;
+  float2 v = czero();
+  if (x >= 0 && x < p.D)
+    v = cmul(p.field[((f * p.n_lam + lam) * p.D + y) * p.D + x], p.rx[((long long)lam * p.n_a + a) * p.D + x]);
+  p.rbuf[(((f * p.n_lam + lam) * p.n_a + a) * p.Nc + xc) * p.Dp + y] = v;
+}
+
+// arm x: I[f][o + y][X(xc)] = sum_lam w2[lam] sum_points |R[f][lam][key][xc][y]|^2,
+// rows outside the pupil zero in full-plane mode; one thread per output
+// element, rows fastest
+__global__ __launch_bounds__(kBlock) void k_cols_ident(IdentArgs p) {
+  const int Yn = p.full ? p.N : p.D;
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long total = (long long)p.nf * p.Nc * Yn;
+  if (i >= total) return;
+  const int yo = (int)(i % Yn);
+  long long r = i / Yn;
+  const int xc = (int)(r % p.Nc);
+  const long long f = r / p.Nc;
+  const int Y = p.full ? yo : p.o + yo;
+  const int y = Y - p.o;
+  float acc = 0.f;
+  if (y >= 0 && y < p.D) {
+    for (int lam = 0; lam < p.n_lam; ++lam) {
+      const float2* base = p.rbuf + (((f * p.n_lam + lam) * p.n_a) * p.Nc + xc) * (long long)p.Dp + y;
+      float part = 0.f, val = 0.f;
+      int prev = -1;
+      for (int k = 0; k < p.n_mod; ++k) {
+        const int a = p.kord[k].y;
+        if (a != prev) {
+          val = cabs2(base[(long long)a * p.Nc * p.Dp]);
+          prev = a;
+        }
+        part += val;
+      }
+      acc += p.w2[lam] * part;
+    }
+  }
+  const int X = p.full ? xc : window_coord(xc, p.D, p.win_lo, p.win_hi);
+  p.out[f * p.out_stride + (long long)Y * p.N + X] = acc;
+}
+
 // -------------------------------------------------------------- slopes ----
 // One workgroup per frame.  Block sums are work items (quadrant, subaperture)
 // spread over the NT threads; consecutive threads read consecutive blocks of

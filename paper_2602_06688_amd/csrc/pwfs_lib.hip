@@ -561,6 +561,36 @@ static PassArgs build_pass_any(const SensorPlan& sp, const float* opd, long long
 // split: G workgroups per column instead of one per G columns
 constexpr unsigned kColsSplitBelow = 512;
 
+// the flat-axis pass of a double-roof arm (sp.ident): no transforms, the
+// same scratch and output layouts as k_rows / k_cols
+static IdentArgs ident_args(const SensorPlan& sp, const PassArgs& pa, int nf) {
+  const Geometry& g = sp.g;
+  IdentArgs ia{};
+  ia.field = pa.ra.field;
+  ia.rx = pa.ra.rx;
+  ia.rbuf = pa.ra.rbuf;
+  ia.kord = pa.ca.kord;
+  ia.out = pa.ca.out;
+  ia.out_stride = pa.ca.out_stride;
+  ia.nf = nf;
+  ia.D = g.D;
+  ia.Dp = g.Dp;
+  ia.Nc = g.Nc;
+  ia.N = g.N;
+  ia.n_a = g.n_a;
+  ia.n_lam = g.n_lam;
+  ia.n_mod = g.n_mod;
+  ia.o = g.o;
+  ia.full = g.full;
+  ia.win_lo = g.win_lo;
+  ia.win_hi = g.win_hi;
+  for (int l = 0; l < g.n_lam; ++l)
+    ia.w2[l] = (float)(0.5 * sp.desc.lambda_weight[l] / ((double)g.n_mod * sp.sumA2));
+  return ia;
+}
+
+static unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
 template <int N, int QM>
 static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_stride, float* out,
                        long long out_stride, int nf, float2* rbuf, hipStream_t st, Prof* prof) {
@@ -570,11 +600,21 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
   HIP_TRY(hipGetLastError(), "launch k_field");
   prof->end(slot, st, K_FIELD);
   slot = prof->begin(st);
-  hipLaunchKernelGGL((k_rows<N, QM>), dim3(pa.grid_rows), dim3(kBlock), pa.lds_rows, st, pa.ra);
+  if (sp.ident == 2) {
+    const IdentArgs ia = ident_args(sp, pa, nf);
+    hipLaunchKernelGGL(k_rows_ident, dim3(blocks_for((long long)nf * ia.n_lam * ia.n_a * ia.Nc * ia.D)),
+                       dim3(kBlock), 0, st, ia);
+  } else {
+    hipLaunchKernelGGL((k_rows<N, QM>), dim3(pa.grid_rows), dim3(kBlock), pa.lds_rows, st, pa.ra);
+  }
   HIP_TRY(hipGetLastError(), "launch k_rows");
   prof->end(slot, st, K_ROWS);
   slot = prof->begin(st);
-  if (pa.grid_cols < kColsSplitBelow)   // few frames: one column per workgroup, more workgroups
+  if (sp.ident == 1) {
+    const IdentArgs ia = ident_args(sp, pa, nf);
+    hipLaunchKernelGGL(k_cols_ident, dim3(blocks_for((long long)nf * ia.Nc * (ia.full ? ia.N : ia.D))),
+                       dim3(kBlock), 0, st, ia);
+  } else if (pa.grid_cols < kColsSplitBelow)   // few frames: one column per workgroup, more workgroups
     hipLaunchKernelGGL((k_cols<N, QM, true>), dim3(pa.grid_cols_split), dim3(kBlock), pa.lds_cols_split, st, pa.ca);
   else
     hipLaunchKernelGGL((k_cols<N, QM, false>), dim3(pa.grid_cols), dim3(kBlock), pa.lds_cols, st, pa.ca);
@@ -1059,6 +1099,9 @@ int forward_sensor(pwfs_plan_s* p, int i, const float* opd, long long opd_stride
       for (int a = 0; a < 2; ++a) {
         SensorPlan arm = sp;
         arm.g = sp.arm_g[a];
+        // with no field stop the flat axis is the identity: arm x skips its
+        // column transforms, arm y its row transforms
+        arm.ident = sp.desc.fov_lod > 0.0 ? 0 : (a == 0 ? 1 : 2);
         arm.dev[R_MROW] = (char*)sp.dev[R_MROW] + sizeof(float2) * (size_t)a * sp.g.n_lam * sp.g.N;
         arm.dev[R_MCOL] = (char*)sp.dev[R_MCOL] + sizeof(float2) * (size_t)a * sp.g.n_lam * sp.g.N;
         rc = forward_fp32(arm, o, opd_stride, r + (size_t)a * sp.g.N * sp.g.N, out_stride, n, sp.rbuf, st,
