@@ -245,3 +245,40 @@ def test_soul_geometry_chain():
     dsl, dfl = plan.ccd_slopes(got, d)
     ws, wf = C.detector_slopes(want, s, 120, r)
     assert O.slope_rel_rms(dsl.cpu().numpy(), ws, valid) < 1e-5
+
+
+def test_soul_chain_in_the_benchmark_launch():
+    """The SOUL chain exactly as the benchmark runs it: 1000 frames (200
+    distinct screens repeated) in one plan call, the 120 px detector with
+    photon and readout noise, detector slopes; frames 0 and 999 against the
+    oracle (frame 999 repeats frame 199's screen but draws its own noise)."""
+    P = _P()
+    from workloads import von_karman_opd
+    from workloads.configs import photo_electrons
+    s = tiny_sensor(n_pupil=220, n_fft=768, n_subap=40, pupil_sep_px=264.0, n_mod=24, mod_radius_lod=3.0,
+                    diameter_m=8.222, fov_lod=SOUL_FOV_LOD, flags=FLAG_REF_SLOPES)
+    scr = von_karman_opd(200, 220, 8.222, 0.126, 40.0, seed=70, grid=512)
+    opd = np.ascontiguousarray(np.tile(scr, (5, 1, 1)))
+    x = torch.from_numpy(opd).cuda()
+    plan = P.Plan([s], max_frames=1000)
+    el = photo_electrons(8.0, 8.222, 0.0, 300.0, 0.000588, 0.32)
+    r = Fraction(11, 2)
+    d = P.ccd_desc(120, r, el, P.CCD_PHOTON | P.CCD_READOUT, 0.4, seed=12)
+    print("[gpu] SOUL chain, 1000-frame launch", flush=True)
+    I = plan.forward(x)
+    pix = plan.ccd(I, d)
+    sl, fl = plan.ccd_slopes(pix, d)
+    torch.cuda.synchronize()
+    m = _window_mask(s)
+    valid = O.valid_subapertures(s)
+    for f in (0, 999):
+        I_ref = O.forward(opd[f:f + 1].astype(np.float64), s)
+        Ig = I[f:f + 1].cpu().numpy().astype(np.float64) * m[None]
+        e = np.linalg.norm(Ig - I_ref * m[None]) / np.linalg.norm(I_ref * m[None])
+        print(f"      frame {f}: intensity rel err {e:.2e}", flush=True)
+        assert e < 1e-5
+        # detector and slopes of the GPU's own intensity, as the chain feeds them
+        want = C.detector(Ig.astype(np.float32), 120, r, el, 3, 0.4, 12, frame0=f)
+        np.testing.assert_allclose(pix[f:f + 1].cpu().numpy(), want.astype(np.float32), rtol=1e-6, atol=1e-5)
+        ws, _ = C.detector_slopes(want, s, 120, r)
+        assert O.slope_rel_rms(sl[f:f + 1].cpu().numpy(), ws, valid) < 1e-5

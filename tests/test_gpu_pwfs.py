@@ -284,3 +284,25 @@ def test_polychromatic_batched_path_and_persistent():
     torch.cuda.synchronize()
     assert np.array_equal(I0, I1.cpu().numpy().astype(np.float64))
     assert np.array_equal(S0, S1.cpu().numpy().astype(np.float64))
+
+
+def test_sixteen_wavelengths_in_the_benchmark_launch():
+    """The 16-wavelength form as the benchmark runs it: the 160 px / N=512 /
+    48-point sensor over 600-900 nm, 200 frames in one call; the last frame
+    against the oracle."""
+    P = _P()
+    w = workload("cfg2")
+    lams, ws = band_sampling(750.0, 300.0, 16)
+    s = w.sensors[0].with_(lambdas_nm=lams, lambda_weights=ws)
+    opd = workload_opd(w, frames=range(200))
+    plan = P.Plan([s], max_frames=200)
+    _say("[gpu] 16 wavelengths, 200-frame launch")
+    I, sl, flux = plan.step(torch.from_numpy(opd).cuda())
+    torch.cuda.synchronize()
+    f = 199
+    I_ref = O.forward(opd[f:f + 1].astype(np.float64), s)
+    e = O.intensity_rel_error(_windows(I[f:f + 1].cpu().numpy(), s), _windows(I_ref, s))[0]
+    s_ref, _ = O.slopes(I_ref, s)
+    se = O.slope_rel_rms(sl[f:f + 1].cpu().numpy(), s_ref, O.valid_subapertures(s))
+    _say(f"      frame {f}: intensity rel err {e:.2e}, slope rel rms {se:.2e}")
+    assert e <= INT_TOL and se <= SLOPE_TOL
