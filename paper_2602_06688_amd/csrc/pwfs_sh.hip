@@ -160,33 +160,27 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
     }
     __syncthreads();
   }
-  // centre of gravity (fixed-order tree over the pixels)
+  // centre of gravity: the first wavefront sums the pixels lane-strided,
+  // then a fixed butterfly of cross-lane adds (no workgroup barriers)
+  if (tid >= 64) return;
   float t0 = 0.f, tx = 0.f, ty = 0.f;
   const float c0 = 0.5f * (float)(k - 1);
-  for (int P = tid; P < kk; P += kShBlock) {
+  for (int P = tid; P < kk; P += 64) {
     const float v = sP[P];
     t0 += v;
     tx = fmaf(v, (float)(P % k) - c0, tx);
     ty = fmaf(v, (float)(P / k) - c0, ty);
     if (pix_out) pix_out[P] = v;
   }
-  __shared__ float red[3][kShBlock];
-  red[0][tid] = t0;
-  red[1][tid] = tx;
-  red[2][tid] = ty;
-  __syncthreads();
-  for (int w = kShBlock / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      red[0][tid] += red[0][tid + w];
-      red[1][tid] += red[1][tid + w];
-      red[2][tid] += red[2][tid + w];
-    }
-    __syncthreads();
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    t0 += __shfl_xor(t0, off, 64);
+    tx += __shfl_xor(tx, off, 64);
+    ty += __shfl_xor(ty, off, 64);
   }
   if (tid == 0) {
-    const float tot = red[0][0];
-    sl[sub] = tot > 0.f ? red[1][0] / tot : 0.f;
-    sl[p.n * p.n + sub] = tot > 0.f ? red[2][0] / tot : 0.f;
+    sl[sub] = t0 > 0.f ? tx / t0 : 0.f;
+    sl[p.n * p.n + sub] = t0 > 0.f ? ty / t0 : 0.f;
   }
 }
 
