@@ -158,7 +158,7 @@ template <> struct FftPlan<128> { static constexpr int T = 16; static constexpr 
 template <> struct FftPlan<256> { static constexpr int T = 32; static constexpr int NS = 3; static constexpr int r[3] = {8, 4, 8}; };
 template <> struct FftPlan<384> { static constexpr int T = 32; static constexpr int NS = 5; static constexpr int r[5] = {4, 4, 4, 2, 3}; };
 template <> struct FftPlan<512> { static constexpr int T = 64; static constexpr int NS = 3; static constexpr int r[3] = {8, 8, 8}; };
-template <> struct FftPlan<768> { static constexpr int T = 64; static constexpr int NS = 5; static constexpr int r[5] = {4, 4, 4, 4, 3}; };
+template <> struct FftPlan<768> { static constexpr int T = 64; static constexpr int NS = 5; static constexpr int r[5] = {4, 4, 3, 4, 4}; };
 
 template <int N, int S, bool INV>
 struct StageInfo {
@@ -268,7 +268,7 @@ struct Palindromic {
     using P = FftPlan<N>;
     for (int s = 0; s < P::NS; ++s)
       if (P::r[s] != P::r[P::NS - 1 - s]) return false;
-    return P::NS <= 3;
+    return P::NS <= 5;
   }
   static constexpr bool value = check();
 };
@@ -302,9 +302,13 @@ struct TwSet {
   static constexpr int NS = FftPlan<N>::NS;
   StageTw<N, 1> s1;
   StageTw<N, (NS > 2 ? 2 : 1)> s2;
+  StageTw<N, (NS > 3 ? 3 : 1)> s3;
+  StageTw<N, (NS > 4 ? 4 : 1)> s4;
   __device__ __forceinline__ void load(int t, const float2* tw) {
     s1.load(t, tw);
     if constexpr (NS > 2) s2.load(t, tw);
+    if constexpr (NS > 3) s3.load(t, tw);
+    if constexpr (NS > 4) s4.load(t, tw);
   }
 };
 
@@ -353,7 +357,9 @@ __device__ __forceinline__ void stage_store_pad(const float2* v, int t, float2* 
 template <int N, int S>
 __device__ __forceinline__ const auto& tw_of(const TwSet<N>& tw) {
   if constexpr (S == 1) return tw.s1;
-  else return tw.s2;
+  else if constexpr (S == 2) return tw.s2;
+  else if constexpr (S == 3) return tw.s3;
+  else return tw.s4;
 }
 
 // Same contract as fft_from, for palindromic plans, with register twiddles
@@ -363,6 +369,12 @@ __device__ __forceinline__ void fft_reg(float2* v, int t, float2* buf, const TwS
   using P = FftPlan<N>;
   using SI = StageInfo<N, S, INV>;
   static_assert(Palindromic<N>::value, "plan must be palindromic");
+  if constexpr (S == 0 && P::NS > 3) {
+    // long plans: the lane index is made opaque at each transform, so the
+    // exchange addresses of all stages are recomputed here rather than
+    // hoisted out of the caller's loops into registers
+    __asm__ volatile("" : "+v"(t));
+  }
   if constexpr (S > 0) {
     wave_sync();
     stage_load_pad<N, SI::R>(v, t, buf);
