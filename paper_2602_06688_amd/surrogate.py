@@ -109,17 +109,21 @@ class SurrogatePipeline:
         return r
 
     def train(self, z, s, hidden=(1024, 1024), epochs: int = 20, batch: int = 1024, lr: float = 1e-3,
-              lr_final: float = 5e-5, seed: int = 5, precision: int = P.BF16) -> TrainReport:
+              lr_final: float = 5e-5, seed: int = 5, precision: int = P.BF16,
+              infer_batch: int = 32768) -> TrainReport:
         """Trains the network on the residual of (z, s) over the interaction
         matrix (built first if missing); cosine learning-rate decay from
-        ``lr`` to ``lr_final``; one Adam step per batch."""
+        ``lr`` to ``lr_final``; one Adam step per batch.  The network holds
+        activations for ``infer_batch`` rows, so that inference runs its
+        products over that many rows at once (enough tiles to fill the chip)."""
         from workloads.modes import init_params
         torch = self.torch
         if self.im is None:
             self.interaction_matrix()
         n = int(z.shape[0]) // batch * batch
         sizes = [self.n_modes, *hidden, self.n_out]
-        self.mlp = P.MLP(sizes, max_batch=max(batch, self.chunk), precision=precision, device=self.device)
+        self.mlp = P.MLP(sizes, max_batch=max(batch, self.chunk, infer_batch), precision=precision,
+                         device=self.device)
         self.mlp.set_params(torch.from_numpy(init_params(sizes, seed, zero_last=True)).to(self.device))
         r = self.residual(z[:n], s[:n])
         rms = P.row_rms(r)
