@@ -164,8 +164,8 @@ def surrogate_form(torch, dev, n_train, n_test, epochs, reps):
     dt = (time.perf_counter() - t0) / reps
     sizes = [ex["n_modes"], ex["hidden"], ex["hidden"], 2 * s.n_subap ** 2]
     # matrix-core flops per frame: the network (one bf16 product per layer)
-    # and the linear part IM z in bf16x3 (three bf16 products)
-    fl = 2.0 * sum(a * b for a, b in zip(sizes[:-1], sizes[1:])) + 3 * 2.0 * sizes[0] * sizes[-1]
+    # and the linear part IM z (one bf16 product)
+    fl = 2.0 * sum(a * b for a, b in zip(sizes[:-1], sizes[1:])) + 2.0 * sizes[0] * sizes[-1]
     ach = fl * n_test / dt / 1e12
     print(f"# surrogate: {n_test / dt:.0f} frames/s, error {e_nn:.3e} (linear IM {e_lin:.3e}), "
           f"train {rep.seconds:.1f} s", file=sys.stderr, flush=True)
@@ -175,7 +175,7 @@ def surrogate_form(torch, dev, n_train, n_test, epochs, reps):
             "train_seconds": round(rep.seconds, 2), "data_seconds": round(t_data, 2),
             "loss_first_last": [rep.losses[0], rep.losses[-1]],
             "form": "IM z + r_rms * net(z): push-pull interaction matrix plus the trained correction",
-            "roofline": {"kernel": "k_gemm (network bf16, linear part bf16x3; fp32 accumulation)", "bound": "mfma",
+            "roofline": {"kernel": "k_gemm (network and linear part bf16; fp32 accumulation)", "bound": "mfma",
                          "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                          "frac": round(ach / MFMA_PEAK_TFLOPS["bf16"], 4), "flops_per_frame": fl,
                          "traffic": None}}

@@ -144,9 +144,12 @@ class SurrogatePipeline:
         torch.cuda.synchronize(self.device)
         return TrainReport(epochs, steps, time.perf_counter() - t0, losses)
 
-    def predict(self, z, out=None):
+    def predict(self, z, out=None, linear_precision: int = P.BF16):
         """Surrogate slopes [n][n_out] (device): the network in chunks of
-        max_batch, then the linear part accumulated on top."""
+        max_batch, then the linear part accumulated on top.  The linear part
+        runs in bf16 like the network's weights (bf16x3 reproduces it to fp32
+        accuracy at three times the matrix-core work; the difference is two
+        orders below the surrogate's own error)."""
         torch = self.torch
         n = int(z.shape[0])
         if out is None:
@@ -155,7 +158,7 @@ class SurrogatePipeline:
         for i0 in range(0, n, mb):
             i1 = min(n, i0 + mb)
             self.mlp.forward(z[i0:i1], out=out[i0:i1], out_scale=self.s_scale)
-        P.gemm(z, self.im, out=out, alpha=1.0, beta=1.0, precision=P.BF16X3)
+        P.gemm(z, self.im, out=out, alpha=1.0, beta=1.0, precision=linear_precision)
         return out
 
     def predict_with_fallback(self, z, rms_limit: float = 1.5):
