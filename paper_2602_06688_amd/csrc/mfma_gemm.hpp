@@ -9,9 +9,9 @@
 //
 // A workgroup of 256 lanes (2 x 2 wavefronts) owns a 128 x 128 tile of C;
 // each wavefront a 64 x 64 quarter held as 2 x 2 v_mfma_f32_32x32x16 tiles.
-// K advances 32 at a time through a double-buffered LDS stage whose rows are
-// padded from 64 to 80 bytes so that the 16-byte fragment reads of 8
-// consecutive lanes hit distinct banks.
+// K advances BK (32 or 64) at a time through a double-buffered LDS stage
+// whose rows are padded by 16 bytes (2 BK + 16 bytes each) so that the
+// 16-byte fragment reads of 16 consecutive lanes hit distinct banks.
 //
 // Accumulator layout of one 32 x 32 tile (16 floats per lane): element
 // 4*j + r of lane l is C[8*j + 4*(l/32) + r][l % 32]; operand fragments:
@@ -30,8 +30,7 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));   // 16 bytes, 8 x 16-bit
 
 constexpr int kGemmTile = 128;  // BM = BN
-constexpr int kGemmBK = 32;
-constexpr int kLdsRow = 40;     // 16-bit elements per padded LDS row
+constexpr int kGemmBK = 32;     // default K step
 
 // ----------------------------------------------------------- conversions --
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
@@ -59,10 +58,14 @@ __device__ __forceinline__ void split16(float x, uint16_t& hi, uint16_t& lo) {
 }
 
 // --------------------------------------------------------------- engine ---
-template <int NPLANES, bool F16>
+template <int NPLANES, bool F16, int BK = kGemmBK>
 struct MfmaTile {
+  static_assert(BK == 32 || BK == 64, "K step of 32 or 64");
   static constexpr int NACC = (F16 && NPLANES == 2) ? 2 : 1;
-  static constexpr int STAGE = 2 * NPLANES * kGemmTile * kLdsRow;  // uint16 per stage (A and B)
+  static constexpr int BK_ = BK;
+  static constexpr int LROW = BK + 8;     // 16-bit elements per padded LDS row
+  static constexpr int H = BK / 16;       // 16-byte chunks per lane and operand plane in one K step
+  static constexpr int STAGE = 2 * NPLANES * kGemmTile * LROW;  // uint16 per stage (A and B)
   static constexpr size_t lds_bytes() { return sizeof(uint16_t) * 2 * STAGE; }
 
   f32x16_t acc[NACC][2][2];
@@ -93,11 +96,11 @@ struct MfmaTile {
                                                      __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
   }
 
-  // Global -> registers for one K step of 32: each lane moves 2 x 16 bytes
-  // of each plane of A and of B.  Rows past the operand's end are clamped
-  // (their products land in C rows/columns that are never stored).
+  // Global -> registers for one K step: each lane moves H x 16 bytes of each
+  // plane of A and of B.  Rows past the operand's end are clamped (their
+  // products land in C rows/columns that are never stored).
   struct Pref {
-    u32x4_t a[NPLANES][2], b[NPLANES][2];
+    u32x4_t a[NPLANES][H], b[NPLANES][H];
   };
 
   // first row of the tile in each plane of A and B
@@ -106,12 +109,20 @@ struct MfmaTile {
     const uint16_t* b[NPLANES];
   };
 
+  // the tile row and K offset of the 16-byte chunk lane tid moves in part h
+  // of a fetch
+  __device__ __forceinline__ static void fetch_slot(int tid, int h, int& row, int& kq) {
+    const int c = tid + 256 * h;
+    row = c / (BK / 8);
+    kq = (c % (BK / 8)) * 8;
+  }
+
   __device__ __forceinline__ static void fetch(Pref& p, const Ops& o, long long lda, int arows, long long ldb,
                                                int brows, int k0, int tid) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int c = tid + 256 * h;
-      const int row = c >> 2, kq = (c & 3) * 8;
+    for (int h = 0; h < H; ++h) {
+      int row, kq;
+      fetch_slot(tid, h, row, kq);
       const int ra = min(row, arows - 1), rb = min(row, brows - 1);
 #pragma unroll
       for (int pl = 0; pl < NPLANES; ++pl) {
@@ -121,32 +132,46 @@ struct MfmaTile {
     }
   }
 
-  __device__ __forceinline__ static void stash(const Pref& p, uint16_t* stage, int tid) {
+  // Global -> registers for one K step with per-lane row offsets (elements,
+  // the chunk's K offset included) given by the caller: ao[h] and bo[h]
+  // address the rows of A and B this lane moves in part h.
+  __device__ __forceinline__ static void fetch_at(Pref& p, const Ops& o, const long long (&ao)[H],
+                                                  const long long (&bo)[H], int k0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int c = tid + 256 * h;
-      const int row = c >> 2, kq = (c & 3) * 8;
+    for (int h = 0; h < H; ++h)
 #pragma unroll
       for (int pl = 0; pl < NPLANES; ++pl) {
-        *(u32x4_t*)(stage + (pl * kGemmTile + row) * kLdsRow + kq) = p.a[pl][h];
-        *(u32x4_t*)(stage + ((NPLANES + pl) * kGemmTile + row) * kLdsRow + kq) = p.b[pl][h];
+        p.a[pl][h] = *(const u32x4_t*)(o.a[pl] + ao[h] + k0);
+        p.b[pl][h] = *(const u32x4_t*)(o.b[pl] + bo[h] + k0);
+      }
+  }
+
+  __device__ __forceinline__ static void stash(const Pref& p, uint16_t* stage, int tid) {
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      int row, kq;
+      fetch_slot(tid, h, row, kq);
+#pragma unroll
+      for (int pl = 0; pl < NPLANES; ++pl) {
+        *(u32x4_t*)(stage + (pl * kGemmTile + row) * LROW + kq) = p.a[pl][h];
+        *(u32x4_t*)(stage + ((NPLANES + pl) * kGemmTile + row) * LROW + kq) = p.b[pl][h];
       }
     }
   }
 
-  // the MFMAs of one 32-wide K step held in `stage`
+  // the MFMAs of one K step held in `stage`
   __device__ __forceinline__ void compute(const uint16_t* stage, int wm, int wn, int lane) {
     const int r = lane & 31, kh = (lane >> 5) * 8;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < BK / 16; ++s) {
       u32x4_t fa[NPLANES][2], fb[NPLANES][2];
 #pragma unroll
       for (int pl = 0; pl < NPLANES; ++pl)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          fa[pl][i] = *(const u32x4_t*)(stage + (pl * kGemmTile + wm * 64 + i * 32 + r) * kLdsRow + s * 16 + kh);
-          fb[pl][i] = *(const u32x4_t*)(stage + ((NPLANES + pl) * kGemmTile + wn * 64 + i * 32 + r) * kLdsRow +
-                                      s * 16 + kh);
+          fa[pl][i] = *(const u32x4_t*)(stage + (pl * kGemmTile + wm * 64 + i * 32 + r) * LROW + s * 16 + kh);
+          fb[pl][i] =
+              *(const u32x4_t*)(stage + ((NPLANES + pl) * kGemmTile + wn * 64 + i * 32 + r) * LROW + s * 16 + kh);
         }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -161,12 +186,12 @@ struct MfmaTile {
     }
   }
 
-  // Full K loop of one GEMM tile; K is a multiple of 32.
+  // Full K loop of one GEMM tile; K is a multiple of BK.
   __device__ __forceinline__ void run(const Ops o, long long lda, int arows, long long ldb, int brows, int K,
                                       uint16_t* lds, int tid) {
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
-    const int nk = K / kGemmBK;
+    const int nk = K / BK;
     Pref p;
     fetch(p, o, lda, arows, ldb, brows, 0, tid);
     __syncthreads();   // previous users of the LDS stages are done
@@ -174,7 +199,7 @@ struct MfmaTile {
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
       uint16_t* cur = lds + (kt & 1) * STAGE;
-      if (kt + 1 < nk) fetch(p, o, lda, arows, ldb, brows, (kt + 1) * kGemmBK, tid);
+      if (kt + 1 < nk) fetch(p, o, lda, arows, ldb, brows, (kt + 1) * BK, tid);
       compute(cur, wm, wn, lane);
       if (kt + 1 < nk) stash(p, lds + ((kt + 1) & 1) * STAGE, tid);
       __syncthreads();

@@ -33,6 +33,12 @@ namespace pwfs {
 
 namespace {
 
+// The one-term form runs K steps of 64 (8 products per wavefront between
+// barriers rather than 4, so that load latency hides behind them); the
+// split forms' three products already give 12 per step of 32.
+template <int NPL, bool F16>
+using Engine = MfmaTile<NPL, F16, NPL == 1 ? 64 : 32>;
+
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
 struct MGeom {
@@ -46,7 +52,8 @@ MGeom mgeom(const pwfs_sensor_desc& d) {
   m.D = g.D;
   m.N = g.N;
   m.Nc = g.Nc;
-  m.Kp = (2 * g.D + kGemmBK - 1) / kGemmBK * kGemmBK;
+  const int bk = d.precision == PWFS_BF16 ? 64 : 32;   // the K step of the engine used
+  m.Kp = (2 * g.D + bk - 1) / bk * bk;
   m.M = 2 * g.Nc;
   m.n_a = g.n_a;
   m.n_lam = g.n_lam;
@@ -157,58 +164,124 @@ struct G1Args {
   int M, F, D, Kp, Nc, n_a, n_lam, mtiles, ntiles;
 };
 
+// Workgroups renumbered so that each of the 8 XCDs (which receive
+// workgroups in turn) holds a contiguous run of tiles.
+__device__ __forceinline__ int xcd_major_block() {
+  const int G = (int)gridDim.x, xcd = (int)blockIdx.x % 8, idx = (int)blockIdx.x / 8;
+  const int per = G / 8, rem = G % 8;
+  return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + idx;
+}
+
+// One workgroup owns a tile of (wavelength, output rows, field rows) and runs
+// the n_a products T_a of that tile (same field rows, one Qx_a each) as one
+// stream of K steps; each product is stored as it completes, while the
+// next product's first operands are in flight.
 template <int NPL, bool F16>
 __global__ __launch_bounds__(256) void k_mfma_rows(G1Args p) {
   extern __shared__ uint4 lds_raw[];
   uint16_t* lds = (uint16_t*)lds_raw;
-  using E = MfmaTile<NPL, F16>;
+  using E = Engine<NPL, F16>;
   const int tid = threadIdx.x;
-  int bid = blockIdx.x;
-  const int nt = bid % p.ntiles;
-  bid /= p.ntiles;
+  int bid = xcd_major_block();
   const int mt = bid % p.mtiles;
-  const int la = bid / p.mtiles;          // lam * n_a + a
-  const int lam = la / p.n_a, a = la % p.n_a;
+  bid /= p.mtiles;
+  const int nt = bid % p.ntiles;
+  const int lam = bid / p.ntiles;
   const int m0 = mt * kGemmTile, n0 = nt * kGemmTile;
   const int NF = p.F * p.D;
-  typename E::Ops ops;
+  long long ao[E::H], bo[E::H];
 #pragma unroll
-  for (int pl = 0; pl < NPL; ++pl) {
-    ops.a[pl] = p.a + pl * p.a_plane + ((long long)la * p.M + m0) * p.Kp;
-    ops.b[pl] = p.b + pl * p.b_plane + ((long long)lam * NF + n0) * p.Kp;
+  for (int h = 0; h < E::H; ++h) {
+    int row, kq;
+    E::fetch_slot(tid, h, row, kq);
+    ao[h] = (long long)min(m0 + row, p.M - 1) * p.Kp + kq;
+    bo[h] = (long long)min(n0 + row, NF - 1) * p.Kp + kq;
   }
+  auto ops_of = [&](int a) {
+    typename E::Ops o;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) {
+      o.a[pl] = p.a + pl * p.a_plane + ((long long)lam * p.n_a + a) * p.M * p.Kp;
+      o.b[pl] = p.b + pl * p.b_plane + (long long)lam * NF * p.Kp;
+    }
+    return o;
+  };
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int nk = p.Kp / E::BK_;
+  const int steps = p.n_a * nk;
+
   E eng;
   eng.zero();
-  eng.run(ops, p.Kp, p.M - m0, p.Kp, NF - n0, p.Kp, lds, tid);
+  typename E::Pref pf;
+  typename E::Ops cur_ops = ops_of(0);
+  E::fetch_at(pf, cur_ops, ao, bo, 0);
+  E::stash(pf, lds, tid);
+  __syncthreads();
+  int a = 0, kt = 0;
+  for (int st = 0; st < steps; ++st) {
+    int na = a, nkt = kt + 1;
+    if (nkt == nk) {
+      nkt = 0;
+      ++na;
+    }
+    const bool more = st + 1 < steps;
+    if (more) {
+      if (nkt == 0) cur_ops = ops_of(na);
+      E::fetch_at(pf, cur_ops, ao, bo, nkt * E::BK_);
+    }
+    eng.compute(lds + (st & 1) * E::STAGE, wm, wn, lane);
+    if (kt == nk - 1) {
+      // output offset = column part (frame, y; j only) + row part (X, c)
+      long long cofs[2];
+      int ys[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int row, col;
-        E::coord(tid, i, j, e, row, col);
-        const int m = m0 + row, n = n0 + col;
-        if (m >= p.M || n >= NF) continue;
-        const int X = m >> 1, c = m & 1;
-        const int f = n / p.D, y = n - f * p.D;
-        const long long o = ((((long long)f * p.n_lam + lam) * p.n_a + a) * p.Nc + X) * p.Kp + c * p.D + y;
-        const float v = eng.value(i, j, e);
-        if constexpr (NPL == 2) {
-          uint16_t hi, lo;
-          split16<F16>(v, hi, lo);
-          p.t[o] = hi;
-          p.t[p.t_plane + o] = lo;
-        } else {
-          p.t[o] = F16 ? f32_to_f16_rne(v) : f32_to_bf16_rne(v);
-        }
-        // the K padding [2D, Kp) of this row must hold zeros for stage 2
-        if (c == 1)
-          for (int z = y; z < p.Kp - 2 * p.D; z += p.D) {
-            p.t[o + p.D + z - y] = 0;
-            if constexpr (NPL == 2) p.t[p.t_plane + o + p.D + z - y] = 0;
-          }
+      for (int j = 0; j < 2; ++j) {
+        const int n = min(n0 + wn * 64 + j * 32 + (lane & 31), NF - 1);
+        const int f = n / p.D;
+        ys[j] = n - f * p.D;
+        cofs[j] = (((long long)f * p.n_lam + lam) * p.n_a + a) * p.Nc * p.Kp + ys[j];
       }
+      int mb = m0 + wm * 64 + 4 * (lane >> 5);   // even: element e has c = e & 1
+      // opaque, so that the 32 row offsets below are formed here and not kept
+      // live across the whole K stream
+      __asm__ volatile("" : "+v"(mb));
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int m = mb + i * 32 + 8 * (e >> 2) + (e & 3);
+          if (m >= p.M) continue;
+          const int c = e & 1;
+          const int rofs = (m >> 1) * p.Kp + c * p.D;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            if (n0 + wn * 64 + j * 32 + (lane & 31) >= NF) continue;
+            const long long o = cofs[j] + rofs;
+            const float v = eng.value(i, j, e);
+            if constexpr (NPL == 2) {
+              uint16_t hi, lo;
+              split16<F16>(v, hi, lo);
+              p.t[o] = hi;
+              p.t[p.t_plane + o] = lo;
+            } else {
+              p.t[o] = F16 ? f32_to_f16_rne(v) : f32_to_bf16_rne(v);
+            }
+            // the K padding [2D, Kp) of this row must hold zeros for stage 2
+            if (c == 1)
+              for (int z = ys[j]; z < p.Kp - 2 * p.D; z += p.D) {
+                p.t[o + p.D + z - ys[j]] = 0;
+                if constexpr (NPL == 2) p.t[p.t_plane + o + p.D + z - ys[j]] = 0;
+              }
+          }
+        }
+      eng.zero();
+    }
+    if (more) E::stash(pf, lds + ((st + 1) & 1) * E::STAGE, tid);
+    __syncthreads();
+    a = na;
+    kt = nkt;
+  }
 }
 
 struct G2Args {
@@ -217,22 +290,42 @@ struct G2Args {
   const int2* kord;       // [n_mod] (k, a)
   float* out;             // first frame of the pass, frame stride out_stride
   long long a_plane, t_plane, out_stride;
-  int M, Nc, N, D, Kp, n_a, n_lam, n_mod, mtiles, ntiles, win_lo, win_hi, full;
+  int M, F, Nc, N, D, Kp, n_a, n_lam, n_mod, mtiles, ntiles, win_lo, win_hi, full;
   float scale[PWFS_MAX_LAMBDA];
 };
 
+// Columns of C run over all frames of the pass (n = f Nc + c), so a tile may
+// straddle two frames and only the pass's last tile is ragged.  The
+// n_lam x n_mod products of one tile form one stream of K steps: the next
+// step's operands (possibly the next product's first) are fetched while the
+// current step runs, and a product's |e|^2 is accumulated as it completes.
 template <int NPL, bool F16>
 __global__ __launch_bounds__(256) void k_mfma_cols(G2Args p) {
   extern __shared__ uint4 lds_raw[];
   uint16_t* lds = (uint16_t*)lds_raw;
-  using E = MfmaTile<NPL, F16>;
+  using E = Engine<NPL, F16>;
   const int tid = threadIdx.x;
-  int bid = blockIdx.x;
-  const int nt = bid % p.ntiles;
-  bid /= p.ntiles;
+  // the mtiles row tiles that read the same columns of T are neighbours, so
+  // they share one XCD's L2
+  const int bid = xcd_major_block();
   const int mt = bid % p.mtiles;
-  const int f = bid / p.mtiles;
+  const int nt = bid / p.mtiles;
   const int m0 = mt * kGemmTile, n0 = nt * kGemmTile;
+  const int NT = p.F * p.Nc;
+  const long long t_frame = (long long)p.n_lam * p.n_a * p.Nc * p.Kp;
+
+  // per-lane row offsets of the two rows this lane moves (rows past the end
+  // are clamped; their products are never stored)
+  long long ao[E::H], bo[E::H];
+#pragma unroll
+  for (int h = 0; h < E::H; ++h) {
+    int row, kq;
+    E::fetch_slot(tid, h, row, kq);
+    ao[h] = (long long)min(m0 + row, p.M - 1) * p.Kp + kq;
+    const int n = min(n0 + row, NT - 1);
+    const int fr = n / p.Nc;
+    bo[h] = fr * t_frame + (long long)(n - fr * p.Nc) * p.Kp + kq;
+  }
 
   float inten[2][2][8];
 #pragma unroll
@@ -242,19 +335,45 @@ __global__ __launch_bounds__(256) void k_mfma_cols(G2Args p) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) inten[i][j][e] = 0.f;
 
-  E eng;
-  for (int lam = 0; lam < p.n_lam; ++lam) {
-    const float sc = p.scale[lam];
-    for (int it = 0; it < p.n_mod; ++it) {
-      const int2 ka = p.kord[it];
-      typename E::Ops ops;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int nk = p.Kp / E::BK_;
+  const int steps = p.n_lam * p.n_mod * nk;
+  auto ops_of = [&](int prod) {
+    const int lam = prod / p.n_mod;
+    const int2 ka = p.kord[prod - lam * p.n_mod];
+    typename E::Ops o;
 #pragma unroll
-      for (int pl = 0; pl < NPL; ++pl) {
-        ops.a[pl] = p.a + pl * p.a_plane + (((long long)lam * p.n_mod + ka.x) * p.M + m0) * p.Kp;
-        ops.b[pl] = p.t + pl * p.t_plane + ((((long long)f * p.n_lam + lam) * p.n_a + ka.y) * p.Nc + n0) * p.Kp;
-      }
-      eng.zero();
-      eng.run(ops, p.Kp, p.M - m0, p.Kp, p.Nc - n0, p.Kp, lds, tid);
+    for (int pl = 0; pl < NPL; ++pl) {
+      o.a[pl] = p.a + pl * p.a_plane + ((long long)lam * p.n_mod + ka.x) * p.M * p.Kp;
+      o.b[pl] = p.t + pl * p.t_plane + ((long long)lam * p.n_a + ka.y) * p.Nc * p.Kp;
+    }
+    return o;
+  };
+
+  E eng;
+  eng.zero();
+  typename E::Pref pf;
+  typename E::Ops cur_ops = ops_of(0);
+  E::fetch_at(pf, cur_ops, ao, bo, 0);
+  E::stash(pf, lds, tid);
+  __syncthreads();
+  int prod = 0, kt = 0;
+  for (int st = 0; st < steps; ++st) {
+    // the step after this one
+    int nprod = prod, nkt = kt + 1;
+    if (nkt == nk) {
+      nkt = 0;
+      ++nprod;
+    }
+    const bool more = st + 1 < steps;
+    if (more) {
+      if (nkt == 0) cur_ops = ops_of(nprod);
+      E::fetch_at(pf, cur_ops, ao, bo, nkt * E::BK_);
+    }
+    eng.compute(lds + (st & 1) * E::STAGE, wm, wn, lane);
+    if (kt == nk - 1) {
+      const float sc = p.scale[prod / p.n_mod];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -264,9 +383,13 @@ __global__ __launch_bounds__(256) void k_mfma_cols(G2Args p) {
             const float re = eng.value(i, j, e), im = eng.value(i, j, e + 1);
             inten[i][j][e >> 1] += sc * (re * re + im * im);
           }
+      eng.zero();
     }
+    if (more) E::stash(pf, lds + ((st + 1) & 1) * E::STAGE, tid);
+    __syncthreads();
+    prod = nprod;
+    kt = nkt;
   }
-  float* out = p.out + (long long)f * p.out_stride;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -275,11 +398,12 @@ __global__ __launch_bounds__(256) void k_mfma_cols(G2Args p) {
       for (int e = 0; e < 16; e += 2) {
         int row, col;
         E::coord(tid, i, j, e, row, col);
-        const int Yc = (m0 + row) >> 1, Xc = n0 + col;
-        if (Yc >= p.Nc || Xc >= p.Nc) continue;
+        const int Yc = (m0 + row) >> 1, n = n0 + col;
+        if (Yc >= p.Nc || n >= NT) continue;
+        const int fr = n / p.Nc, Xc = n - fr * p.Nc;
         const int Y = p.full ? Yc : window_coord(Yc, p.D, p.win_lo, p.win_hi);
         const int X = p.full ? Xc : window_coord(Xc, p.D, p.win_lo, p.win_hi);
-        out[(long long)Y * p.N + X] = inten[i][j][e >> 1];
+        p.out[(long long)fr * p.out_stride + (long long)Y * p.N + X] = inten[i][j][e >> 1];
       }
 }
 
@@ -316,7 +440,7 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
   if (e != hipSuccess) return PWFS_EHIP;
   prof->end(slot, st, K_FIELD);
 
-  const size_t lds = MfmaTile<NPL, F16>::lds_bytes();
+  const size_t lds = Engine<NPL, F16>::lds_bytes();
   G1Args a1{};
   a1.a = qx;
   a1.b = field;
@@ -333,7 +457,7 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
   a1.n_lam = m.n_lam;
   a1.mtiles = (m.M + kGemmTile - 1) / kGemmTile;
   a1.ntiles = (nf * m.D + kGemmTile - 1) / kGemmTile;
-  const unsigned g1 = (unsigned)(m.n_lam * m.n_a * a1.mtiles * a1.ntiles);
+  const unsigned g1 = (unsigned)(m.n_lam * a1.mtiles * a1.ntiles);
   slot = prof->begin(st);
   hipLaunchKernelGGL((k_mfma_rows<NPL, F16>), dim3(g1), dim3(256), lds, st, a1);
   if ((e = hipGetLastError()) != hipSuccess) return PWFS_EHIP;
@@ -348,6 +472,7 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
   a2.t_plane = t_plane;
   a2.out_stride = ost;
   a2.M = m.M;
+  a2.F = nf;
   a2.Nc = m.Nc;
   a2.N = m.N;
   a2.D = m.D;
@@ -356,13 +481,13 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
   a2.n_lam = m.n_lam;
   a2.n_mod = m.n_mod;
   a2.mtiles = (m.M + kGemmTile - 1) / kGemmTile;
-  a2.ntiles = (m.Nc + kGemmTile - 1) / kGemmTile;
+  a2.ntiles = (int)(((long long)nf * m.Nc + kGemmTile - 1) / kGemmTile);
   a2.win_lo = g.win_lo;
   a2.win_hi = g.win_hi;
   a2.full = g.full;
   for (int l = 0; l < m.n_lam; ++l)
     a2.scale[l] = (float)(sp.desc.lambda_weight[l] / ((double)sp.g.n_mod * sp.sumA2));
-  const unsigned g2 = (unsigned)(nf * a2.mtiles * a2.ntiles);
+  const unsigned g2 = (unsigned)(a2.mtiles * a2.ntiles);
   slot = prof->begin(st);
   hipLaunchKernelGGL((k_mfma_cols<NPL, F16>), dim3(g2), dim3(256), lds, st, a2);
   if ((e = hipGetLastError()) != hipSuccess) return PWFS_EHIP;
@@ -372,7 +497,7 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
 
 template <int NPL, bool F16>
 void set_lds() {
-  const int lds = (int)MfmaTile<NPL, F16>::lds_bytes();
+  const int lds = (int)Engine<NPL, F16>::lds_bytes();
   if (hipFuncSetAttribute((const void*)k_mfma_rows<NPL, F16>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
       hipSuccess)
     (void)hipGetLastError();

@@ -79,6 +79,30 @@ def test_edge_sensors_mfma(prec):
         assert e.max() <= 1e-3 and se <= 1e-3
 
 
+def test_edge_sensors_bf16():
+    """The one-term form runs K steps of 64, so a pupil whose 2D is not a
+    multiple of 64 exercises the zero padding of both operands."""
+    from workloads import von_karman_opd
+    cases = [tiny_sensor(n_pupil=40, n_fft=128, n_subap=5, pupil_sep_px=48.0, n_mod=5, obstruction=0.3,
+                         mod_radius_lod=3.0, precision=PREC_BF16),
+             tiny_sensor(n_pupil=48, n_fft=128, n_subap=12, pupil_sep_px=56.0, n_mod=8, precision=PREC_BF16,
+                         lambdas_nm=(600.0, 750.0, 900.0), lambda_weights=(0.2, 0.3, 0.5), flags=3)]
+    for s in cases:
+        opd = von_karman_opd(3, s.n_pupil, 8.0, 0.5, 25.0, seed=7)
+        print(f"[gpu] mfma bf16 D={s.n_pupil} N={s.n_fft} flags={s.flags}", flush=True)
+        I, sl, _ = _run(s, opd)
+        ref_s = s.with_(precision=0)
+        I_ref = O.forward(opd, ref_s)
+        s_ref, _ = O.slopes(I_ref, ref_s)
+        if s.flags & 2:
+            e = O.intensity_rel_error(I, I_ref)
+        else:
+            e = O.intensity_rel_error(_windows(I, s), _windows(I_ref, s))
+        se = O.slope_rel_rms(sl, s_ref, O.valid_subapertures(s))
+        print(f"      intensity {e.max():.2e}, slopes {se:.2e}", flush=True)
+        assert e.max() <= BOUNDS[PREC_BF16][0] and se <= BOUNDS[PREC_BF16][1]
+
+
 def test_160px_sampled_bf16x3():
     w = workload("cfg2")
     s = w.sensors[0].with_(precision=PREC_BF16X3)
