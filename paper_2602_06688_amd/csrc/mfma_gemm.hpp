@@ -3,9 +3,10 @@
 // C[M][N] = sum_k A[M][K] B[N][K] (both operands K-contiguous, "NT"), with
 // A and B given as 16-bit planes: one plane (plain bf16) or a hi/lo pair
 // (x = hi + lo, three products hi*hi + hi*lo + lo*hi accumulated in fp32).
-// For fp16 the lo plane is stored scaled by 2^11 and its two products go to
-// a second accumulator that is scaled back at the end, so the small lo parts
-// never fall into fp16 subnormals.
+// For fp16 the lo plane is stored scaled by 2^11, so the small lo parts never
+// fall into fp16 subnormals; the hi*hi product then takes A's hi fragment
+// scaled by 2^11 in registers (exact: every A operand here has |a| <= 1), so
+// the three products share one accumulator that holds 2^11 C.
 //
 // A workgroup of 256 lanes (2 x 2 wavefronts) owns a 128 x 128 tile of C;
 // each wavefront a 64 x 64 quarter held as 2 x 2 v_mfma_f32_32x32x16 tiles.
@@ -61,30 +62,28 @@ __device__ __forceinline__ void split16(float x, uint16_t& hi, uint16_t& lo) {
 template <int NPLANES, bool F16, int BK = kGemmBK>
 struct MfmaTile {
   static_assert(BK == 32 || BK == 64, "K step of 32 or 64");
-  static constexpr int NACC = (F16 && NPLANES == 2) ? 2 : 1;
+  static constexpr bool SCALED = F16 && NPLANES == 2;   // accumulator holds 2^11 C
   static constexpr int BK_ = BK;
   static constexpr int LROW = BK + 8;     // 16-bit elements per padded LDS row
   static constexpr int H = BK / 16;       // 16-byte chunks per lane and operand plane in one K step
   static constexpr int STAGE = 2 * NPLANES * kGemmTile * LROW;  // uint16 per stage (A and B)
   static constexpr size_t lds_bytes() { return sizeof(uint16_t) * 2 * STAGE; }
 
-  f32x16_t acc[NACC][2][2];
+  f32x16_t acc[2][2];
 
   __device__ __forceinline__ void zero() {
 #pragma unroll
-    for (int c = 0; c < NACC; ++c)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int e = 0; e < 16; ++e) acc[c][i][j][e] = 0.f;
+        for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
   }
 
   // value of accumulator element e of tile (i, j), scale folded in
   __device__ __forceinline__ float value(int i, int j, int e) const {
-    if constexpr (NACC == 2) return acc[0][i][j][e] + acc[1][i][j][e] * (1.f / 2048.f);
-    else return acc[0][i][j][e];
+    if constexpr (SCALED) return acc[i][j][e] * (1.f / 2048.f);
+    else return acc[i][j][e];
   }
 
   __device__ __forceinline__ static f32x16_t mma(u32x4_t a, u32x4_t b, f32x16_t c) {
@@ -174,15 +173,19 @@ struct MfmaTile {
               *(const u32x4_t*)(stage + ((NPLANES + pl) * kGemmTile + wn * 64 + i * 32 + r) * LROW + s * 16 + kh);
         }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) {
+        u32x4_t hi_a = fa[0][i];
+        if constexpr (SCALED)
+          hi_a = __builtin_bit_cast(u32x4_t, __builtin_bit_cast(f16x8_t, hi_a) * (_Float16)2048.0f);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          acc[0][i][j] = mma(fa[0][i], fb[0][j], acc[0][i][j]);
+          acc[i][j] = mma(hi_a, fb[0][j], acc[i][j]);
           if constexpr (NPLANES == 2) {
-            acc[NACC - 1][i][j] = mma(fa[0][i], fb[1][j], acc[NACC - 1][i][j]);
-            acc[NACC - 1][i][j] = mma(fa[1][i], fb[0][j], acc[NACC - 1][i][j]);
+            acc[i][j] = mma(fa[0][i], fb[1][j], acc[i][j]);
+            acc[i][j] = mma(fa[1][i], fb[0][j], acc[i][j]);
           }
         }
+      }
     }
   }
 
