@@ -220,7 +220,9 @@ def detector_form(P, torch, dev, stream, x, plan, I, s, steps: int):
             "roofline": {"kernel": "k_ccd (rebin, Poisson, Gamma, Gaussian per detector pixel)", "bound": "hbm",
                          "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_frame": byts,
-                         "avg_launch_ms": round(ccd_ms / max(1, ccd_n), 4), "traffic": None}}
+                         "avg_launch_ms": round(ccd_ms / max(1, ccd_n), 4), "traffic": None,
+                         "note": "bytes are reported for reference; the kernel is bound by its float64 "
+                                 "sampling arithmetic (Philox, Poisson inversion, Gamma), not by HBM"}}
 
 
 def roof_form(P, torch, dev, x, s, steps: int):
