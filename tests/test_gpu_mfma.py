@@ -117,3 +117,29 @@ def test_160px_sampled_bf16x3():
         se = O.slope_rel_rms(sl[f:f + 1], s_ref, valid)
         print(f"      frame {f}: intensity {e:.2e} slopes {se:.2e}", flush=True)
         assert e <= 1e-3 and se <= 1e-3
+
+
+@pytest.mark.parametrize("prec", [PREC_BF16X3, PREC_FP16X3])
+def test_160px_full_size_in_the_benchmark_launch(prec):
+    """All 1000 frames in one plan, as the bench launches the split forms.
+    A frame's 320 image columns are 2.5 column tiles, so odd frames start in
+    the middle of a tile shared with the frame before; frames 0, 1 (the first
+    straddling tile), 517 and 999 against the oracle, every frame finite with
+    its flux in range."""
+    w = workload("cfg2")
+    s = w.sensors[0].with_(precision=prec)
+    print(f"[gpu] mfma {NAMES[prec]} 160px 1000 frames: inputs", flush=True)
+    opd = workload_opd(w)
+    print(f"[gpu] mfma {NAMES[prec]} 160px 1000 frames: forward + slopes", flush=True)
+    I, sl, fl = _run(s, opd)
+    assert np.isfinite(I).all() and np.isfinite(sl).all()
+    assert (fl > 0.5).all() and (fl < 1.0 + 1e-3).all()
+    valid = O.valid_subapertures(s)
+    for f in (0, 1, 517, 999):
+        I_ref = O.forward(opd[f:f + 1], w.sensors[0])
+        s_ref, f_ref = O.slopes(I_ref, w.sensors[0])
+        e = O.intensity_rel_error(_windows(I[f:f + 1], s), _windows(I_ref, s))[0]
+        se = O.slope_rel_rms(sl[f:f + 1], s_ref, valid)
+        print(f"      frame {f}: intensity {e:.2e} slopes {se:.2e}", flush=True)
+        assert e <= 1e-3 and se <= 1e-3
+        assert abs(fl[f] / f_ref[0] - 1) <= 1e-3
