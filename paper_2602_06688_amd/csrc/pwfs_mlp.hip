@@ -85,11 +85,11 @@ __device__ __forceinline__ void put16(uint16_t* base, long long plane, long long
   }
 }
 
-template <int NPL, int EPI>
+template <int NPL, int EPI, int BK>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
   extern __shared__ u32x4_t lds_raw[];
   uint16_t* lds = (uint16_t*)lds_raw;
-  using E = MfmaTile<NPL, false>;
+  using E = MfmaTile<NPL, false, BK>;
   const int tid = threadIdx.x;
   const int nt = blockIdx.x % p.ntiles;
   const int mt = blockIdx.x / p.ntiles;
@@ -120,10 +120,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
           *cp = (p.beta != 0.f) ? p.alpha * v + p.beta * *cp : p.alpha * v;
         } else if constexpr (EPI == E_HIDDEN) {
           const float zz = v + p.bias[n];
-          p.z[(long long)m * p.ldz + n] = zz;
           const float hv = gelu_f(zz);
           put16(p.h, p.h_plane, (long long)m * p.ldh + n, hv, p.planes_out);
-          put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, hv, p.planes_out);
+          // the pre-activation and the transposed copy serve the backward
+          // pass only (absent in inference)
+          if (p.z) p.z[(long long)m * p.ldz + n] = zz;
+          if (p.ht) put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, hv, p.planes_out);
         } else if constexpr (EPI == E_OUTPUT) {
           const float y = v + p.bias[n];
           if (p.c) p.c[(long long)m * p.ldc + n] = p.alpha * y;
@@ -247,28 +249,34 @@ __global__ __launch_bounds__(256) void k_row_rms(const float* x, long long ld, i
   out[r] = (float)sqrt(s / cols);
 }
 
-template <int NPL, int EPI>
+template <int NPL, int EPI, int BK>
 int gemm_launch(const GemmArgs& a0, hipStream_t st) {
   GemmArgs a = a0;
   a.mtiles = (a.M + kGemmTile - 1) / kGemmTile;
   a.ntiles = (a.N + kGemmTile - 1) / kGemmTile;
   static bool lds_set = false;
   if (!lds_set) {
-    if (hipFuncSetAttribute((const void*)k_gemm<NPL, EPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)MfmaTile<NPL, false>::lds_bytes()) != hipSuccess)
+    if (hipFuncSetAttribute((const void*)k_gemm<NPL, EPI, BK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)MfmaTile<NPL, false, BK>::lds_bytes()) != hipSuccess)
       (void)hipGetLastError();
     lds_set = true;
   }
-  const size_t lds = MfmaTile<NPL, false>::lds_bytes();
-  hipLaunchKernelGGL((k_gemm<NPL, EPI>), dim3((unsigned)(a.mtiles * a.ntiles)), dim3(256), lds, st, a);
+  const size_t lds = MfmaTile<NPL, false, BK>::lds_bytes();
+  hipLaunchKernelGGL((k_gemm<NPL, EPI, BK>), dim3((unsigned)(a.mtiles * a.ntiles)), dim3(256), lds, st, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return mfail(PWFS_EHIP, "launch k_gemm: %s", hipGetErrorString(e));
   return PWFS_OK;
 }
 
+// One-plane products whose K is a multiple of 64 take K steps of 64 (8
+// matrix products per wavefront between barriers instead of 4, so load
+// latency hides behind them; same products in the same order, same bits).
+// Two-plane products keep steps of 32 (their 80 KB stages allow two
+// workgroups per CU; 64 would allow one).
 template <int EPI>
 int gemm_dispatch(int planes, const GemmArgs& a, hipStream_t st) {
-  return planes == 2 ? gemm_launch<2, EPI>(a, st) : gemm_launch<1, EPI>(a, st);
+  if (planes == 2) return gemm_launch<2, EPI, 32>(a, st);
+  return a.K % 64 == 0 ? gemm_launch<1, EPI, 64>(a, st) : gemm_launch<1, EPI, 32>(a, st);
 }
 
 int split_launch(const float* src, long long ld, int rows, int cols, int Kp, uint16_t* dst, long long plane,
@@ -563,12 +571,12 @@ int mlp_forward(pwfs_mlp_t m, const float* x, int batch, float* y, float out_sca
     g.planes_out = pl;
     const long long ap = (long long)m->Bm * m->P[l + 1];
     if (l + 1 < L) {
-      g.z = m->Z[l + 1];
+      g.z = target ? m->Z[l + 1] : nullptr;
       g.ldz = m->P[l + 1];
       g.h = m->H[l + 1];
       g.h_plane = ap;
       g.ldh = m->P[l + 1];
-      g.ht = m->Ht[l + 1];
+      g.ht = target ? m->Ht[l + 1] : nullptr;
       g.ht_plane = ap;
       g.ldht = m->Bm;
       if ((rc = gemm_dispatch<E_HIDDEN>(pl, g, st))) return rc;
