@@ -161,7 +161,8 @@ struct G1Args {
   const uint16_t* b;      // split field plane 0 [n_lam][F][D][Kp]; plane 1 at +b_plane
   uint16_t* t;            // T plane 0 [F][n_lam][n_a][Nc][Kp]; plane 1 at +t_plane
   long long a_plane, b_plane, t_plane;
-  int M, F, D, Kp, Nc, n_a, n_lam, mtiles, ntiles;
+  int M, F, D, Kp, Nc, n_a, n_lam;
+  int mtiles, ntiles;     // tiles over the M output rows and over all F D field rows of the pass
 };
 
 // Workgroups renumbered so that each of the 8 XCDs (which receive
@@ -290,7 +291,8 @@ struct G2Args {
   const int2* kord;       // [n_mod] (k, a)
   float* out;             // first frame of the pass, frame stride out_stride
   long long a_plane, t_plane, out_stride;
-  int M, F, Nc, N, D, Kp, n_a, n_lam, n_mod, mtiles, ntiles, win_lo, win_hi, full;
+  int M, F, Nc, N, D, Kp, n_a, n_lam, n_mod, win_lo, win_hi, full;
+  int mtiles, ntiles;     // tiles over the M rows of e and over all F Nc columns of the pass
   float scale[PWFS_MAX_LAMBDA];
 };
 
