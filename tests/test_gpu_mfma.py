@@ -62,7 +62,10 @@ def test_edge_sensors_mfma(prec):
              # a 300 nm band in 16 samples
              tiny_sensor(n_pupil=48, n_fft=128, n_subap=12, pupil_sep_px=56.0, n_mod=8, precision=prec,
                          lambdas_nm=band_sampling(750.0, 300.0, 16)[0],
-                         lambda_weights=band_sampling(750.0, 300.0, 16)[1])]
+                         lambda_weights=band_sampling(750.0, 300.0, 16)[1]),
+             # D not a multiple of 4: stage 1 stores element by element
+             tiny_sensor(n_pupil=42, n_fft=128, n_subap=6, pupil_sep_px=48.0, n_mod=8, obstruction=0.2,
+                         mod_radius_lod=3.0, precision=prec)]
     for s in cases:
         opd = von_karman_opd(3, s.n_pupil, 8.0, 0.5, 25.0, seed=7)
         print(f"[gpu] mfma {NAMES[prec]} D={s.n_pupil} N={s.n_fft} flags={s.flags}", flush=True)
@@ -81,12 +84,16 @@ def test_edge_sensors_mfma(prec):
 
 def test_edge_sensors_bf16():
     """The one-term form runs K steps of 64, so a pupil whose 2D is not a
-    multiple of 64 exercises the zero padding of both operands."""
+    multiple of 64 exercises the zero padding of both operands; D = 42 also
+    takes stage 1's element-by-element stores."""
     from workloads import von_karman_opd
     cases = [tiny_sensor(n_pupil=40, n_fft=128, n_subap=5, pupil_sep_px=48.0, n_mod=5, obstruction=0.3,
                          mod_radius_lod=3.0, precision=PREC_BF16),
              tiny_sensor(n_pupil=48, n_fft=128, n_subap=12, pupil_sep_px=56.0, n_mod=8, precision=PREC_BF16,
-                         lambdas_nm=(600.0, 750.0, 900.0), lambda_weights=(0.2, 0.3, 0.5), flags=3)]
+                         lambdas_nm=(600.0, 750.0, 900.0), lambda_weights=(0.2, 0.3, 0.5), flags=3),
+             # D not a multiple of 4, and K padding (128 - 84) longer than D
+             tiny_sensor(n_pupil=42, n_fft=128, n_subap=6, pupil_sep_px=48.0, n_mod=8, obstruction=0.2,
+                         mod_radius_lod=3.0, precision=PREC_BF16)]
     for s in cases:
         opd = von_karman_opd(3, s.n_pupil, 8.0, 0.5, 25.0, seed=7)
         print(f"[gpu] mfma bf16 D={s.n_pupil} N={s.n_fft} flags={s.flags}", flush=True)
