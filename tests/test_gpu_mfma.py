@@ -150,3 +150,27 @@ def test_160px_full_size_in_the_benchmark_launch(prec):
         print(f"      frame {f}: intensity {e:.2e} slopes {se:.2e}", flush=True)
         assert e <= 1e-3 and se <= 1e-3
         assert abs(fl[f] / f_ref[0] - 1) <= 1e-3
+
+
+@pytest.mark.parametrize("prec", [PREC_BF16X3, PREC_FP16X3, PREC_BF16])
+def test_pass_split_gives_the_same_bits(prec):
+    """Column tiles run across the frames of a pass, so where a tile straddles
+    two frames, and which tile is ragged, depend on the pass size.  Each output
+    element still sees the same products in the same order: 12 frames in one
+    pass and in passes of 5, 5, 2 (and of 1) give identical intensities and
+    slopes.  D = 40 gives Nc = 80 image columns per frame, 0.625 of a tile."""
+    from workloads import von_karman_opd
+    from paper_2602_06688_amd import pwfs as P
+    s = tiny_sensor(n_pupil=40, n_fft=128, n_subap=5, pupil_sep_px=48.0, n_mod=5, obstruction=0.3,
+                    mod_radius_lod=3.0, precision=prec)
+    opd = von_karman_opd(12, s.n_pupil, 8.0, 0.5, 25.0, seed=11)
+    x = torch.from_numpy(np.ascontiguousarray(opd, np.float32)).cuda()
+    plan = P.Plan([s], max_frames=12)
+    print(f"[gpu] mfma {NAMES[prec]} pass split: one pass of {plan.get_tuning()['chunk']}", flush=True)
+    I0, S0, F0 = [t.clone() for t in plan.step(x)]
+    for chunk in (5, 1):
+        print(f"[gpu] mfma {NAMES[prec]} pass split: passes of {chunk}", flush=True)
+        plan.set_tuning(chunk=chunk)
+        I1, S1, F1 = plan.step(x)
+        torch.cuda.synchronize()
+        assert torch.equal(I0, I1) and torch.equal(S0, S1) and torch.equal(F0, F1)
