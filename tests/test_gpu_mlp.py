@@ -131,6 +131,34 @@ def test_mlp_forward_grad_adam_vs_oracle(prec_name, tol, sizes, B):
         assert err <= 1e-6
 
 
+@pytest.mark.parametrize("prec_name", ["bf16", "bf16x3"])
+def test_inference_between_training_steps_changes_nothing(prec_name):
+    """Inference skips the activations only the backward pass reads; a
+    training step's gradients and loss are the same bits whether or not an
+    inference pass on other inputs (and another batch size) ran before it,
+    and inference gives the same outputs before and after training calls."""
+    P = _P()
+    from workloads.modes import init_params
+    prec = P.BF16X3 if prec_name == "bf16x3" else P.BF16
+    sizes = [40, 96, 64, 30]
+    rng = np.random.default_rng(8)
+    x = torch.from_numpy(rng.standard_normal((64, sizes[0])).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.standard_normal((64, sizes[-1])).astype(np.float32)).cuda()
+    xi = torch.from_numpy(rng.standard_normal((37, sizes[0])).astype(np.float32)).cuda()
+    mlp = P.MLP(sizes, max_batch=128, precision=prec)
+    mlp.set_params(torch.from_numpy(init_params(sizes, 5)).cuda())
+    print(f"[gpu] mlp {prec_name}: inference between training steps", flush=True)
+    g0 = torch.zeros(mlp.n_params, dtype=torch.float32, device="cuda")
+    g1 = torch.zeros_like(g0)
+    y0 = mlp.forward(xi).clone()
+    l0 = mlp.grad(x, t, grads=g0).clone()
+    y1 = mlp.forward(xi).clone()
+    l1 = mlp.grad(x, t, grads=g1).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(g0, g1) and torch.equal(l0, l1)
+    assert torch.equal(y0, y1)
+
+
 def test_training_loss_decreases():
     """A small teacher-student regression: 300 Adam steps cut the loss at least 4x."""
     P = _P()
