@@ -1,0 +1,80 @@
+"""Element-wise parity metrics shared by the GPU tests (test infrastructure).
+
+Besides the normwise figures of the error-metric reading (per-frame
+||I - I_ref|| / ||I_ref||, pooled slope RMS), every comparison bounds each
+element on its own, so that a wrong value in a few dim pixels or a handful of
+subapertures cannot hide inside a norm over 10^5 pixels or 10^3 subapertures:
+
+  pixel:  max over the frame's pixels of |I - I_ref| / (|I_ref| + mean|I_ref|)
+          (mean over the compared pixels of that frame: a bright pixel is held
+          to a relative bound, a dim one to the same fraction of the mean)
+  subap:  max over the frame's valid subapertures and both axes of
+          |s - s_ref| / (|s_ref| + rms(s_ref))   (rms over the frame's valid
+          subapertures and both axes)
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def pixel_error(I, I_ref) -> np.ndarray:
+    """Per-frame max of |I - I_ref| / (|I_ref| + mean |I_ref|) over the pixels
+    (arrays [F, ...] of any trailing shape)."""
+    a = np.asarray(I, np.float64).reshape(len(I_ref), -1)
+    b = np.asarray(I_ref, np.float64).reshape(len(I_ref), -1)
+    scale = np.abs(b) + np.abs(b).mean(axis=1, keepdims=True)
+    return (np.abs(a - b) / scale).max(axis=1)
+
+
+def subap_error(s, s_ref, valid) -> np.ndarray:
+    """Per-frame max of |s - s_ref| / (|s_ref| + rms s_ref) over valid subapertures."""
+    a = np.asarray(s, np.float64)[:, :, valid].reshape(len(s_ref), -1)
+    b = np.asarray(s_ref, np.float64)[:, :, valid].reshape(len(s_ref), -1)
+    rms = np.sqrt((b ** 2).mean(axis=1, keepdims=True))
+    return (np.abs(a - b) / (np.abs(b) + rms)).max(axis=1)
+
+
+def normwise_error(I, I_ref) -> np.ndarray:
+    a = np.asarray(I, np.float64).reshape(len(I_ref), -1)
+    b = np.asarray(I_ref, np.float64).reshape(len(I_ref), -1)
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+def slope_rms_error(s, s_ref, valid) -> float:
+    a = np.asarray(s, np.float64)[:, :, valid]
+    b = np.asarray(s_ref, np.float64)[:, :, valid]
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def errors(I, I_ref, s, s_ref, valid) -> dict:
+    """All four figures: worst frame of each per-frame one, the pooled slope RMS."""
+    return {"normwise": float(normwise_error(I, I_ref).max()), "pixel": float(pixel_error(I, I_ref).max()),
+            "slope_rms": slope_rms_error(s, s_ref, valid), "subap": float(subap_error(s, s_ref, valid).max())}
+
+
+def fmt(e: dict) -> str:
+    return (f"intensity normwise {e['normwise']:.2e} pixel {e['pixel']:.2e}; "
+            f"slopes rms {e['slope_rms']:.2e} subap {e['subap']:.2e}")
+
+
+def check(e: dict, bounds: dict) -> None:
+    """Asserts every figure named in ``bounds`` is within it."""
+    bad = {k: (e[k], b) for k, b in bounds.items() if not e[k] <= b}
+    assert not bad, "over bound (value, bound): " + ", ".join(f"{k} {v:.3e} > {b:.1e}" for k, (v, b) in bad.items())
+
+
+# Bounds per arithmetic, a small multiple of what each form reaches on the
+# GPU (worst case over the parity cases):
+#   FP32:    normwise 2.8e-7, pixel 5.0e-7, slope rms 3.7e-7, subap 1.0e-6;
+#            the sensor's stated 1e-5 on intensities (also per element) and
+#            1e-4 pooled on slopes, 1e-5 per subaperture;
+#   bf16 x3: normwise 4.1e-6, pixel 1.1e-5, slope rms 1.7e-6, subap 7.2e-6;
+#   fp16 x3: normwise 1.7e-7, pixel 6.3e-7, slope rms 2.7e-7, subap 8.6e-7;
+#   bf16:    normwise 2.2e-3, pixel 5.7e-3, slope rms 1.1e-3, subap 4.1e-3.
+# A split form that lost one of its three products would err near the
+# one-term form (~1e-3) and fail every split bound.
+FP32 = {"normwise": 1e-5, "pixel": 1e-5, "slope_rms": 1e-4, "subap": 1e-5}
+BF16X3 = {"normwise": 2e-5, "pixel": 5e-5, "slope_rms": 1e-5, "subap": 5e-5}
+FP16X3 = {"normwise": 1e-6, "pixel": 5e-6, "slope_rms": 1e-6, "subap": 5e-6}
+BF16 = {"normwise": 5e-3, "pixel": 2e-2, "slope_rms": 3e-3, "subap": 2e-2}

@@ -1,22 +1,30 @@
 """Matrix-core (DFT-as-GEMM) precision form against the FP64 oracle.
 
 The split forms carry ~16 (bf16 x3) or ~22 (fp16 x3) significand bits per
-operand with fp32 accumulation; the one-term bf16 form carries 8.  Bounds:
-  bf16 x3 / fp16 x3: slopes <= 1e-3 pooled relative RMS (the stated target
-                     for the matrix-core form), intensity <= 1e-3 per frame;
-  bf16 x1:           reported, bounded loosely (slopes <= 5e-2).
+operand with fp32 accumulation; the one-term bf16 form carries 8.  Every
+comparison bounds the normwise figures and every pixel and subaperture on its
+own (tests/parity.py), at a small multiple of what each form reaches, so that
+a split that lost one of its three products (an error near the one-term
+form's ~1e-3) fails:
+  bf16 x3: intensity normwise 2e-5, pixel 5e-5; slopes pooled 1e-5, subap 5e-5
+  fp16 x3: intensity normwise 1e-6, pixel 5e-6; slopes pooled 1e-6, subap 5e-6
+  bf16:    intensity normwise 5e-3, pixel 2e-2; slopes pooled 3e-3, subap 2e-2
+The one-term form is held to the 1e-3 slope target of the matrix-core forms
+on the 160 px sensor in the benchmark's 1000-frame launch; on the 64 px
+sensor it reaches ~1.1e-3, above that target, and is reported as such.
 """
 
 import numpy as np
 import pytest
 
+import parity
 from oracle import pwfs as O
 from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16X3, band_sampling, tiny_sensor, workload, workload_opd
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-BOUNDS = {PREC_BF16X3: (1e-3, 1e-3), PREC_FP16X3: (1e-3, 1e-3), PREC_BF16: (5e-2, 5e-2)}
+BOUNDS = {PREC_BF16X3: parity.BF16X3, PREC_FP16X3: parity.FP16X3, PREC_BF16: parity.BF16}
 NAMES = {PREC_BF16X3: "bf16x3", PREC_FP16X3: "fp16x3", PREC_BF16: "bf16"}
 
 
@@ -42,12 +50,9 @@ def test_64px_all_frames(prec):
     I, sl, fl = _run(s, opd)
     I_ref = O.forward(opd, w.sensors[0])
     s_ref, f_ref = O.slopes(I_ref, w.sensors[0])
-    e = O.intensity_rel_error(_windows(I, s), _windows(I_ref, s))
-    se = O.slope_rel_rms(sl, s_ref, O.valid_subapertures(s))
-    print(f"      intensity max {e.max():.2e} mean {e.mean():.2e}, slopes {se:.2e}, "
-          f"flux {np.abs(fl / f_ref - 1).max():.2e}", flush=True)
-    bi, bs = BOUNDS[prec]
-    assert e.max() <= bi and se <= bs
+    err = parity.errors(_windows(I, s), _windows(I_ref, s), sl, s_ref, O.valid_subapertures(s))
+    print(f"      {parity.fmt(err)}; flux {np.abs(fl / f_ref - 1).max():.2e}", flush=True)
+    parity.check(err, BOUNDS[prec])
 
 
 @pytest.mark.parametrize("prec", [PREC_BF16X3, PREC_FP16X3])
@@ -74,12 +79,11 @@ def test_edge_sensors_mfma(prec):
         I_ref = O.forward(opd, ref_s)
         s_ref, _ = O.slopes(I_ref, ref_s)
         if s.flags & 2:
-            e = O.intensity_rel_error(I, I_ref)
+            err = parity.errors(I, I_ref, sl, s_ref, O.valid_subapertures(s))
         else:
-            e = O.intensity_rel_error(_windows(I, s), _windows(I_ref, s))
-        se = O.slope_rel_rms(sl, s_ref, O.valid_subapertures(s))
-        print(f"      intensity {e.max():.2e}, slopes {se:.2e}", flush=True)
-        assert e.max() <= 1e-3 and se <= 1e-3
+            err = parity.errors(_windows(I, s), _windows(I_ref, s), sl, s_ref, O.valid_subapertures(s))
+        print(f"      {parity.fmt(err)}", flush=True)
+        parity.check(err, BOUNDS[prec])
 
 
 def test_edge_sensors_bf16():
@@ -102,12 +106,11 @@ def test_edge_sensors_bf16():
         I_ref = O.forward(opd, ref_s)
         s_ref, _ = O.slopes(I_ref, ref_s)
         if s.flags & 2:
-            e = O.intensity_rel_error(I, I_ref)
+            err = parity.errors(I, I_ref, sl, s_ref, O.valid_subapertures(s))
         else:
-            e = O.intensity_rel_error(_windows(I, s), _windows(I_ref, s))
-        se = O.slope_rel_rms(sl, s_ref, O.valid_subapertures(s))
-        print(f"      intensity {e.max():.2e}, slopes {se:.2e}", flush=True)
-        assert e.max() <= BOUNDS[PREC_BF16][0] and se <= BOUNDS[PREC_BF16][1]
+            err = parity.errors(_windows(I, s), _windows(I_ref, s), sl, s_ref, O.valid_subapertures(s))
+        print(f"      {parity.fmt(err)}", flush=True)
+        parity.check(err, BOUNDS[PREC_BF16])
 
 
 def test_160px_sampled_bf16x3():
@@ -120,19 +123,19 @@ def test_160px_sampled_bf16x3():
     for f in (0, 63):
         I_ref = O.forward(opd[f:f + 1], w.sensors[0])
         s_ref, _ = O.slopes(I_ref, w.sensors[0])
-        e = O.intensity_rel_error(_windows(I[f:f + 1], s), _windows(I_ref, s))[0]
-        se = O.slope_rel_rms(sl[f:f + 1], s_ref, valid)
-        print(f"      frame {f}: intensity {e:.2e} slopes {se:.2e}", flush=True)
-        assert e <= 1e-3 and se <= 1e-3
+        err = parity.errors(_windows(I[f:f + 1], s), _windows(I_ref, s), sl[f:f + 1], s_ref, valid)
+        print(f"      frame {f}: {parity.fmt(err)}", flush=True)
+        parity.check(err, parity.BF16X3)
 
 
-@pytest.mark.parametrize("prec", [PREC_BF16X3, PREC_FP16X3])
+@pytest.mark.parametrize("prec", [PREC_BF16X3, PREC_FP16X3, PREC_BF16])
 def test_160px_full_size_in_the_benchmark_launch(prec):
-    """All 1000 frames in one plan, as the bench launches the split forms.
-    A frame's 320 image columns are 2.5 column tiles, so odd frames start in
-    the middle of a tile shared with the frame before; frames 0, 1 (the first
-    straddling tile), 517 and 999 against the oracle, every frame finite with
-    its flux in range."""
+    """All 1000 frames in one plan, as the bench launches the matrix-core
+    forms.  A frame's 320 image columns are 2.5 column tiles, so odd frames
+    start in the middle of a tile shared with the frame before; frames 0, 1
+    (the first straddling tile), 517 and 999 against the oracle, every frame
+    finite with its flux in range.  The one-term bf16 form is held here to
+    the 1e-3 relative slope RMS target of the matrix-core forms."""
     w = workload("cfg2")
     s = w.sensors[0].with_(precision=prec)
     print(f"[gpu] mfma {NAMES[prec]} 160px 1000 frames: inputs", flush=True)
@@ -142,14 +145,21 @@ def test_160px_full_size_in_the_benchmark_launch(prec):
     assert np.isfinite(I).all() and np.isfinite(sl).all()
     assert (fl > 0.5).all() and (fl < 1.0 + 1e-3).all()
     valid = O.valid_subapertures(s)
-    for f in (0, 1, 517, 999):
+    frames = (0, 1, 517, 999)
+    refs = []
+    for f in frames:
         I_ref = O.forward(opd[f:f + 1], w.sensors[0])
-        s_ref, f_ref = O.slopes(I_ref, w.sensors[0])
-        e = O.intensity_rel_error(_windows(I[f:f + 1], s), _windows(I_ref, s))[0]
-        se = O.slope_rel_rms(sl[f:f + 1], s_ref, valid)
-        print(f"      frame {f}: intensity {e:.2e} slopes {se:.2e}", flush=True)
-        assert e <= 1e-3 and se <= 1e-3
-        assert abs(fl[f] / f_ref[0] - 1) <= 1e-3
+        refs.append(O.slopes(I_ref, w.sensors[0]) + (I_ref,))
+    for f, (s_ref, f_ref, I_ref) in zip(frames, refs):
+        err = parity.errors(_windows(I[f:f + 1], s), _windows(I_ref, s), sl[f:f + 1], s_ref, valid)
+        print(f"      frame {f}: {parity.fmt(err)}", flush=True)
+        parity.check(err, BOUNDS[prec])
+        assert abs(fl[f] / f_ref[0] - 1) <= (1e-3 if prec == PREC_BF16 else 1e-5)
+    if prec == PREC_BF16:
+        pooled = parity.slope_rms_error(np.concatenate([sl[f:f + 1] for f in frames]),
+                                        np.concatenate([r[0] for r in refs]), valid)
+        print(f"      bf16 one-term, pooled slope rms over the sampled frames {pooled:.2e}", flush=True)
+        assert pooled <= 1e-3
 
 
 @pytest.mark.parametrize("prec", [PREC_BF16X3, PREC_FP16X3, PREC_BF16])

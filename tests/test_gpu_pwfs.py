@@ -1,9 +1,12 @@
 """GPU parity of the FP32 forward model and slope stage against the FP64 oracle.
 
-Tolerances (float32 arithmetic, float64 phase reduction and tables):
+Tolerances (float32 arithmetic, float64 phase reduction and tables), each
+compared element by element as well as normwise (tests/parity.py):
   intensity: per-frame normwise relative error <= 1e-5 (the sensor's stated
-             bound for the plain FP32 path);
-  slopes:    pooled relative RMS over valid subapertures <= 1e-4;
+             bound for the plain FP32 path), and every pixel within 1e-5 of
+             (|I_ref| + the frame's mean);
+  slopes:    pooled relative RMS over valid subapertures <= 1e-4, and every
+             valid subaperture within 1e-5 of (|s_ref| + the frame's RMS);
   flux:      relative 1e-5.
 """
 
@@ -12,6 +15,7 @@ import math
 import numpy as np
 import pytest
 
+import parity
 from oracle import pwfs as O
 from workloads import band_sampling, tiny_sensor, workload, workload_opd
 
@@ -53,16 +57,17 @@ def _check(s, opd, plan_frames=None, label=""):
     s_ref, f_ref = O.slopes(I_ref, s)
     valid = O.valid_subapertures(s)
     if s.flags & P.F_FULL_PLANE:
-        e = O.intensity_rel_error(I, I_ref)
+        err = parity.errors(I, I_ref, sl, s_ref, valid)
         assert np.abs(I.sum(axis=(1, 2)) - I_ref.sum(axis=(1, 2))).max() < 1e-5   # 1 without a field stop
     else:
-        e = O.intensity_rel_error(_windows(I, s), _windows(I_ref, s))
-    se = O.slope_rel_rms(sl, s_ref, valid) if np.linalg.norm(s_ref[:, :, valid]) > 0 else \
-        float(np.abs(sl).max())
+        err = parity.errors(_windows(I, s), _windows(I_ref, s), sl, s_ref, valid)
     fe = np.abs(flux / f_ref - 1).max()
-    _say(f"      intensity max rel err {e.max():.2e}, slope rel rms {se:.2e}, flux {fe:.2e}")
-    assert e.max() <= INT_TOL
-    assert se <= SLOPE_TOL
+    _say(f"      {parity.fmt(err)}; flux {fe:.2e}")
+    bounds = dict(parity.FP32)
+    if not np.linalg.norm(s_ref[:, :, valid]) > 0:   # a sensor whose slopes are all zero
+        bounds = {k: v for k, v in bounds.items() if k in ("normwise", "pixel")}
+        assert float(np.abs(sl).max()) <= SLOPE_TOL
+    parity.check(err, bounds)
     assert fe <= 1e-5
     assert np.array_equal(plan.valid_map(0), valid)
     assert (sl[:, :, ~valid] == 0).all()
@@ -164,8 +169,9 @@ def test_multi_sensor_plan_packs_sensors():
         Ss = sl[:, info.slope_offset:info.slope_offset + 2 * n * n].reshape(2, 2, n, n).astype(np.float64)
         I_ref = O.forward(o, s)
         s_ref, _ = O.slopes(I_ref, s)
-        assert O.intensity_rel_error(_windows(Is, s), _windows(I_ref, s)).max() <= INT_TOL
-        assert O.slope_rel_rms(Ss, s_ref, O.valid_subapertures(s)) <= SLOPE_TOL
+        err = parity.errors(_windows(Is, s), _windows(I_ref, s), Ss, s_ref, O.valid_subapertures(s))
+        _say(f"      D={s.n_pupil}: {parity.fmt(err)}")
+        parity.check(err, parity.FP32)
 
 
 def test_cfg2_full_size_sampled():
@@ -192,10 +198,10 @@ def test_cfg2_full_size_sampled():
     for f in (0, 517, 999):
         I_ref = O.forward(opd[f:f + 1], s)
         s_ref, f_ref = O.slopes(I_ref, s)
-        e = O.intensity_rel_error(_windows(In[f:f + 1].astype(np.float64), s), _windows(I_ref, s))[0]
-        se = O.slope_rel_rms(sn[f:f + 1], s_ref, valid)
-        _say(f"      frame {f}: intensity {e:.2e} slopes {se:.2e}")
-        assert e <= INT_TOL and se <= SLOPE_TOL
+        err = parity.errors(_windows(In[f:f + 1].astype(np.float64), s), _windows(I_ref, s), sn[f:f + 1], s_ref,
+                            valid)
+        _say(f"      frame {f}: {parity.fmt(err)}")
+        parity.check(err, parity.FP32)
         assert abs(fn[f] / f_ref[0] - 1) <= 1e-5
 
 
@@ -301,8 +307,8 @@ def test_sixteen_wavelengths_in_the_benchmark_launch():
     torch.cuda.synchronize()
     f = 199
     I_ref = O.forward(opd[f:f + 1].astype(np.float64), s)
-    e = O.intensity_rel_error(_windows(I[f:f + 1].cpu().numpy(), s), _windows(I_ref, s))[0]
     s_ref, _ = O.slopes(I_ref, s)
-    se = O.slope_rel_rms(sl[f:f + 1].cpu().numpy(), s_ref, O.valid_subapertures(s))
-    _say(f"      frame {f}: intensity rel err {e:.2e}, slope rel rms {se:.2e}")
-    assert e <= INT_TOL and se <= SLOPE_TOL
+    err = parity.errors(_windows(I[f:f + 1].cpu().numpy(), s), _windows(I_ref, s), sl[f:f + 1].cpu().numpy(), s_ref,
+                        O.valid_subapertures(s))
+    _say(f"      frame {f}: {parity.fmt(err)}")
+    parity.check(err, parity.FP32)
