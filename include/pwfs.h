@@ -192,15 +192,29 @@ int pwfs_slopes(pwfs_plan_t plan, const float* d_intensity, int n_frames, float*
  *  chunk      frames per pass, 1 .. max_chunk (set by the workspace size)
  *  wg_per_cu  persistent workgroups per compute unit, 1 .. 8
  *  row_groups minimum number of row-pass work items per pass
+ *  spin_limit polls of a persistent pass's dependency wait before it gives
+ *             up (0 = the default, 2^24); a wait that gives up skips its
+ *             work item and sets the plan's sticky error flag (pwfs_device_status).
+ *             A negative value makes every wait give up at once: a failure
+ *             forced from the host, for testing that path
  */
 enum { PWFS_MODE_LAUNCHES = 0, PWFS_MODE_PERSISTENT = 1 };
 typedef struct {
-  int32_t mode, chunk, wg_per_cu, row_groups, max_chunk, reserved[3];
+  int32_t mode, chunk, wg_per_cu, row_groups, max_chunk, spin_limit, reserved[2];
 } pwfs_tuning;
 int pwfs_get_tuning(pwfs_plan_t plan, pwfs_tuning* out);
 /* PWFS_EUNSUPPORTED for the persistent mode unless every sensor is FP32 with
  * N >= 256 and at most 3 non-zero inputs per first-stage butterfly. */
 int pwfs_set_tuning(pwfs_plan_t plan, const pwfs_tuning* tuning);
+
+/*
+ * Device-side status of the plan's work enqueued on hip_stream so far:
+ * synchronises hip_stream, then returns PWFS_EHIP (message in
+ * pwfs_last_error) if a persistent pass's dependency wait gave up since the
+ * last call (those calls' intensities may be incomplete), and clears the
+ * flag; PWFS_OK otherwise.  Not for use under graph capture.
+ */
+int pwfs_device_status(pwfs_plan_t plan, void* hip_stream);
 
 /* Geometry and packing of sensor `sensor` of the plan. */
 int pwfs_query(pwfs_plan_t plan, int sensor, pwfs_sensor_info* info);
@@ -419,6 +433,16 @@ int pwfs_mlp_param_count(pwfs_mlp_t mlp, size_t* count);
 /* Loads parameters (device, packed) and clears the Adam state and step. */
 int pwfs_mlp_set_params(pwfs_mlp_t mlp, const float* d_params, void* hip_stream);
 int pwfs_mlp_get_params(pwfs_mlp_t mlp, float* d_params, void* hip_stream);
+/*
+ * Optimiser state, for checkpoint and resume: d_moments [2 * param_count]
+ * holds Adam's first moments then its second moments, each packed like the
+ * parameters, and *step the number of Adam steps taken.  Restoring a
+ * checkpoint is pwfs_mlp_set_params then pwfs_mlp_set_state (in that order:
+ * set_params clears the state); training then continues exactly as it would
+ * have without the interruption (same bits, given the same batches).
+ */
+int pwfs_mlp_get_state(pwfs_mlp_t mlp, float* d_moments, long long* step, void* hip_stream);
+int pwfs_mlp_set_state(pwfs_mlp_t mlp, const float* d_moments, long long step, void* hip_stream);
 /* d_y [batch][sizes[n]] = out_scale * network(d_x [batch][sizes[0]]), 1 <= batch <= max_batch. */
 int pwfs_mlp_forward(pwfs_mlp_t mlp, const float* d_x, int batch, float* d_y, float out_scale, void* hip_stream);
 /*

@@ -653,8 +653,13 @@ __global__ __launch_bounds__(NT) void k_slopes(SlopeArgs p) {
 // published with an agent-scope release after a workgroup barrier, waits use
 // agent-scope acquire loads, so data written on one XCD is read coherently
 // on another.  Items are claimed in increasing order and only wait for
-// smaller items that running workgroups already own, so every wait ends; a
-// spin limit turns a broken schedule into an error flag instead of a hang.
+// smaller items that running workgroups already own, so every wait ends.  A
+// spin limit turns a broken schedule into an error instead of a hang: a wait
+// that gives up sets a sticky flag (counters[1 + 2 kMaxHetero], read and
+// cleared by pwfs_device_status) and skips its item, whose outputs are then
+// incomplete; the item still counts as done, so the launch drains and ends.
+// A negative spin limit makes every wait give up at once (a failure forced
+// from the host, to test that path).
 namespace pwfs {
 
 constexpr int kMaxHetero = 8;
@@ -669,6 +674,10 @@ struct HeteroArgs {
   int n_sensors, total, spin_limit;
   int* counters;   // [0] claim, [1 + 2 s] field done, [2 + 2 s] rows done, [1 + 2 kMaxHetero] error flag
 };
+
+// index of the sticky error flag in the counters; the per-pass reset clears
+// the counters below it only
+constexpr int kHeteroFlag = 1 + 2 * kMaxHetero;
 
 __global__ void k_counter_reset(int* c, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
@@ -685,7 +694,7 @@ __device__ __forceinline__ void hetero_cols(const ColArgs& a, int bid, float2* s
 
 __global__ __launch_bounds__(kBlock, 1) void k_hetero(HeteroArgs p) {
   extern __shared__ float2 smem[];
-  __shared__ int s_item;
+  __shared__ int s_item, s_skip;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&p.counters[0], 1);
     __syncthreads();
@@ -706,22 +715,25 @@ __global__ __launch_bounds__(kBlock, 1) void k_hetero(HeteroArgs p) {
       }
       if (found) break;
     }
+    bool skip = false;
     if (kind > 0) {
       if (threadIdx.x == 0) {
         int* dep = &p.counters[1 + 2 * s + (kind - 1)];
         const int need = p.n_items[kind - 1][s];
-        int spins = 0;
-        while (__hip_atomic_load(dep, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        int spins = 0, gave_up = p.spin_limit < 0;
+        while (!gave_up && __hip_atomic_load(dep, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
           __builtin_amdgcn_s_sleep(2);
-          if (++spins > p.spin_limit) {
-            atomicExch(&p.counters[1 + 2 * kMaxHetero], 1);
-            break;
-          }
+          if (++spins > p.spin_limit) gave_up = 1;
         }
+        if (gave_up) atomicExch(&p.counters[kHeteroFlag], 1);
+        s_skip = gave_up;
       }
       __syncthreads();
+      skip = __builtin_amdgcn_readfirstlane(s_skip) != 0;
     }
-    if (kind == 0) {
+    if (skip) {
+      // the item's inputs may be incomplete: leave its outputs untouched
+    } else if (kind == 0) {
       field_body(p.field[s], item);
     } else if (kind == 1) {
       switch (p.nfft[s]) {

@@ -657,8 +657,8 @@ int forward_hetero(pwfs_plan_s* p, const float* opd, int f0, int nf, float* out,
   for (int i = 0; i < ns; ++i) ha.order[i] = cost[i].second;   // largest sensors claim first
   ha.total = total;
   ha.counters = p->counters;
-  ha.spin_limit = 1 << 24;
-  hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, p->counters, 1 + 2 * kMaxHetero + 1);
+  ha.spin_limit = p->tune.spin_limit != 0 ? p->tune.spin_limit : (1 << 24);
+  hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, p->counters, kHeteroFlag);
   HIP_TRY(hipGetLastError(), "launch k_counter_reset");
   const int grid = p->n_cu * std::max(1, p->tune.wg_per_cu);
   const int slot = p->prof.begin(st);
@@ -918,6 +918,13 @@ int pwfs_plan(const pwfs_sensor_desc* s, int n, int max_frames, void* ws, size_t
   p->opd_stride = opd;
   p->int_stride = inten;
   p->slope_stride = sl;
+  // the persistent pass's counters and its sticky error flag start at zero
+  hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, p->counters, 64);
+  if (hipError_t e0 = hipGetLastError(); e0 != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    delete p;
+    return hip_fail(e0, "launch k_counter_reset");
+  }
   // reference slopes of a flat wavefront, sensor by sensor
   for (int i = 0; i < n && rc == 0; ++i) {
     const SensorPlan& sp = p->s[i];
@@ -976,6 +983,7 @@ int pwfs_set_tuning(pwfs_plan_t p, const pwfs_tuning* t) {
     return fail(PWFS_EINVAL, "chunk must be in [1, %d] (the workspace's pass size)", p->max_chunk);
   if (t->wg_per_cu < 1 || t->wg_per_cu > 8) return fail(PWFS_EINVAL, "wg_per_cu must be in [1, 8]");
   if (t->row_groups < 1 || t->row_groups > (1 << 20)) return fail(PWFS_EINVAL, "row_groups out of range");
+  if (t->reserved[0] != 0 || t->reserved[1] != 0) return fail(PWFS_EINVAL, "reserved fields must be 0");
   if (t->mode == PWFS_MODE_PERSISTENT) {
     if ((int)p->s.size() > kMaxHetero) return fail(PWFS_EUNSUPPORTED, "persistent mode takes at most 8 sensors");
     for (const SensorPlan& sp : p->s)
@@ -987,6 +995,24 @@ int pwfs_set_tuning(pwfs_plan_t p, const pwfs_tuning* t) {
   p->tune.max_chunk = p->max_chunk;
   p->chunk = t->chunk;
   return PWFS_OK;
+}
+
+int pwfs_device_status(pwfs_plan_t p, void* stream) {
+  if (!p) return fail(PWFS_EINVAL, "plan is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  int flag = 0;
+  const int zero = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, p->counters + kHeteroFlag, sizeof(int), hipMemcpyDeviceToHost, st),
+          "hipMemcpyAsync(status)");
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(status)");
+  if (!flag) return PWFS_OK;
+  HIP_TRY(hipMemcpyAsync(p->counters + kHeteroFlag, &zero, sizeof(int), hipMemcpyHostToDevice, st),
+          "hipMemcpyAsync(status clear)");
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(status clear)");
+  return fail(PWFS_EHIP,
+              "a dependency wait of a persistent pass gave up (spin limit %d): the intensities of the calls since "
+              "the last status check may be incomplete",
+              p->tune.spin_limit != 0 ? p->tune.spin_limit : (1 << 24));
 }
 
 int pwfs_slopes(pwfs_plan_t p, const float* in, int nf, float* slopes, float* flux, void* stream) {

@@ -349,7 +349,8 @@ extern "C" int pwfs_row_rms(const float* x, long long ld, int rows, int cols, fl
 
 // ================================================================= MLP ABI ==
 struct pwfs_mlp_s {
-  int L = 0, Bm = 0, precision = 0, planes = 1, step = 0;
+  int L = 0, Bm = 0, precision = 0, planes = 1;
+  long long step = 0;                        // Adam steps taken
   std::vector<int> n, P;                     // true and padded sizes, L + 1 each
   // per layer l (0..L-1)
   std::vector<float*> W, b, mW, vW, mb, vb, gW, gb;
@@ -540,6 +541,48 @@ extern "C" int pwfs_mlp_get_params(pwfs_mlp_t m, float* params, void* stream) {
     if ((rc = copy2d(m->b[l], no, params + off, no, 1, no, st))) return rc;
     off += no;
   }
+  return PWFS_OK;
+}
+
+// the Adam moments, each packed like the parameters: m, then v
+extern "C" int pwfs_mlp_get_state(pwfs_mlp_t m, float* moments, long long* step, void* stream) {
+  if (!m || !moments || !step) return mfail(PWFS_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  size_t count = 0;
+  pwfs_mlp_param_count(m, &count);
+  int rc;
+  for (int which = 0; which < 2; ++which) {
+    size_t off = which * count;
+    for (int l = 0; l < m->L; ++l) {
+      const int no = m->n[l + 1], ni = m->n[l];
+      if ((rc = copy2d(which ? m->vW[l] : m->mW[l], m->P[l], moments + off, ni, no, ni, st))) return rc;
+      off += (size_t)no * ni;
+      if ((rc = copy2d(which ? m->vb[l] : m->mb[l], no, moments + off, no, 1, no, st))) return rc;
+      off += no;
+    }
+  }
+  *step = m->step;
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_mlp_set_state(pwfs_mlp_t m, const float* moments, long long step, void* stream) {
+  if (!m || !moments) return mfail(PWFS_EINVAL, "NULL argument");
+  if (step < 0) return mfail(PWFS_EINVAL, "step must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  size_t count = 0;
+  pwfs_mlp_param_count(m, &count);
+  int rc;
+  for (int which = 0; which < 2; ++which) {
+    size_t off = which * count;
+    for (int l = 0; l < m->L; ++l) {
+      const int no = m->n[l + 1], ni = m->n[l];
+      if ((rc = copy2d(moments + off, ni, which ? m->vW[l] : m->mW[l], m->P[l], no, ni, st))) return rc;
+      off += (size_t)no * ni;
+      if ((rc = copy2d(moments + off, no, which ? m->vb[l] : m->mb[l], no, 1, no, st))) return rc;
+      off += no;
+    }
+  }
+  m->step = step;
   return PWFS_OK;
 }
 

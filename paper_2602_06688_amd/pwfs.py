@@ -64,7 +64,8 @@ class CSensorInfo(ctypes.Structure):
 
 class CTuning(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("row_groups", ctypes.c_int32), ("max_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("row_groups", ctypes.c_int32), ("max_chunk", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 MODE_LAUNCHES = 0
@@ -129,6 +130,7 @@ def lib() -> ctypes.CDLL:
     L.pwfs_forward.argtypes = [vp, vp, i32, vp, vp]
     L.pwfs_slopes.argtypes = [vp, vp, i32, vp, vp, vp]
     L.pwfs_query.argtypes = [vp, i32, P(CSensorInfo)]
+    L.pwfs_device_status.argtypes = [vp, vp]
     L.pwfs_valid_map.argtypes = [vp, i32, P(ctypes.c_uint8)]
     L.pwfs_last_error.restype = ctypes.c_char_p
     L.pwfs_last_error.argtypes = []
@@ -160,15 +162,18 @@ def lib() -> ctypes.CDLL:
     L.pwfs_mlp_param_count.argtypes = [vp, P(ctypes.c_size_t)]
     L.pwfs_mlp_set_params.argtypes = [vp, vp, vp]
     L.pwfs_mlp_get_params.argtypes = [vp, vp, vp]
+    L.pwfs_mlp_get_state.argtypes = [vp, vp, P(ctypes.c_longlong), vp]
+    L.pwfs_mlp_set_state.argtypes = [vp, vp, ctypes.c_longlong, vp]
     L.pwfs_mlp_forward.argtypes = [vp, vp, i32, vp, ctypes.c_float, vp]
     L.pwfs_mlp_grad.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp]
     L.pwfs_mlp_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
     L.pwfs_mlp_destroy.argtypes = [vp]
     L.pwfs_mlp_destroy.restype = None
     for name in ("pwfs_validate", "pwfs_workspace_size", "pwfs_plan", "pwfs_forward", "pwfs_slopes",
-                 "pwfs_query", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
+                 "pwfs_query", "pwfs_device_status", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
                  "pwfs_gemm_workspace_size", "pwfs_gemm", "pwfs_row_rms", "pwfs_mlp_workspace_size",
                  "pwfs_mlp_create", "pwfs_mlp_param_count", "pwfs_mlp_set_params", "pwfs_mlp_get_params",
+                 "pwfs_mlp_get_state", "pwfs_mlp_set_state",
                  "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam", "pwfs_ccd", "pwfs_ccd_slopes", "pwfs_layers", "pwfs_integrator", "pwfs_gemv", "pwfs_sh_validate",
                  "pwfs_sh_workspace_size", "pwfs_sh_plan", "pwfs_sh_forward", "pwfs_sh_query"):
         getattr(L, name).restype = i32
@@ -369,15 +374,21 @@ class Plan:
         t = CTuning()
         check(lib().pwfs_get_tuning(self._h, ctypes.byref(t)))
         return {"mode": t.mode, "chunk": t.chunk, "wg_per_cu": t.wg_per_cu, "row_groups": t.row_groups,
-                "max_chunk": t.max_chunk}
+                "max_chunk": t.max_chunk, "spin_limit": t.spin_limit}
 
     def set_tuning(self, **kw) -> dict:
         cur = self.get_tuning()
         cur.update({k: v for k, v in kw.items() if v is not None})
         t = CTuning(int(cur["mode"]), int(cur["chunk"]), int(cur["wg_per_cu"]), int(cur["row_groups"]),
-                    int(cur["max_chunk"]))
+                    int(cur["max_chunk"]), int(cur["spin_limit"]))
         check(lib().pwfs_set_tuning(self._h, ctypes.byref(t)))
         return self.get_tuning()
+
+    def status(self, stream=None) -> None:
+        """Synchronises the stream and raises PwfsError (PWFS_EHIP) if a
+        persistent pass's dependency wait gave up since the last check
+        (pwfs_device_status); the flag is cleared."""
+        check(lib().pwfs_device_status(self._h, _stream_ptr(stream)))
 
     def profile(self, max_launches: int) -> None:
         """Time the next ``max_launches`` kernel launches with HIP events (0 = off)."""
@@ -572,6 +583,21 @@ class MLP:
         out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
         check(lib().pwfs_mlp_get_params(self._h, _dev_ptr(out, "params", torch.float32), _stream_ptr(stream)))
         return out
+
+    def get_state(self, stream=None):
+        """(Adam moments [2 * n_params] device tensor, step): m then v, each packed like the parameters."""
+        import torch
+        out = torch.empty(2 * self.n_params, dtype=torch.float32, device=self.device)
+        step = ctypes.c_longlong()
+        check(lib().pwfs_mlp_get_state(self._h, _dev_ptr(out, "moments", torch.float32), ctypes.byref(step),
+                                       _stream_ptr(stream)))
+        return out, step.value
+
+    def set_state(self, moments, step: int, stream=None):
+        """Restores the Adam state (after set_params, which clears it)."""
+        import torch
+        check(lib().pwfs_mlp_set_state(self._h, _dev_ptr(moments, "moments", torch.float32, 2 * self.n_params),
+                                       int(step), _stream_ptr(stream)))
 
     def forward(self, x, out=None, out_scale: float = 1.0, stream=None):
         import torch

@@ -186,6 +186,55 @@ def test_training_loss_decreases():
     assert last < 0.25 * first
 
 
+@pytest.mark.parametrize("prec_name", ["bf16", "bf16x3"])
+def test_checkpoint_resume_is_bit_exact(prec_name):
+    """Training interrupted after k Adam steps and resumed in a fresh network
+    from (parameters, Adam moments, step) ends on the same bits as training
+    straight through, given the same batches: a checkpoint holds all the
+    optimiser's state.  Restoring the parameters alone (moments cleared, step
+    0) does not, which shows the state matters."""
+    P = _P()
+    from workloads.modes import init_params
+    prec = P.BF16X3 if prec_name == "bf16x3" else P.BF16
+    sizes = [40, 96, 64, 30]
+    rng = np.random.default_rng(21)
+    X = torch.from_numpy(rng.standard_normal((512, sizes[0])).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((512, sizes[-1])).astype(np.float32)).cuda()
+    p0 = torch.from_numpy(init_params(sizes, 3)).cuda()
+
+    def steps(mlp, k0, k1):
+        for k in range(k0, k1):
+            i0 = (k * 64) % 512
+            mlp.grad(X[i0:i0 + 64], T[i0:i0 + 64])
+            mlp.adam(1e-3 * (1.0 + 0.1 * k))
+
+    print(f"[gpu] mlp {prec_name}: 12 steps straight, and 5 + checkpoint + 7", flush=True)
+    a = P.MLP(sizes, max_batch=64, precision=prec)
+    a.set_params(p0)
+    steps(a, 0, 12)
+    b = P.MLP(sizes, max_batch=64, precision=prec)
+    b.set_params(p0)
+    steps(b, 0, 5)
+    params, (moments, step) = b.get_params().clone(), b.get_state()
+    assert step == 5
+    del b
+    c = P.MLP(sizes, max_batch=64, precision=prec)
+    c.set_params(params)
+    c.set_state(moments, step)
+    steps(c, 5, 12)
+    d = P.MLP(sizes, max_batch=64, precision=prec)
+    d.set_params(params)
+    steps(d, 5, 12)
+    torch.cuda.synchronize()
+    pa, pc, pd = a.get_params(), c.get_params(), d.get_params()
+    (ma, sa), (mc, sc) = a.get_state(), c.get_state()
+    torch.cuda.synchronize()
+    assert torch.equal(pa, pc) and torch.equal(ma, mc) and sa == sc == 12
+    assert not torch.equal(pa, pd)
+    xi = X[:37]
+    assert torch.equal(a.forward(xi), c.forward(xi))
+
+
 def test_errors_and_limits():
     P = _P()
     mlp = P.MLP([40, 64, 30], max_batch=64, precision=P.BF16)
