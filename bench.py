@@ -5,7 +5,12 @@
 A step is one pass of the whole path (forward model + binning/slopes) over
 the 1000-frame batch of the 160 px pupil / 512 px transform / 48-point
 modulation / 40 x 40 subaperture workload, with the synthetic von Karman
-inputs already resident in HBM.  Prints one JSON line.
+inputs already resident in HBM.  The step is captured once as a HIP graph;
+the timed region is K replays of it (events around each replay give the
+median), bracketed by device synchronisations.  Kernel durations for the
+roofline come from HIP events around every launch of K eager steps of the
+same batch, run right after.  Every form's error is measured against the
+FP64 oracle on the frames of the CPU baseline.  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -83,23 +88,26 @@ def mfma_flops(s, terms: int) -> dict:
     return {"stage1": g1, "stage2": g2}
 
 
-def time_form(P, torch, s, x, n_frames, steps, warmup, ref_I, ref_S, dev, stream, label, terms, dtype):
-    """frames/s of one precision form, its error against the FP32 path's
-    outputs (ref_I, ref_S) on the same frames, and its matrix-core roofline."""
+def time_form(P, torch, s, x, n_frames, steps, warmup, ref_I, ref_S, dev, stream, label, terms, dtype, refs=None):
+    """frames/s of one precision form (median of graph replays of the batch),
+    its error against the FP64 oracle on the oracle's frames (refs) and
+    against the FP32 path's outputs (ref_I, ref_S) on all frames, and its
+    matrix-core roofline (HIP events over eager steps)."""
     plan = P.Plan([s], max_frames=n_frames, device=dev, stream=stream)
     I = plan.new_intensity(n_frames)
     S = plan.new_slopes(n_frames)
     Fl = torch.zeros((n_frames, 1), dtype=torch.float32, device=dev)
+    import numpy as np
     for _ in range(warmup):
         plan.step(x, I, S, Fl, stream=stream)
     torch.cuda.synchronize(dev)
+    wall, ms = graph_replays(torch, dev, lambda st: plan.step(x, I, S, Fl, stream=st), steps)
+    med = float(np.median(ms)) / 1e3
     plan.profile(4096)
     torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
     for _ in range(steps):
         plan.step(x, I, S, Fl, stream=stream)
     torch.cuda.synchronize(dev)
-    dt = time.perf_counter() - t0
     g2_ms, g2_n = plan.profile_read("mfma")
     g1_ms, g1_n = plan.profile_read("rows")
     plan.profile(0)
@@ -119,7 +127,11 @@ def time_form(P, torch, s, x, n_frames, steps, warmup, ref_I, ref_S, dev, stream
     frames = n_frames * steps
     ach = fl["stage2"] * frames / (g2_ms / 1e3) / 1e12 if g2_ms > 0 else None
     peak = MFMA_PEAK_TFLOPS[dtype]
-    out = {"value": round(frames / dt, 2), "unit": "frames/s", "ms_per_step": round(dt / steps * 1e3, 4),
+    ev = oracle_errors(torch, I, S, s, refs) if refs is not None else None
+    out = {"value": round(n_frames / med, 2), "unit": "frames/s", "median_step_ms": round(med * 1e3, 4),
+           "mean_step_ms": round(wall / steps * 1e3, 4), "replays": steps,
+           "errors_vs_oracle": ev,
+           "at_stated_error": (ev["slope_rel_rms"] <= 1e-3) if ev else None,
            "intensity_rel_err_max_vs_fp32": ie, "slope_rel_rms_vs_fp32": se,
            "roofline": {"kernel": "k_mfma_cols (stage 2: e_k = Qy_k T, |e|^2 accumulate)", "bound": "mfma",
                         "achieved": round(ach, 2) if ach else None, "peak": peak, "unit": "TFLOP/s",
@@ -127,8 +139,8 @@ def time_form(P, torch, s, x, n_frames, steps, warmup, ref_I, ref_S, dev, stream
                         "avg_launch_ms": round(g2_ms / max(1, g2_n), 4), "flops_per_frame": fl["stage2"]},
            "stage1_ms_per_step": round(g1_ms / steps, 3), "stage2_ms_per_step": round(g2_ms / steps, 3)}
     plan.close()
-    print(f"# {label}: {out['value']:.0f} frames/s, intensity err {ie:.2e}, slope err {se:.2e}",
-          file=sys.stderr, flush=True)
+    print(f"# {label}: {out['value']:.0f} frames/s, vs fp32: intensity {ie:.2e}, slopes {se:.2e}; vs oracle: "
+          f"{ev}", file=sys.stderr, flush=True)
     return out
 
 
@@ -495,28 +507,206 @@ def measured_traffic(kernel: str, frames_per_launch: float):
     return rec["hbm_bytes_per_frame"] * frames_per_launch
 
 
-def _oracle_frame(args):
+_ORACLE = {}
+
+
+def _oracle_init(s, ref):
+    _ORACLE["s"], _ORACLE["ref"] = s, ref
+
+
+def _oracle_frame(opd):
+    """One frame through the oracle: (the four pupil images [4][D][D], slopes
+    [2][n][n], flux), float64."""
     import numpy as np
     from oracle import pwfs as O
-    opd, s = args
+    s = _ORACLE["s"]
     I = O.forward(opd[None], s)
-    O.slopes(I, s)
-    return 0
+    sl, fl = O.slopes(I, s, ref=_ORACLE["ref"])
+    D = s.n_pupil
+    win = np.stack([I[0, r:r + D, c:c + D] for r, c in O.image_origins(s)])
+    return win, sl[0], float(fl[0])
 
 
-def cpu_baseline(s, opd, n_frames: int, cores: int) -> dict:
-    """The FP64 oracle on the host cores, frames split over a process pool."""
+def cpu_baseline(s, opd, n_frames: int, cores: int):
+    """The FP64 oracle on the host cores, frames split over a process pool;
+    the reference slopes (a flat wavefront through the same oracle) are
+    computed once, as a plan does.  Returns the baseline record and the
+    oracle's results on those frames (the reference of every form's error)."""
     import multiprocessing as mp
+    import numpy as np
+    from oracle import pwfs as O
+    ref = O.reference_slopes(s)
     ctx = mp.get_context("spawn")
-    sample = [(opd[i], s) for i in range(n_frames)]
-    with ctx.Pool(cores) as pool:
-        pool.map(_oracle_frame, sample[:cores])          # warm the workers
+    with ctx.Pool(cores, initializer=_oracle_init, initargs=(s, ref)) as pool:
+        pool.map(_oracle_frame, [opd[i] for i in range(min(cores, n_frames))])   # warm the workers
         t0 = time.perf_counter()
-        pool.map(_oracle_frame, sample, chunksize=1)
+        res = pool.map(_oracle_frame, [opd[i] for i in range(n_frames)], chunksize=1)
         dt = time.perf_counter() - t0
-    return {"value": n_frames / dt, "unit": "frames/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_frames} of the 1000 frames, forward+slopes in complex128 numpy, "
-                      f"{cores} worker processes, {dt:.1f} s wall"}
+    refs = {"windows": np.stack([r[0] for r in res]), "slopes": np.stack([r[1] for r in res]),
+            "flux": np.array([r[2] for r in res]), "valid": O.valid_subapertures(s)}
+    rec = {"value": n_frames / dt, "unit": "frames/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n_frames} of the {opd.shape[0]} frames, forward+slopes in complex128 numpy "
+                     f"(reference slopes computed once), {cores} worker processes, {dt:.1f} s wall"}
+    return rec, refs
+
+
+def oracle_errors(torch, I, S, s, refs) -> dict:
+    """Errors of a form's outputs (device intensity [F][N][N], slopes
+    [F][2][n][n]) against the oracle on the oracle's frames: per-frame
+    normwise intensity (worst frame), every pixel against (|I_ref| + frame
+    mean) (worst), pooled slope RMS, every valid subaperture against
+    (|s_ref| + frame RMS) (worst)."""
+    import numpy as np
+    from oracle import pwfs as O
+    F = refs["windows"].shape[0]
+    D = s.n_pupil
+    Ih = I[:F].cpu().numpy()
+    a = np.stack([Ih[:, r:r + D, c:c + D] for r, c in O.image_origins(s)], axis=1).reshape(F, -1).astype(np.float64)
+    b = refs["windows"].reshape(F, -1)
+    v = refs["valid"]
+    sa = S[:F].cpu().numpy().astype(np.float64)[:, :, v].reshape(F, -1)
+    sb = refs["slopes"][:, :, v].reshape(F, -1)
+    rms = np.sqrt((sb ** 2).mean(axis=1, keepdims=True))
+    return {"frames": F,
+            "intensity_normwise_max": float((np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)).max()),
+            "intensity_pixel_max": float((np.abs(a - b) / (np.abs(b) + np.abs(b).mean(axis=1, keepdims=True))).max()),
+            "slope_rel_rms": float(np.linalg.norm(sa - sb) / np.linalg.norm(sb)),
+            "slope_subap_max": float((np.abs(sa - sb) / (np.abs(sb) + rms)).max())}
+
+
+def graph_replays(torch, dev, fn, reps: int):
+    """Captures fn(stream) once as a HIP graph and replays it `reps` times,
+    with events around each replay on the replay stream.  Returns (wall
+    seconds over all replays between two device synchronisations, per-replay
+    ms from the events)."""
+    side = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(side):
+        fn(side)                      # warm on the capture stream
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        fn(side)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    with torch.cuda.stream(side):
+        g.replay()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(side):
+        for a, b in ev:
+            a.record(side)
+            g.replay()
+            b.record(side)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    ms = [a.elapsed_time(b) for a, b in ev]
+    del g
+    return wall, ms
+
+
+def host_info(torch, dev) -> dict:
+    """Hardware and software the numbers were taken on."""
+    cpu = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    rocm = None
+    for path in ("/opt/rocm/.info/version", "/opt/rocm/.info/version-dev"):
+        try:
+            with open(path) as f:
+                rocm = f.read().strip()
+                break
+        except OSError:
+            pass
+    props = torch.cuda.get_device_properties(dev)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": cpu, "cpu_logical": os.cpu_count(), "cpu_available": avail,
+            "gpu": torch.cuda.get_device_name(dev), "gpu_arch": getattr(props, "gcnArchName", None),
+            "compute_units": props.multi_processor_count, "rocm": rocm, "hip_runtime": torch.version.hip,
+            "torch": torch.__version__}
+
+
+def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
+    """The 64 px sensor (N=128, 16 points, 16 x 16, 100 frames): the plain
+    FP32 path and its precision forms (bf16 x3, fp16 x3, bf16) on the same
+    shapes and inputs.  frames/s from the median of graph replays of the
+    100-frame batch, errors against the oracle on all 100 frames, kernel
+    durations from HIP events over eager steps."""
+    import numpy as np
+    from oracle import pwfs as O
+    from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16X3, workload, workload_opd
+    w = workload("cfg1")
+    s = w.sensors[0]
+    F = w.n_frames
+    opd = workload_opd(w)
+    t0 = time.perf_counter()
+    I_ref = O.forward(opd, s)
+    s_ref, f_ref = O.slopes(I_ref, s)
+    D = s.n_pupil
+    refs = {"windows": np.stack([I_ref[:, r:r + D, c:c + D] for r, c in O.image_origins(s)], axis=1),
+            "slopes": s_ref, "flux": f_ref, "valid": O.valid_subapertures(s)}
+    t_oracle = time.perf_counter() - t0
+    x = torch.from_numpy(opd).to(dev)
+    out = {"workload": w.name, "frames_per_batch": F, "oracle_seconds_single_process": round(t_oracle, 2)}
+    for label, prec in (("fp32", 0), ("mfma_bf16x3", PREC_BF16X3), ("mfma_fp16x3", PREC_FP16X3),
+                        ("mfma_bf16", PREC_BF16)):
+        sp = s.with_(precision=prec)
+        plan = P.Plan([sp], max_frames=F, device=dev, stream=stream)
+        I = plan.new_intensity(F)
+        S = plan.new_slopes(F)
+        Fl = torch.zeros((F, 1), dtype=torch.float32, device=dev)
+        wall, ms = graph_replays(torch, dev, lambda st: plan.step(x, I, S, Fl, stream=st), reps)
+        med = float(np.median(ms))
+        err = oracle_errors(torch, I, S, sp, refs)
+        # kernel durations over eager steps
+        plan.profile(4096)
+        for _ in range(reps):
+            plan.step(x, I, S, Fl, stream=stream)
+        torch.cuda.synchronize(dev)
+        kern = {k: plan.profile_read(k) for k in ("field", "rows", "cols", "mfma", "slopes")}
+        plan.profile(0)
+        rec = {"value": round(F / (med / 1e3), 1), "unit": "frames/s", "median_batch_ms": round(med, 4),
+               "replays": reps, "mean_batch_ms": round(wall / reps * 1e3, 4), "errors_vs_oracle": err,
+               "kernel_ms_per_batch": {k: round(v[0] / reps, 4) for k, v in kern.items() if v[1]}}
+        if prec == 0:
+            fl = nominal_flops(sp)
+            cms, cn = kern["cols"]
+            fpl = F * reps / max(1, cn)
+            ach = fl["cols"] * fpl / (cms / max(1, cn) / 1e3) / 1e12 if cms > 0 else None
+            rec["roofline"] = {"kernel": "k_cols (column pass)", "bound": "alu", "achieved": round(ach, 2),
+                               "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
+                               "flops_per_frame": fl["cols"], "frames_per_launch": fpl,
+                               "avg_launch_ms": round(cms / max(1, cn), 4), "traffic": None}
+            gpu_ms = sum(v[0] for v in kern.values()) / reps
+            rec["roofline_path"] = {"achieved": round(fl["path"] * F / (gpu_ms / 1e3) / 1e12, 2),
+                                    "frac": round(fl["path"] * F / (gpu_ms / 1e3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+                                    "flops_per_frame": fl["path"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
+        else:
+            terms = 1 if prec == PREC_BF16 else 3
+            fl = mfma_flops(sp, terms)
+            g2, n2 = kern["mfma"]
+            fpl = F * reps / max(1, n2)
+            ach = fl["stage2"] * fpl / (g2 / max(1, n2) / 1e3) / 1e12 if g2 > 0 else None
+            rec["roofline"] = {"kernel": "k_mfma_cols (stage 2)", "bound": "mfma",
+                               "achieved": round(ach, 2) if ach else None, "peak": MFMA_PEAK_TFLOPS["bf16"],
+                               "unit": "TFLOP/s", "frac": round(ach / MFMA_PEAK_TFLOPS["bf16"], 4) if ach else None,
+                               "flops_per_frame": fl["stage2"], "traffic": None}
+            rec["at_stated_error"] = err["slope_rel_rms"] <= 1e-3
+        out[label] = rec
+        plan.close()
+        print(f"# 64 px {label}: {rec['value']:.0f} frames/s (median of {reps} replays of {F} frames), "
+              f"slope err vs oracle {err['slope_rel_rms']:.2e}", file=sys.stderr, flush=True)
+    base = out["fp32"]["value"]
+    for label in ("mfma_bf16x3", "mfma_fp16x3", "mfma_bf16"):
+        out[label]["vs_fp32_plain"] = round(out[label]["value"] / base, 3)
+    return out
 
 
 def main() -> int:
@@ -528,6 +718,7 @@ def main() -> int:
     ap.add_argument("--cpu-frames", type=int, default=192,
                     help="frames of the oracle CPU baseline (about 10 s on 16 host processes)")
     ap.add_argument("--no-forms", action="store_true", help="time only the plain FP32 path")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64 px sensor and its precision forms")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate form")
     ap.add_argument("--no-detector", action="store_true", help="skip the path with the detector stage")
     ap.add_argument("--no-loop", action="store_true", help="skip the closed AO loop")
@@ -557,10 +748,10 @@ def main() -> int:
     print(f"# inputs: {w.n_frames} frames generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
           flush=True)
 
-    cpu = None
+    cpu, refs = None, None
     if not args.no_cpu:
         cores = max(1, min(16, os.cpu_count() or 1))
-        cpu = cpu_baseline(s, opd, args.cpu_frames, cores)
+        cpu, refs = cpu_baseline(s, opd, args.cpu_frames, cores)
         print(f"# cpu baseline: {cpu['value']:.2f} frames/s on {cores} processes", file=sys.stderr, flush=True)
 
     import torch
@@ -578,16 +769,22 @@ def main() -> int:
     for _ in range(args.warmup):
         plan.step(x, I, S, Fl, stream=stream)
     torch.cuda.synchronize(dev)
-    # per-kernel HIP events on the launch stream over the timed region
+    # the timed region: K replays of the step captured as a HIP graph
+    dt, replay_ms = graph_replays(torch, dev, lambda st: plan.step(x, I, S, Fl, stream=st), args.steps)
+    median_ms = float(np.median(replay_ms))
+    # kernel durations: HIP events around every launch of K eager steps, on the launch stream
     plan.profile(4096)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan.step(x, I, S, Fl, stream=stream)
     torch.cuda.synchronize(dev)
-    dt = time.perf_counter() - t0
+    eager_dt = time.perf_counter() - t0
     kern = {k: plan.profile_read(k) for k in ("field", "rows", "cols", "slopes")}
     plan.profile(0)
+    fp32_err = oracle_errors(torch, I, S, s, refs) if refs is not None else None
+    if fp32_err:
+        print(f"# fp32 vs oracle: {fp32_err}", file=sys.stderr, flush=True)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -599,26 +796,13 @@ def main() -> int:
 
     # per-timestep latency: one frame's forward + slopes captured in a HIP graph
     lat_plan = P.Plan([s], max_frames=1, device=dev, stream=stream)
-    side = torch.cuda.Stream(device=dev)
     x1 = x[:1]
     I1 = lat_plan.new_intensity(1)
     S1 = lat_plan.new_slopes(1)
     F1 = torch.zeros((1, 1), dtype=torch.float32, device=dev)
-    with torch.cuda.stream(side):
-        lat_plan.step(x1, I1, S1, F1, stream=side)
-    side.synchronize()
-    S_eager = S1.clone()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph, stream=side):
-        lat_plan.step(x1, I1, S1, F1, stream=side)
-    graph.replay()
-    torch.cuda.synchronize(dev)
-    graph_ok = bool(torch.equal(S1, S_eager)) and bool(torch.equal(S1, S[:1]))
-    t0 = time.perf_counter()
-    for _ in range(200):
-        graph.replay()
-    torch.cuda.synchronize(dev)
-    graph_ms = (time.perf_counter() - t0) / 200 * 1e3
+    lat_wall, lat_ms = graph_replays(torch, dev, lambda st: lat_plan.step(x1, I1, S1, F1, stream=st), 200)
+    graph_ok = bool(torch.equal(S1, S[:1]))
+    graph_ms = float(np.median(lat_ms))
 
     forms = {}
     if not args.no_forms:
@@ -626,8 +810,10 @@ def main() -> int:
         for label, prec, terms, dt_name in (("mfma_bf16x3", PREC_BF16X3, 3, "bf16"),
                                             ("mfma_fp16x3", PREC_FP16X3, 3, "fp16"),
                                             ("mfma_bf16", PREC_BF16, 1, "bf16")):
-            forms[label] = time_form(P, torch, s.with_(precision=prec), x, w.n_frames, max(2, args.steps // 2),
-                                     1, I, S, dev, stream, label, terms, dt_name)
+            forms[label] = time_form(P, torch, s.with_(precision=prec), x, w.n_frames, max(20, args.steps // 2),
+                                     1, I, S, dev, stream, label, terms, dt_name, refs)
+    if not args.no_small:
+        forms["pwfs64"] = small_sensor_forms(P, torch, dev, stream, max(20, args.steps))
     if not args.no_detector:
         forms["detector"] = detector_form(P, torch, dev, stream, x, plan, I, s, max(2, args.steps // 2))
     if not args.no_surrogate:
@@ -648,6 +834,7 @@ def main() -> int:
     frames = w.n_frames * args.steps
     value = frames / dt
     flops = nominal_flops(s)
+    host = host_info(torch, dev)
     cols_ms, cols_n = kern["cols"]
     frames_per_launch = w.n_frames * args.steps / max(1, cols_n)
     achieved = flops["cols"] * frames_per_launch / (cols_ms / max(1, cols_n) / 1e3) / 1e12
@@ -660,11 +847,18 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "median_step_ms": round(median_ms, 4),
+        "timing": f"{args.steps} replays of the 1000-frame step captured as one HIP graph, between two device "
+                  f"synchronisations (value); median of per-replay events {median_ms:.3f} ms; kernel durations "
+                  f"from HIP events around every launch of {args.steps} eager steps "
+                  f"({eager_dt / args.steps * 1e3:.3f} ms per step)",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic von Karman screens (r0 0.12 m, L0 40 m) + 5 mas tip/tilt jitter, seeds 2/12",
+        "errors_vs_oracle": fp32_err,
+        "host": host,
         "config": {"workload": w.name, "frames_per_step": w.n_frames, "n_pupil": s.n_pupil, "n_fft": s.n_fft,
                    "n_mod": s.n_mod, "n_subap": s.n_subap, "obstruction": s.obstruction,
                    "lambda_nm": s.lambdas_nm[0], "precision": "fp32", "intensity": "pupil-image windows"},
@@ -691,7 +885,7 @@ def main() -> int:
         },
         "graph_timestep": {"ms": round(graph_ms, 4), "frames_per_s": round(1e3 / graph_ms, 1),
                            "replay_matches_batched": graph_ok,
-                           "what": "one frame (forward + slopes) per HIP graph replay"},
+                           "what": "one frame (forward + slopes) per HIP graph replay, median of 200"},
         "forms": forms,
         "cpu_baseline": cpu,
     }
