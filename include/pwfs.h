@@ -20,8 +20,10 @@
  *    a thread-local message for the last failure.  No C++ exception crosses
  *    this boundary.
  *  - Device pointers are HIP device addresses owned by the caller; the
- *    library never allocates or frees device memory.  Streams are hipStream_t
- *    passed as void* (NULL = the null stream).
+ *    library never allocates or frees device memory (the one device array it
+ *    holds, the static scratch of pwfs_gemm_noalloc, is part of its code
+ *    object).  Streams are hipStream_t passed as void* (NULL = the null
+ *    stream).
  *  - pwfs_forward / pwfs_slopes only enqueue kernels on the given stream:
  *    they neither allocate nor synchronise, so they may be captured into a
  *    HIP graph.  Argument checks are synchronous; launch errors are read with
@@ -412,6 +414,25 @@ int pwfs_gemm_workspace_size(int M, int N, int K, int precision, size_t* bytes);
  */
 int pwfs_gemm(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc, int M, int N,
               int K, float alpha, float beta, int precision, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * pwfs_gemm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same product, kernels and bits as pwfs_gemm, with the 16-bit operand
+ * planes in a static device array of PWFS_GEMM_NOALLOC_MAX_BYTES that the
+ * library holds on every GPU it runs on until the process ends, instead of
+ * a caller workspace.  Sizes whose pwfs_gemm_workspace_size exceeds that
+ * return PWFS_EWORKSPACE.  The array of the GPU current at the call is used
+ * (hip_stream must belong to it); its address is looked up on the first
+ * call on each device.  The call allocates and frees nothing.  Every call on
+ * one GPU shares that GPU's array (each call writes all the plane bytes it
+ * reads, so nothing needs clearing): calls that can overlap on one GPU
+ * (different streams, or host threads enqueueing concurrently) race and must
+ * be serialised by the caller.  Asynchronous on hip_stream.
+ */
+#define PWFS_GEMM_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int pwfs_gemm_noalloc(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc, int M,
+                      int N, int K, float alpha, float beta, int precision, void* hip_stream);
 
 /* out[r] = sqrt(mean_c x[r][c]^2) for r < rows (float32 device arrays). */
 int pwfs_row_rms(const float* x, long long ld, int rows, int cols, float* out, void* hip_stream);

@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -305,20 +306,20 @@ extern "C" int pwfs_gemm_workspace_size(int M, int N, int K, int precision, size
   return PWFS_OK;
 }
 
-extern "C" int pwfs_gemm(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc,
-                         int M, int N, int K, float alpha, float beta, int precision, void* ws, size_t ws_bytes,
-                         void* stream) {
-  size_t need = 0;
-  int rc = pwfs_gemm_workspace_size(M, N, K, precision, &need);
-  if (rc) return rc;
-  if (!A || !B || !C) return mfail(PWFS_EINVAL, "NULL device pointer");
-  if (lda < K || ldb < K || ldc < N) return mfail(PWFS_EINVAL, "leading dimension too small");
-  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return mfail(PWFS_EWORKSPACE, "workspace");
-  hipStream_t st = (hipStream_t)stream;
+namespace pwfs {
+namespace {
+
+// C = alpha A B^T + beta C with the operand planes in `ws` (>= the
+// pwfs_gemm_workspace_size bytes, 256-byte aligned; checked by the callers).
+// k_split writes every element of both planes, K padding included, so the
+// workspace needs no clearing.
+int gemm_run(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc, int M, int N,
+             int K, float alpha, float beta, int precision, void* ws, hipStream_t st) {
   const int Kp = up32(K), pl = planes_of(precision);
   uint16_t* a16 = (uint16_t*)ws;
   uint16_t* b16 = (uint16_t*)((char*)ws + a256(2 * pl * (size_t)M * Kp));
   const long long ap = (long long)M * Kp, bp = (long long)N * Kp;
+  int rc;
   if ((rc = split_launch(A, lda, M, K, Kp, a16, ap, Kp, pl, 0, 1.f, st))) return rc;
   if ((rc = split_launch(B, ldb, N, K, Kp, b16, bp, Kp, pl, 0, 1.f, st))) return rc;
   GemmArgs g{};
@@ -336,6 +337,73 @@ extern "C" int pwfs_gemm(const float* A, long long lda, const float* B, long lon
   g.c = C;
   g.ldc = ldc;
   return gemm_dispatch<E_STORE>(pl, g, st);
+}
+
+int gemm_args_check(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc, int M,
+                    int N, int K, int precision, size_t* need) {
+  int rc = pwfs_gemm_workspace_size(M, N, K, precision, need);
+  if (rc) return rc;
+  if (!A || !B || !C) return mfail(PWFS_EINVAL, "NULL device pointer");
+  if (lda < K || ldb < K || ldc < N) return mfail(PWFS_EINVAL, "leading dimension too small");
+  return PWFS_OK;
+}
+
+// ------------------------------------------- static scratch of the GEMM ----
+// pwfs_gemm_noalloc keeps its operand planes in this file-scope device array
+// instead of a caller workspace.  Every GPU the library runs on holds its own
+// copy for the life of the process.  In host code the array's name is only a
+// stand-in: its device address is looked up once per device with
+// hipGetSymbolAddress (with that device current) and only that address is
+// passed to kernels.
+constexpr size_t kGemmScratchBytes = PWFS_GEMM_NOALLOC_MAX_BYTES;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kGemmScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return mfail(PWFS_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return mfail(PWFS_EUNSUPPORTED, "device index %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return mfail(PWFS_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    if (!p || ((uintptr_t)p & 255)) return mfail(PWFS_EHIP, "static scratch has no aligned device address");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return PWFS_OK;
+}
+
+}  // namespace
+}  // namespace pwfs
+
+extern "C" int pwfs_gemm(const float* A, long long lda, const float* B, long long ldb, float* C, long long ldc,
+                         int M, int N, int K, float alpha, float beta, int precision, void* ws, size_t ws_bytes,
+                         void* stream) {
+  size_t need = 0;
+  int rc = gemm_args_check(A, lda, B, ldb, C, ldc, M, N, K, precision, &need);
+  if (rc) return rc;
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return mfail(PWFS_EWORKSPACE, "workspace");
+  return gemm_run(A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, precision, ws, (hipStream_t)stream);
+}
+
+extern "C" int pwfs_gemm_noalloc(const float* A, long long lda, const float* B, long long ldb, float* C,
+                                 long long ldc, int M, int N, int K, float alpha, float beta, int precision,
+                                 void* stream) {
+  size_t need = 0;
+  int rc = gemm_args_check(A, lda, B, ldb, C, ldc, M, N, K, precision, &need);
+  if (rc) return rc;
+  if (need > kGemmScratchBytes)
+    return mfail(PWFS_EWORKSPACE, "operand planes need %zu bytes; the static scratch holds %zu", need,
+                 kGemmScratchBytes);
+  void* ws = nullptr;
+  if ((rc = scratch_of_current_device(&ws))) return rc;
+  return gemm_run(A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, precision, ws, (hipStream_t)stream);
 }
 
 extern "C" int pwfs_row_rms(const float* x, long long ld, int rows, int cols, float* out, void* stream) {

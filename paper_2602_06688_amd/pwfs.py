@@ -156,6 +156,7 @@ def lib() -> ctypes.CDLL:
     L.pwfs_gemm_workspace_size.argtypes = [i32, i32, i32, i32, P(ctypes.c_size_t)]
     L.pwfs_gemm.argtypes = [vp, ll, vp, ll, vp, ll, i32, i32, i32, ctypes.c_float, ctypes.c_float, i32, vp,
                             ctypes.c_size_t, vp]
+    L.pwfs_gemm_noalloc.argtypes = [vp, ll, vp, ll, vp, ll, i32, i32, i32, ctypes.c_float, ctypes.c_float, i32, vp]
     L.pwfs_row_rms.argtypes = [vp, ll, i32, i32, vp, vp]
     L.pwfs_mlp_workspace_size.argtypes = [i32, P(ctypes.c_int32), i32, i32, P(ctypes.c_size_t)]
     L.pwfs_mlp_create.argtypes = [i32, P(ctypes.c_int32), i32, i32, vp, ctypes.c_size_t, vp, P(vp)]
@@ -171,7 +172,7 @@ def lib() -> ctypes.CDLL:
     L.pwfs_mlp_destroy.restype = None
     for name in ("pwfs_validate", "pwfs_workspace_size", "pwfs_plan", "pwfs_forward", "pwfs_slopes",
                  "pwfs_query", "pwfs_device_status", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
-                 "pwfs_gemm_workspace_size", "pwfs_gemm", "pwfs_row_rms", "pwfs_mlp_workspace_size",
+                 "pwfs_gemm_workspace_size", "pwfs_gemm", "pwfs_gemm_noalloc", "pwfs_row_rms", "pwfs_mlp_workspace_size",
                  "pwfs_mlp_create", "pwfs_mlp_param_count", "pwfs_mlp_set_params", "pwfs_mlp_get_params",
                  "pwfs_mlp_get_state", "pwfs_mlp_set_state",
                  "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam", "pwfs_ccd", "pwfs_ccd_slopes", "pwfs_layers", "pwfs_integrator", "pwfs_gemv", "pwfs_sh_validate",
@@ -422,25 +423,49 @@ def _aligned_workspace(nbytes: int, device):
     return buf, ptr
 
 
-def gemm(A, B, out=None, alpha: float = 1.0, beta: float = 0.0, precision: int = BF16X3, stream=None):
-    """out [M, N] = alpha * A [M, K] @ B [N, K]^T + beta * out on the matrix
-    cores (with beta == 0 the old contents of ``out`` are not read)."""
+def _gemm_operands(A, B, out, beta):
     import torch
-    M, K = A.shape
-    N, K2 = B.shape
+    M, K = (int(v) for v in A.shape)
+    N, K2 = (int(v) for v in B.shape)
     if K2 != K:
         raise ValueError("inner dimensions differ")
     if out is None:
         if beta != 0.0:
             raise ValueError("beta != 0 needs an output to accumulate into")
         out = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    if tuple(out.shape) != (M, N):
+        raise ValueError(f"out must have shape {(M, N)}, has {tuple(out.shape)}")
+    for name, t in (("A", A), ("B", B), ("out", out)):
+        if t.dtype != torch.float32 or not t.is_cuda or t.stride(1) != 1:
+            raise ValueError(f"{name} must be a row-major float32 device matrix")
+    return M, N, K, out
+
+
+def gemm(A, B, out=None, alpha: float = 1.0, beta: float = 0.0, precision: int = BF16X3, stream=None):
+    """out [M, N] = alpha * A [M, K] @ B [N, K]^T + beta * out on the matrix
+    cores (with beta == 0 the old contents of ``out`` are not read)."""
+    import torch
+    M, N, K, out = _gemm_operands(A, B, out, beta)
     n = ctypes.c_size_t()
     check(lib().pwfs_gemm_workspace_size(M, N, K, precision, ctypes.byref(n)))
     ws, ptr = _aligned_workspace(n.value, A.device)
-    check(lib().pwfs_gemm(_dev_ptr(A, "A", torch.float32), A.stride(0), _dev_ptr(B, "B", torch.float32),
-                          B.stride(0), _dev_ptr(out, "out", torch.float32), out.stride(0), M, N, K,
-                          float(alpha), float(beta), precision, ctypes.c_void_p(ptr), n.value,
-                          _stream_ptr(stream)))
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    ws.record_stream(st)   # the kernels read it on `st` after this function returns
+    check(lib().pwfs_gemm(ctypes.c_void_p(A.data_ptr()), A.stride(0), ctypes.c_void_p(B.data_ptr()), B.stride(0),
+                          ctypes.c_void_p(out.data_ptr()), out.stride(0), M, N, K, float(alpha), float(beta),
+                          precision, ctypes.c_void_p(ptr), n.value, _stream_ptr(st)))
+    return out
+
+
+def gemm_noalloc(A, B, out, alpha: float = 1.0, beta: float = 0.0, precision: int = BF16X3, stream=None):
+    """``gemm`` into a caller-provided ``out`` with the operand planes in the
+    library's static device scratch (pwfs_gemm_noalloc): nothing is allocated,
+    so it can run where allocation is not allowed.  Calls that can overlap on
+    one GPU share that scratch and must be serialised by the caller."""
+    M, N, K, out = _gemm_operands(A, B, out, beta)
+    check(lib().pwfs_gemm_noalloc(ctypes.c_void_p(A.data_ptr()), A.stride(0), ctypes.c_void_p(B.data_ptr()),
+                                  B.stride(0), ctypes.c_void_p(out.data_ptr()), out.stride(0), M, N, K,
+                                  float(alpha), float(beta), precision, _stream_ptr(stream)))
     return out
 
 

@@ -164,6 +164,11 @@ void run_dense() {
     EXPECT(pwfs_gemm(A.f(), K, B.f(), K, C.f(), N, M, N, K, 1.f, 0.f, prec, ws.p, bytes, nullptr) == PWFS_OK);
     EXPECT(pwfs_gemm(A.f(), K, B.f(), K, C.f(), N, M, N, K, 1.f, 0.f, prec, ws.p, bytes - 256, nullptr) ==
            PWFS_EWORKSPACE);
+    EXPECT(pwfs_gemm_noalloc(A.f(), K, B.f(), K, C.f(), N, M, N, K, 1.f, 1.f, prec, nullptr) == PWFS_OK);
+    EXPECT(pwfs_gemm_noalloc(A.f(), K, B.f(), K, C.f(), N - 1, M, N, K, 1.f, 1.f, prec, nullptr) == PWFS_EINVAL);
+    // planes of 65536 x 1024 operands exceed the static scratch (pointers not touched)
+    EXPECT(pwfs_gemm_noalloc(A.f(), 1024, B.f(), 1024, C.f(), 1 << 16, 1 << 16, 1 << 16, 1024, 1.f, 0.f, prec,
+                             nullptr) == PWFS_EWORKSPACE);
   }
   Buf x(sizeof(float) * 64 * 33), r(sizeof(float) * 64);
   EXPECT(pwfs_row_rms(x.f(), 33, 64, 33, r.f(), nullptr) == PWFS_OK);
