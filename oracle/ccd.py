@@ -101,11 +101,103 @@ def uniform(w) -> np.ndarray:
     return (np.asarray(w, np.uint64) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
 
 
+# ----------------------------------------------- elementary functions ---
+# log, sqrt and cos(2 pi u) of the samplers, evaluated with + - * / and
+# exact scalings by powers of two only, each operation rounded on its own,
+# so that an implementation doing the same operations in the same order
+# gets the same bits.  An accept/reject decision (the Gamma sampler's) then
+# no longer depends on which math library evaluates it.
+
+LN2 = 0.6931471805599453              # the float64 nearest ln 2
+TWO_PI = 6.283185307179586            # the float64 nearest 2 pi
+SQRT_HALF = 0.7071067811865476        # the float64 nearest sqrt(1/2)
+LOG_TERMS = 12                        # atanh series terms: |s| <= 0.1716, s^26 / 27 < 1e-21
+SQRT_NEWTON = 5                       # Newton steps after a linear first guess
+
+
+def log_basic(x: np.ndarray) -> np.ndarray:
+    """ln x for finite x > 0: x = m 2^e with m in [sqrt(1/2), sqrt 2), then
+    ln m = 2 atanh(s), s = (m - 1) / (m + 1), as s times a Horner polynomial
+    in s^2 of the series coefficients 1 / (2j + 1); ln x = e ln 2 + ln m."""
+    m, e = np.frexp(np.asarray(x, np.float64))      # m in [0.5, 1)
+    low = m < SQRT_HALF
+    m = np.where(low, m * 2.0, m)
+    e = np.where(low, e - 1, e).astype(np.float64)
+    s = (m - 1.0) / (m + 1.0)
+    s2 = s * s
+    p = np.full(s.shape, 1.0 / (2.0 * LOG_TERMS + 1.0))
+    for j in range(LOG_TERMS - 1, -1, -1):
+        t = p * s2
+        p = t + 1.0 / (2.0 * j + 1.0)
+    t = s * p
+    t = t * 2.0
+    return e * LN2 + t
+
+
+def sqrt_basic(y: np.ndarray) -> np.ndarray:
+    """sqrt y for finite y >= 0: y = m 2^e with e even and m in [0.5, 2),
+    first guess 0.41731 + 0.59016 m, SQRT_NEWTON Newton steps
+    g <- (g + m / g) / 2, then scaled by 2^(e/2)."""
+    y = np.asarray(y, np.float64)
+    m, e = np.frexp(y)                              # m in [0.5, 1)
+    odd = (e % 2) != 0
+    m = np.where(odd, m * 2.0, m)
+    e = np.where(odd, e - 1, e)
+    g = 0.41731 + 0.59016 * m
+    for _ in range(SQRT_NEWTON):
+        q = m / g
+        g = (g + q) * 0.5
+    r = np.ldexp(g, e // 2)
+    return np.where(y == 0.0, 0.0, r)
+
+
+def _fact(n: int) -> float:
+    """n! as a float64 product formed left to right (exact for n <= 18)."""
+    f = 1.0
+    for i in range(2, n + 1):
+        f = f * float(i)
+    return f
+
+
+def _cos_poly(x: np.ndarray) -> np.ndarray:
+    """cos x for |x| <= pi/4: sum over k <= 8 of (-1)^k x^(2k) / (2k)!,
+    Horner in x^2 from the highest term."""
+    x2 = x * x
+    c = np.full(x.shape, 1.0 / _fact(16))
+    for k in range(7, -1, -1):
+        t = c * x2
+        c = (1.0 if k % 2 == 0 else -1.0) / _fact(2 * k) + t
+    return c
+
+
+def _sin_poly(x: np.ndarray) -> np.ndarray:
+    """sin x for |x| <= pi/4: x times the sum over k <= 8 of
+    (-1)^k x^(2k) / (2k + 1)!, Horner in x^2 from the highest term."""
+    x2 = x * x
+    c = np.full(x.shape, 1.0 / _fact(17))
+    for k in range(7, -1, -1):
+        t = c * x2
+        c = (1.0 if k % 2 == 0 else -1.0) / _fact(2 * k + 1) + t
+    return c * x
+
+
+def cos_2pi_basic(u: np.ndarray) -> np.ndarray:
+    """cos(2 pi u) for u in [0, 1): w = |u - round(u)| in [0, 1/2] (exact),
+    then cos(2 pi w) on [0, 1/8], sin(2 pi (1/4 - w)) on (1/8, 3/8] and
+    -cos(2 pi (1/2 - w)) above (each reduced argument exact, at most 1/8)."""
+    u = np.asarray(u, np.float64)
+    w = np.where(u >= 0.5, 1.0 - u, u)
+    a = np.where(w <= 0.125, w, np.where(w <= 0.375, 0.25 - w, 0.5 - w))
+    x = a * TWO_PI
+    return np.where(w <= 0.125, _cos_poly(x), np.where(w <= 0.375, _sin_poly(x), -_cos_poly(x)))
+
+
 def box_muller(w0, w1) -> np.ndarray:
-    """Standard normal from two 64-bit words."""
+    """Standard normal from two 64-bit words: sqrt(-2 ln u1) cos(2 pi u2)
+    with the basic-operation functions above."""
     u1 = 1.0 - uniform(w0)              # (0, 1]
     u2 = uniform(w1)
-    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+    return sqrt_basic(-2.0 * log_basic(u1)) * cos_2pi_basic(u2)
 
 
 # -------------------------------------------------------------- samplers ---
@@ -170,7 +262,7 @@ def gamma_mt(n: np.ndarray, pix: np.ndarray, frame: int, key) -> np.ndarray:
     counter block i: words 0, 1 -> normal x, word 2 -> uniform u."""
     n = np.asarray(n, np.float64)
     d = n - 1.0 / 3.0
-    c = 1.0 / np.sqrt(9.0 * d)
+    c = 1.0 / sqrt_basic(9.0 * d)
     out = d.copy()
     live = np.ones(n.shape, bool)
     for i in range(GAMMA_TRIES):
@@ -184,7 +276,8 @@ def gamma_mt(n: np.ndarray, pix: np.ndarray, frame: int, key) -> np.ndarray:
         ok = v > 0.0
         v3 = np.where(ok, v * v * v, 1.0)
         with np.errstate(divide="ignore"):
-            acc = ok & (np.log(u) < 0.5 * x * x + d[idx] - d[idx] * v3 + d[idx] * np.log(v3))
+            lhs = np.where(u > 0.0, log_basic(np.where(u > 0.0, u, 1.0)), -np.inf)
+            acc = ok & (lhs < 0.5 * x * x + d[idx] - d[idx] * v3 + d[idx] * log_basic(v3))
         out[idx[acc]] = d[idx[acc]] * v3[acc]
         live[idx[acc]] = False
     return out

@@ -9,10 +9,13 @@
 // (Salmon, Moraes, Dror, Shaw, SC'11) keyed by (seed, 0) with counter
 // (pixel, frame, purpose, block): every draw is a pure function of where it
 // is used, so results do not depend on the launch shape or the chunking of
-// frames.  The Poisson integer is decided in float64 by CDF inversion built
-// from correctly rounded + - * / only (exp(-mu) by a fixed Taylor series and
-// repeated squaring; contraction off), so it is reproducible bit for bit by
-// any implementation doing the same operations in the same order.
+// frames.  Every float64 step of the samplers is a correctly rounded + - * /
+// or an exact power-of-two scaling (contraction off): exp(-mu) of the Poisson
+// inversion by a fixed Taylor series and repeated squaring, and the ln, sqrt
+// and cos of the normal and Gamma draws by the fixed series below.  So the
+// Poisson integers, the Gamma accept/reject decisions and the draws are
+// reproduced bit for bit by any implementation doing the same operations in
+// the same order, with no math library in between.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -60,10 +63,110 @@ __device__ __forceinline__ u64x4 philox(uint64_t c0, uint64_t c1, uint64_t c2, u
 
 __device__ __forceinline__ double uniform01(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
 
+// ---------------------------------------------- elementary functions ----
+// ln, sqrt and cos(2 pi u) of the samplers from + - * / and exact scalings
+// by powers of two only (contraction off), each step rounded on its own:
+// the Gamma sampler's accept/reject decision is then the same bits on any
+// implementation that does the same operations in the same order, whatever
+// its math library.
+constexpr double kLn2 = 0.6931471805599453;        // float64 nearest ln 2
+constexpr double kTwoPi = 6.283185307179586;       // float64 nearest 2 pi
+constexpr double kSqrtHalf = 0.7071067811865476;   // float64 nearest sqrt(1/2)
+constexpr int kLogTerms = 12;                      // atanh series: |s| <= 0.1716
+constexpr int kSqrtNewton = 5;
+
+// ln x, x finite > 0: x = m 2^e, m in [sqrt(1/2), sqrt 2), ln m = 2 atanh s,
+// s = (m - 1)/(m + 1), the series sum_j s^(2j+1)/(2j+1) by Horner in s^2
+__device__ double log_basic(double x) {
+#pragma clang fp contract(off)
+  int e;
+  double m = frexp(x, &e);   // [0.5, 1)
+  if (m < kSqrtHalf) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double s2 = s * s;
+  double p = 1.0 / (2.0 * kLogTerms + 1.0);
+  for (int j = kLogTerms - 1; j >= 0; --j) {
+    const double t = p * s2;
+    p = t + 1.0 / (2.0 * j + 1.0);
+  }
+  double t = s * p;
+  t = t * 2.0;
+  const double el = (double)e * kLn2;
+  return el + t;
+}
+
+// sqrt y, y finite >= 0: y = m 2^e, e even, m in [0.5, 2); first guess
+// 0.41731 + 0.59016 m, then Newton g <- (g + m/g) / 2, scaled by 2^(e/2)
+__device__ double sqrt_basic(double y) {
+#pragma clang fp contract(off)
+  if (y == 0.0) return 0.0;
+  int e;
+  double m = frexp(y, &e);
+  if (e & 1) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  double g = 0.59016 * m;
+  g = 0.41731 + g;
+  for (int i = 0; i < kSqrtNewton; ++i) {
+    const double q = m / g;
+    g = g + q;
+    g = g * 0.5;
+  }
+  return ldexp(g, e / 2);
+}
+
+// n! as a float64 product formed left to right
+__device__ double fact(int n) {
+#pragma clang fp contract(off)
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f = f * (double)i;
+  return f;
+}
+
+// cos x and sin x for |x| <= pi/4: Taylor terms through x^16/16! and
+// x^17/17!, Horner in x^2 from the highest term
+__device__ double cos_poly(double x) {
+#pragma clang fp contract(off)
+  const double x2 = x * x;
+  double c = 1.0 / fact(16);
+  for (int k = 7; k >= 0; --k) {
+    const double t = c * x2;
+    c = ((k & 1) ? -1.0 : 1.0) / fact(2 * k) + t;
+  }
+  return c;
+}
+__device__ double sin_poly(double x) {
+#pragma clang fp contract(off)
+  const double x2 = x * x;
+  double c = 1.0 / fact(17);
+  for (int k = 7; k >= 0; --k) {
+    const double t = c * x2;
+    c = ((k & 1) ? -1.0 : 1.0) / fact(2 * k + 1) + t;
+  }
+  return c * x;
+}
+
+// cos(2 pi u), u in [0, 1): w = min(u, 1 - u) in [0, 1/2] (exact), then one
+// of cos(2 pi w), sin(2 pi (1/4 - w)), -cos(2 pi (1/2 - w)) on an exact
+// reduced argument of at most 1/8
+__device__ double cos_2pi_basic(double u) {
+#pragma clang fp contract(off)
+  const double w = u >= 0.5 ? 1.0 - u : u;
+  if (w <= 0.125) return cos_poly(w * kTwoPi);
+  if (w <= 0.375) return sin_poly((0.25 - w) * kTwoPi);
+  return -cos_poly((0.5 - w) * kTwoPi);
+}
+
 __device__ double box_muller(uint64_t w0, uint64_t w1) {
+#pragma clang fp contract(off)
   const double u1 = 1.0 - uniform01(w0);   // (0, 1]
   const double u2 = uniform01(w1);
-  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2);
+  const double r = sqrt_basic(-2.0 * log_basic(u1));
+  return r * cos_2pi_basic(u2);
 }
 
 // exp(-mu), 0 <= mu <= 256: 24-term Taylor series at mu / 256, eight squarings
@@ -113,7 +216,7 @@ __device__ long long poisson(double lam, uint64_t pix, uint64_t frame, uint64_t 
 __device__ double gamma_mt(double n, uint64_t pix, uint64_t frame, uint64_t k0, uint64_t k1) {
 #pragma clang fp contract(off)
   const double d = n - 1.0 / 3.0;
-  const double c = 1.0 / sqrt(9.0 * d);
+  const double c = 1.0 / sqrt_basic(9.0 * d);
   for (int i = 0; i < kGammaTries; ++i) {
     const u64x4 w = philox(pix, frame, kExcessPurpose, (uint64_t)i, k0, k1);
     const double x = box_muller(w.w[0], w.w[1]);
@@ -121,11 +224,12 @@ __device__ double gamma_mt(double n, uint64_t pix, uint64_t frame, uint64_t k0, 
     double v = 1.0 + c * x;
     if (!(v > 0.0)) continue;
     v = v * v * v;
-    const double lhs = log(u);
-    double rhs = 0.5 * x * x;
+    const double lhs = u > 0.0 ? log_basic(u) : -__builtin_inf();
+    double rhs = 0.5 * x;
+    rhs = rhs * x;
     rhs = rhs + d;
     rhs = rhs - d * v;
-    rhs = rhs + d * log(v);
+    rhs = rhs + d * log_basic(v);
     if (lhs < rhs) return d * v;
   }
   return d;

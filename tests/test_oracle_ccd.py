@@ -141,3 +141,24 @@ def test_poisson_bounds():
     pix = np.arange(4, dtype=np.uint64)
     k = C.poisson(np.array([-1.0, 0.0, np.inf, 2.0 ** 24 + 1]), pix, 0, (1, 0))
     assert k[0] == 0 and k[1] == 0 and np.isnan(k[2]) and np.isnan(k[3])
+
+
+def test_basic_operation_elementary_functions():
+    """The samplers' log, sqrt and cos(2 pi u), built from + - * / and exact
+    power-of-two scalings only, agree with the math library to a few ulp over
+    their whole ranges of use (u in (0, 1], Gamma shapes up to 2^24, v^3 of
+    the Marsaglia-Tsang step, normals' radius)."""
+    x = np.concatenate([np.geomspace(1e-300, 1e300, 20001), np.linspace(0.01, 4.0, 100001),
+                        1.0 - np.geomspace(2.0 ** -53, 0.5, 1001)])
+    ref = np.log(x)
+    big = np.abs(ref) > 1e-3
+    assert (np.abs(C.log_basic(x) - ref)[big] / np.abs(ref[big])).max() < 1e-15
+    assert np.abs(C.log_basic(x) - ref)[~big].max() < 1e-18
+    assert C.log_basic(np.array([1.0]))[0] == 0.0
+    y = np.concatenate([[0.0], np.geomspace(1e-300, 1e300, 20001), np.linspace(0.0, 100.0, 100001)])
+    r = np.sqrt(y)
+    assert (np.abs(C.sqrt_basic(y) - r) / np.maximum(r, 1e-300)).max() < 5e-16
+    assert C.sqrt_basic(np.array([4.0, 0.0]))[0] == 2.0
+    u = np.linspace(0.0, 1.0, 1_000_001, endpoint=False)
+    assert np.abs(C.cos_2pi_basic(u) - np.cos(2.0 * np.pi * u)).max() < 1e-15
+    assert C.cos_2pi_basic(np.array([0.0]))[0] == 1.0 and C.cos_2pi_basic(np.array([0.5]))[0] == -1.0
