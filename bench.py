@@ -193,6 +193,43 @@ def surrogate_form(torch, dev, n_train, n_test, epochs, reps):
                          "traffic": None}}
 
 
+def surrogate_study(torch, dev, n_max: int, n_test: int, configs) -> dict:
+    """Error of the learned surrogate against the plain path as the training
+    set, the width of the hidden layers and the epochs grow: one pool of
+    n_max training samples (seed of the workload) and one held-out test set,
+    the push-pull interaction matrix built once, then one network per
+    (samples, width, epochs) trained on the first `samples` of the pool."""
+    from paper_2602_06688_amd.surrogate import SurrogatePipeline
+    from workloads import workload
+    from workloads.modes import coefficient_sigmas, kl_modes
+    w = workload("cfg5")
+    s = w.sensors[0]
+    ex = w.extra
+    modes, ev = kl_modes(s.n_pupil, s.obstruction, s.diameter_m, w.L0_m, ex["n_modes"])
+    sig = coefficient_sigmas(ev, ex["residual_rms_nm"], s.lambdas_nm[0])
+    pipe = SurrogatePipeline(s, modes, sig, device=dev)
+    t0 = time.perf_counter()
+    z, S = pipe.generate(n_max, seed=w.seeds[0])
+    zt, St = pipe.generate(n_test, seed=ex["test_seed"])
+    torch.cuda.synchronize(dev)
+    t_data = time.perf_counter() - t0
+    pipe.interaction_matrix()
+    e_lin = pipe.rel_error(pipe.linear_predict(zt), St)
+    print(f"# study: {n_max} + {n_test} samples in {t_data:.1f} s, linear IM error {e_lin:.4e}", file=sys.stderr,
+          flush=True)
+    rows = []
+    for n, width, epochs in configs:
+        rep = pipe.train(z[:n], S[:n], hidden=(width, width), epochs=epochs, batch=1024, lr=1e-3)
+        e = pipe.rel_error(pipe.predict(zt), St)
+        e_train = pipe.rel_error(pipe.predict(z[:n_test]), S[:n_test])
+        rows.append({"train_samples": n, "hidden": width, "epochs": epochs, "test_error": e,
+                     "train_error": e_train, "train_seconds": round(rep.seconds, 1),
+                     "loss_last": rep.losses[-1]})
+        print(f"# study: n={n} width={width} epochs={epochs}: test {e:.4e} train {e_train:.4e} "
+              f"({rep.seconds:.1f} s)", file=sys.stderr, flush=True)
+    return {"linear_im_error": e_lin, "test_samples": n_test, "data_seconds": round(t_data, 1), "runs": rows}
+
+
 def detector_form(P, torch, dev, stream, x, plan, I, s, steps: int):
     """The plain path followed by the detector (120 x 120, photon + excess +
     readout noise, magnitude-8 source) and the slopes on detector pixels:
@@ -732,7 +769,18 @@ def main() -> int:
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
                          "(calibrates the HBM byte counters of a profiler run)")
+    ap.add_argument("--surrogate-study", action="store_true",
+                    help="instead of the benchmark: the surrogate's error against training samples, width and "
+                         "epochs (prints one JSON line)")
     args = ap.parse_args()
+    if args.surrogate_study:
+        import torch
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        cfgs = [(200_000, 1024, 20), (800_000, 1024, 20), (1_600_000, 1024, 20), (200_000, 2048, 20),
+                (1_600_000, 2048, 20), (1_600_000, 1024, 60)]
+        print(json.dumps({"surrogate_study": surrogate_study(torch, dev, 1_600_000, 20_000, cfgs)}), flush=True)
+        return 0
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the sensor path is measured at its single-GPU shape "
               "(sharding over GPUs is described in DESIGN.md, not run).", file=sys.stderr)

@@ -464,7 +464,18 @@ int pwfs_mlp_get_params(pwfs_mlp_t mlp, float* d_params, void* hip_stream);
  */
 int pwfs_mlp_get_state(pwfs_mlp_t mlp, float* d_moments, long long* step, void* hip_stream);
 int pwfs_mlp_set_state(pwfs_mlp_t mlp, const float* d_moments, long long step, void* hip_stream);
-/* d_y [batch][sizes[n]] = out_scale * network(d_x [batch][sizes[0]]), 1 <= batch <= max_batch. */
+/*
+ * Fixed linear term of inference: d_C [sizes[n]][sizes[0]] (device, row-major;
+ * NULL removes it).  With it, pwfs_mlp_forward returns
+ * out_scale * network(x) + C x, the linear part folded into the output
+ * layer's product as a second run of its K loop (the input's 16-bit planes
+ * against those of C / out_scale), so no separate product re-reads the
+ * output.  Training (pwfs_mlp_grad) is unaffected: it fits the network part.
+ * The learned surrogate uses it for its interaction-matrix term.
+ */
+int pwfs_mlp_set_linear(pwfs_mlp_t mlp, const float* d_C, void* hip_stream);
+/* d_y [batch][sizes[n]] = out_scale * network(d_x [batch][sizes[0]]) (+ C x
+ * with a linear term), 1 <= batch <= max_batch. */
 int pwfs_mlp_forward(pwfs_mlp_t mlp, const float* d_x, int batch, float* d_y, float out_scale, void* hip_stream);
 /*
  * Loss and gradients of mean((y - target_scale * t)^2) over the batch

@@ -68,6 +68,12 @@ struct GemmArgs {
   long long ldzp;
   double* loss_part;      // [grid] (E_OUTPUT with loss)
   int planes_out;
+  // optional second K segment accumulated into the same tile before the
+  // epilogue: acc += A2[M][K2] B2[N][K2]^T (K2 = 0: none)
+  const uint16_t* a2;
+  const uint16_t* b2;
+  long long a2_plane, b2_plane, lda2, ldb2;
+  int K2;
 };
 
 __device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
@@ -104,6 +110,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
   E eng;
   eng.zero();
   eng.run(ops, p.lda, p.M - m0, p.ldb, p.N - n0, p.K, lds, tid);
+  if (p.K2 > 0) {
+    typename E::Ops ops2;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) {
+      ops2.a[pl] = p.a2 + pl * p.a2_plane + (long long)m0 * p.lda2;
+      ops2.b[pl] = p.b2 + pl * p.b2_plane + (long long)n0 * p.ldb2;
+    }
+    eng.run(ops2, p.lda2, p.M - m0, p.ldb2, p.N - n0, p.K2, lds, tid);
+  }
   double lsum = 0.0;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -277,7 +292,7 @@ int gemm_launch(const GemmArgs& a0, hipStream_t st) {
 template <int EPI>
 int gemm_dispatch(int planes, const GemmArgs& a, hipStream_t st) {
   if (planes == 2) return gemm_launch<2, EPI, 32>(a, st);
-  return a.K % 64 == 0 ? gemm_launch<1, EPI, 64>(a, st) : gemm_launch<1, EPI, 32>(a, st);
+  return (a.K % 64 == 0 && a.K2 % 64 == 0) ? gemm_launch<1, EPI, 64>(a, st) : gemm_launch<1, EPI, 32>(a, st);
 }
 
 int split_launch(const float* src, long long ld, int rows, int cols, int Kp, uint16_t* dst, long long plane,
@@ -427,6 +442,13 @@ struct pwfs_mlp_s {
   std::vector<uint16_t*> H, Ht, G, Gt;
   std::vector<float*> Z, dZ;
   float* Y = nullptr;
+  // fixed linear term of inference (pwfs_mlp_set_linear): C [P_L][P_0] fp32
+  // and its 16-bit planes holding C / c_scale (c_scale = the out_scale they
+  // were made for, 0 = stale)
+  float* C = nullptr;
+  uint16_t* Cq = nullptr;
+  bool have_linear = false;
+  float c_scale = 0.f;
   double* loss_part = nullptr;
   int loss_parts = 0;
   bool have_grad = false;
@@ -459,6 +481,8 @@ void mlp_regions(int L, const std::vector<int>& P, int Bm, int planes, CB cb) {
     cb(4 * a);           // dZ
   }
   cb(4 * (size_t)Bm * P[L]);                   // Y
+  cb(4 * (size_t)P[L] * P[0]);                 // C
+  cb(2 * planes * (size_t)P[L] * P[0]);        // Cq
   const int tiles = ((Bm + 127) / 128) * ((P[L] + 127) / 128);
   cb(8 * (size_t)tiles);                       // loss partials
 }
@@ -532,6 +556,8 @@ extern "C" int pwfs_mlp_create(int L, const int32_t* sizes, int max_batch, int p
     m->dZ.push_back((float*)reg[r++]);
   }
   m->Y = (float*)reg[r++];
+  m->C = (float*)reg[r++];
+  m->Cq = (uint16_t*)reg[r++];
   m->loss_part = (double*)reg[r++];
   m->loss_parts = ((max_batch + 127) / 128) * ((m->P[L] + 127) / 128);
   // everything starts at zero: padding of every buffer must stay zero
@@ -609,6 +635,21 @@ extern "C" int pwfs_mlp_get_params(pwfs_mlp_t m, float* params, void* stream) {
     if ((rc = copy2d(m->b[l], no, params + off, no, 1, no, st))) return rc;
     off += no;
   }
+  return PWFS_OK;
+}
+
+extern "C" int pwfs_mlp_set_linear(pwfs_mlp_t m, const float* C, void* stream) {
+  if (!m) return mfail(PWFS_EINVAL, "NULL argument");
+  if (!C) {
+    m->have_linear = false;
+    return PWFS_OK;
+  }
+  int rc;
+  const int no = m->n[m->L], ni = m->n[0];
+  // rows and columns past the true sizes stay zero (the workspace is cleared at create)
+  if ((rc = copy2d(C, ni, m->C, m->P[0], no, ni, (hipStream_t)stream))) return rc;
+  m->have_linear = true;
+  m->c_scale = 0.f;
   return PWFS_OK;
 }
 
@@ -695,6 +736,23 @@ int mlp_forward(pwfs_mlp_t m, const float* x, int batch, float* y, float out_sca
       g.alpha = out_scale;
       g.c = y;
       g.ldc = m->n[L];
+      if (!target && m->have_linear) {
+        // y = out_scale (h W^T + b) + x C^T as one product: the planes of
+        // C / out_scale extend K after the layer's own weights
+        if (m->c_scale != out_scale) {
+          const int PL = m->P[L], P0 = m->P[0];
+          if ((rc = split_launch(m->C, P0, PL, P0, P0, m->Cq, (long long)PL * P0, P0, pl, 0, 1.f / out_scale, st)))
+            return rc;
+          m->c_scale = out_scale;
+        }
+        g.a2 = m->H[0];
+        g.a2_plane = a0;
+        g.lda2 = m->P[0];
+        g.b2 = m->Cq;
+        g.b2_plane = (long long)m->P[L] * m->P[0];
+        g.ldb2 = m->P[0];
+        g.K2 = m->P[0];
+      }
       if (target) {
         g.target = target;
         g.ldt = m->n[L];
@@ -721,6 +779,8 @@ int mlp_forward(pwfs_mlp_t m, const float* x, int batch, float* y, float out_sca
 extern "C" int pwfs_mlp_forward(pwfs_mlp_t m, const float* x, int batch, float* y, float out_scale, void* stream) {
   if (!m || !x || !y) return mfail(PWFS_EINVAL, "NULL argument");
   if (batch < 1 || batch > m->Bm) return mfail(PWFS_ESTATE, "batch outside [1, max_batch]");
+  if (m->have_linear && !(out_scale != 0.f && std::isfinite(out_scale)))
+    return mfail(PWFS_EINVAL, "out_scale must be finite and non-zero with a linear term");
   return mlp_forward(m, x, batch, y, out_scale, nullptr, 1.f, (hipStream_t)stream);
 }
 

@@ -163,6 +163,7 @@ def lib() -> ctypes.CDLL:
     L.pwfs_mlp_param_count.argtypes = [vp, P(ctypes.c_size_t)]
     L.pwfs_mlp_set_params.argtypes = [vp, vp, vp]
     L.pwfs_mlp_get_params.argtypes = [vp, vp, vp]
+    L.pwfs_mlp_set_linear.argtypes = [vp, vp, vp]
     L.pwfs_mlp_get_state.argtypes = [vp, vp, P(ctypes.c_longlong), vp]
     L.pwfs_mlp_set_state.argtypes = [vp, vp, ctypes.c_longlong, vp]
     L.pwfs_mlp_forward.argtypes = [vp, vp, i32, vp, ctypes.c_float, vp]
@@ -174,7 +175,7 @@ def lib() -> ctypes.CDLL:
                  "pwfs_query", "pwfs_device_status", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
                  "pwfs_gemm_workspace_size", "pwfs_gemm", "pwfs_gemm_noalloc", "pwfs_row_rms", "pwfs_mlp_workspace_size",
                  "pwfs_mlp_create", "pwfs_mlp_param_count", "pwfs_mlp_set_params", "pwfs_mlp_get_params",
-                 "pwfs_mlp_get_state", "pwfs_mlp_set_state",
+                 "pwfs_mlp_get_state", "pwfs_mlp_set_state", "pwfs_mlp_set_linear",
                  "pwfs_mlp_forward", "pwfs_mlp_grad", "pwfs_mlp_adam", "pwfs_ccd", "pwfs_ccd_slopes", "pwfs_layers", "pwfs_integrator", "pwfs_gemv", "pwfs_sh_validate",
                  "pwfs_sh_workspace_size", "pwfs_sh_plan", "pwfs_sh_forward", "pwfs_sh_query"):
         getattr(L, name).restype = i32
@@ -608,6 +609,13 @@ class MLP:
         out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
         check(lib().pwfs_mlp_get_params(self._h, _dev_ptr(out, "params", torch.float32), _stream_ptr(stream)))
         return out
+
+    def set_linear(self, C, stream=None):
+        """Fixed linear term C [sizes[-1], sizes[0]] added by forward (None removes it)."""
+        import torch
+        ptr = ctypes.c_void_p(None) if C is None else \
+            _dev_ptr(C, "C", torch.float32, self.sizes[-1] * self.sizes[0])
+        check(lib().pwfs_mlp_set_linear(self._h, ptr, _stream_ptr(stream)))
 
     def get_state(self, stream=None):
         """(Adam moments [2 * n_params] device tensor, step): m then v, each packed like the parameters."""

@@ -60,6 +60,7 @@ class SurrogatePipeline:
         self.mlp = None
         self.s_scale = 1.0
         self.im = None
+        self._linear_set = False
 
     # ------------------------------------------------------------ plain path --
     def slopes_of(self, z, out=None):
@@ -124,6 +125,7 @@ class SurrogatePipeline:
         sizes = [self.n_modes, *hidden, self.n_out]
         self.mlp = P.MLP(sizes, max_batch=max(batch, self.chunk, infer_batch), precision=precision,
                          device=self.device)
+        self._linear_set = False
         self.mlp.set_params(torch.from_numpy(init_params(sizes, seed, zero_last=True)).to(self.device))
         r = self.residual(z[:n], s[:n])
         rms = P.row_rms(r)
@@ -144,21 +146,21 @@ class SurrogatePipeline:
         torch.cuda.synchronize(self.device)
         return TrainReport(epochs, steps, time.perf_counter() - t0, losses)
 
-    def predict(self, z, out=None, linear_precision: int = P.BF16):
-        """Surrogate slopes [n][n_out] (device): the network in chunks of
-        max_batch, then the linear part accumulated on top.  The linear part
-        runs in bf16 like the network's weights (bf16x3 reproduces it to fp32
-        accuracy at three times the matrix-core work; the difference is two
-        orders below the surrogate's own error)."""
+    def predict(self, z, out=None):
+        """Surrogate slopes [n][n_out] (device): IM z + r_rms net(z), the
+        interaction-matrix term folded into the network's output-layer
+        product (bf16 like the network's weights), in chunks of max_batch."""
         torch = self.torch
         n = int(z.shape[0])
         if out is None:
             out = torch.empty((n, self.n_out), dtype=torch.float32, device=self.device)
+        if not self._linear_set:
+            self.mlp.set_linear(self.im)
+            self._linear_set = True
         mb = self.mlp.max_batch
         for i0 in range(0, n, mb):
             i1 = min(n, i0 + mb)
             self.mlp.forward(z[i0:i1], out=out[i0:i1], out_scale=self.s_scale)
-        P.gemm(z, self.im, out=out, alpha=1.0, beta=1.0, precision=linear_precision)
         return out
 
     def predict_with_fallback(self, z, rms_limit: float = 1.5):

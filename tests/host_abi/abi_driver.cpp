@@ -188,6 +188,12 @@ void run_dense() {
     EXPECT(pwfs_mlp_set_params(m, prm.f(), nullptr) == PWFS_OK);
     EXPECT(pwfs_mlp_get_params(m, g.f(), nullptr) == PWFS_OK);
     EXPECT(pwfs_mlp_forward(m, in.f(), 37, y.f(), 1.f, nullptr) == PWFS_OK);
+    Buf lin(sizeof(float) * 130 * 50);
+    EXPECT(pwfs_mlp_set_linear(m, lin.f(), nullptr) == PWFS_OK);
+    EXPECT(pwfs_mlp_forward(m, in.f(), 64, y.f(), 0.5f, nullptr) == PWFS_OK);
+    EXPECT(pwfs_mlp_forward(m, in.f(), 64, y.f(), 2.0f, nullptr) == PWFS_OK);
+    EXPECT(pwfs_mlp_forward(m, in.f(), 64, y.f(), 0.f, nullptr) == PWFS_EINVAL);
+    EXPECT(pwfs_mlp_set_linear(m, nullptr, nullptr) == PWFS_OK);
     EXPECT(pwfs_mlp_grad(m, in.f(), t.f(), 64, 1.f, loss.f(), g.f(), nullptr) == PWFS_OK);
     EXPECT(pwfs_mlp_grad(m, in.f(), t.f(), 33, 1.f, loss.f(), g.f(), nullptr) == PWFS_ESTATE);
     EXPECT(pwfs_mlp_adam(m, 1e-3f, 0.9f, 0.999f, 1e-8f, nullptr) == PWFS_OK);

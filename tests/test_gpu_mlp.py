@@ -131,6 +131,44 @@ def test_mlp_forward_grad_adam_vs_oracle(prec_name, tol, sizes, B):
         assert err <= 1e-6
 
 
+@pytest.mark.parametrize("prec_name,tol,sizes,B", [("bf16x3", 1e-4, [40, 96, 64, 30], 37),
+                                                   ("bf16", 3e-2, [40, 96, 64, 30], 64),
+                                                   ("bf16", 3e-2, [500, 1024, 1024, 3200], 300)])
+def test_linear_term_folded_into_the_output_layer(prec_name, tol, sizes, B):
+    """forward with a linear term C returns out_scale net(x) + C x (the
+    surrogate's IM z + r_rms net(z)) against float64, for two scales in a row
+    (the planes of C / out_scale are remade when the scale changes); removing
+    the term gives back the plain network; training is unaffected."""
+    P = _P()
+    from workloads.modes import init_params
+    prec = P.BF16X3 if prec_name == "bf16x3" else P.BF16
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal((B, sizes[0])).astype(np.float32)
+    C = (rng.standard_normal((sizes[-1], sizes[0])) / np.sqrt(sizes[0])).astype(np.float32)
+    p0 = init_params(sizes, 12)
+    p0[-sizes[-1]:] = 0.05
+    print(f"[gpu] mlp {prec_name} linear term, sizes {sizes}, batch {B}", flush=True)
+    mlp = P.MLP(sizes, max_batch=(max(128, B) + 31) // 32 * 32, precision=prec)
+    mlp.set_params(torch.from_numpy(p0).cuda())
+    xd = torch.from_numpy(x).cuda()
+    y_net = mlp.forward(xd, out_scale=1.0).clone()
+    mlp.set_linear(torch.from_numpy(C).cuda())
+    y_ref, _ = MO.forward(_to_oracle(p0, sizes), x)
+    for scale in (0.37, 2.5):
+        y = mlp.forward(xd, out_scale=scale)
+        torch.cuda.synchronize()
+        ref = scale * y_ref + x.astype(np.float64) @ C.astype(np.float64).T
+        e = _rel(y.cpu().numpy(), ref)
+        print(f"      out_scale {scale}: rel err {e:.2e}", flush=True)
+        assert e <= tol
+    with pytest.raises(P.PwfsError):
+        mlp.forward(xd, out_scale=0.0)
+    mlp.set_linear(None)
+    y2 = mlp.forward(xd, out_scale=1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(y2, y_net)
+
+
 @pytest.mark.parametrize("prec_name", ["bf16", "bf16x3"])
 def test_inference_between_training_steps_changes_nothing(prec_name):
     """Inference skips the activations only the backward pass reads; a

@@ -31,9 +31,11 @@ def test_surrogate_beats_linear_interaction_matrix_and_falls_back():
     print(f"      linear IM {e_lin:.3e}, surrogate {e_nn:.3e}, losses {rep.losses[0]:.3e}->{rep.losses[-1]:.3e}",
           flush=True)
     assert rep.losses[-1] < rep.losses[0]
-    # the network must remove a real part of what the linear model misses
-    # (observed: 0.73 of the linear error at this size)
+    # the network must remove a real part of what the linear model misses:
+    # observed 6.16e-2 against 8.46e-2 for the linear model at this size
+    # (0.73 of it); the bound holds that figure with a small margin
     assert e_nn < 0.85 * e_lin
+    assert e_nn < 0.065
     # fallback: rows far outside the training distribution go to the plain sensor
     zz = zt[:64].clone()
     zz[::4] *= 3.0
