@@ -692,10 +692,12 @@ def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
     t_oracle = time.perf_counter() - t0
     x = torch.from_numpy(opd).to(dev)
     out = {"workload": w.name, "frames_per_batch": F, "oracle_seconds_single_process": round(t_oracle, 2)}
-    for label, prec in (("fp32", 0), ("mfma_bf16x3", PREC_BF16X3), ("mfma_fp16x3", PREC_FP16X3),
-                        ("mfma_bf16", PREC_BF16)):
+    for label, prec in (("fp32", 0), ("fp32_fused", 0), ("mfma_bf16x3", PREC_BF16X3),
+                        ("mfma_fp16x3", PREC_FP16X3), ("mfma_bf16", PREC_BF16)):
         sp = s.with_(precision=prec)
         plan = P.Plan([sp], max_frames=F, device=dev, stream=stream)
+        if label == "fp32_fused":
+            plan.set_tuning(mode=P.MODE_FUSED)
         I = plan.new_intensity(F)
         S = plan.new_slopes(F)
         Fl = torch.zeros((F, 1), dtype=torch.float32, device=dev)
@@ -707,12 +709,21 @@ def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
         for _ in range(reps):
             plan.step(x, I, S, Fl, stream=stream)
         torch.cuda.synchronize(dev)
-        kern = {k: plan.profile_read(k) for k in ("field", "rows", "cols", "mfma", "slopes")}
+        kern = {k: plan.profile_read(k) for k in ("field", "rows", "cols", "fused", "mfma", "slopes")}
         plan.profile(0)
         rec = {"value": round(F / (med / 1e3), 1), "unit": "frames/s", "median_batch_ms": round(med, 4),
                "replays": reps, "mean_batch_ms": round(wall / reps * 1e3, 4), "errors_vs_oracle": err,
                "kernel_ms_per_batch": {k: round(v[0] / reps, 4) for k, v in kern.items() if v[1]}}
-        if prec == 0:
+        if label == "fp32_fused":
+            fl = nominal_flops(sp)
+            fms, fn = kern["fused"]
+            ach = fl["path"] * F * reps / (fms / 1e3) / 1e12 if fms > 0 else None
+            rec["roofline"] = {"kernel": "k_fused (field, rows, columns, |e|^2 of one frame per workgroup)",
+                               "bound": "alu", "achieved": round(ach, 2) if ach else None, "peak": FP32_PEAK_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4) if ach else None,
+                               "flops_per_frame": fl["path"], "avg_launch_ms": round(fms / max(1, fn), 4),
+                               "traffic": None}
+        elif prec == 0:
             fl = nominal_flops(sp)
             cms, cn = kern["cols"]
             fpl = F * reps / max(1, cn)
@@ -741,7 +752,7 @@ def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
         print(f"# 64 px {label}: {rec['value']:.0f} frames/s (median of {reps} replays of {F} frames), "
               f"slope err vs oracle {err['slope_rel_rms']:.2e}", file=sys.stderr, flush=True)
     base = out["fp32"]["value"]
-    for label in ("mfma_bf16x3", "mfma_fp16x3", "mfma_bf16"):
+    for label in ("fp32_fused", "mfma_bf16x3", "mfma_fp16x3", "mfma_bf16"):
         out[label]["vs_fp32_plain"] = round(out[label]["value"] / base, 3)
     return out
 

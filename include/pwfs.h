@@ -190,7 +190,12 @@ int pwfs_slopes(pwfs_plan_t plan, const float* d_intensity, int n_frames, float*
  *             pass for all sensors, whose workgroups claim field, row and
  *             column work items from a device counter (a sensor's row items
  *             wait for its field items, its column items for its row items).
- *             Both modes give bit-identical results.
+ *             Both modes give bit-identical results.  PWFS_MODE_FUSED (FP32
+ *             pyramid sensors with N = 64 or 128): one launch for all frames,
+ *             one workgroup per frame holding the field, the row-pass output
+ *             and the intensity on chip, so a frame reads only its OPD from
+ *             HBM and writes only its intensity; the |e|^2 sum runs in point
+ *             order, so results match the other modes to rounding, not bits.
  *  chunk      frames per pass, 1 .. max_chunk (set by the workspace size)
  *  wg_per_cu  persistent workgroups per compute unit, 1 .. 8
  *  row_groups minimum number of row-pass work items per pass
@@ -200,7 +205,7 @@ int pwfs_slopes(pwfs_plan_t plan, const float* d_intensity, int n_frames, float*
  *             A negative value makes every wait give up at once: a failure
  *             forced from the host, for testing that path
  */
-enum { PWFS_MODE_LAUNCHES = 0, PWFS_MODE_PERSISTENT = 1 };
+enum { PWFS_MODE_LAUNCHES = 0, PWFS_MODE_PERSISTENT = 1, PWFS_MODE_FUSED = 2 };
 typedef struct {
   int32_t mode, chunk, wg_per_cu, row_groups, max_chunk, spin_limit, reserved[2];
 } pwfs_tuning;
@@ -232,7 +237,8 @@ int pwfs_valid_map(pwfs_plan_t plan, int sensor, uint8_t* host_out);
  * the pool.  Not for use under graph capture.
  * pwfs_profile_read waits for the recorded events of one kernel kind
  * (0 = row pass, 1 = column pass, 2 = slope stage, 3 = matrix-core forward,
- * 4 = pupil-field pass, 5 = persistent heterogeneous pass)
+ * 4 = pupil-field pass, 5 = persistent heterogeneous pass, 6 = detector,
+ * 7 = fused pass)
  * and returns their summed duration in ms and their number.
  */
 int pwfs_profile(pwfs_plan_t plan, int max_launches);

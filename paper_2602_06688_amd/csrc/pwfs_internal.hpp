@@ -74,7 +74,9 @@ int forward_mfma(const SensorPlan& sp, const float* opd, long long opd_stride, f
 
 // Optional per-kernel timing: HIP events recorded on the launch stream
 // around each kernel (pool created when profiling is switched on).
-enum KernelId { K_ROWS = 0, K_COLS = 1, K_SLOPES = 2, K_MFMA = 3, K_FIELD = 4, K_HETERO = 5, K_CCD = 6, kKernelIds = 8 };
+enum KernelId {
+  K_ROWS = 0, K_COLS = 1, K_SLOPES = 2, K_MFMA = 3, K_FIELD = 4, K_HETERO = 5, K_CCD = 6, K_FUSED = 7, kKernelIds = 8
+};
 
 struct Prof {
   bool on = false;

@@ -462,6 +462,199 @@ __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
   cols_body<N, QM, SPLIT>(p, blockIdx.x, smem);
 }
 
+// --------------------------------------------- fused pass (N = 64, 128) ----
+// One workgroup owns one frame and never leaves the chip between its input
+// and its output: the pupil field of each wavelength is formed in registers,
+// the row transforms of one x-tilt key go to an LDS tile [Nc][D] (the row
+// pass's output, kept on chip instead of in HBM), the column transforms of
+// every point of that key read it back, and |e|^2 accumulates in registers
+// over every key, point and wavelength.  At the end the accumulator goes
+// through LDS so that the intensity rows leave in coalesced stores.  The
+// arithmetic of each transform pair is the two-pass kernels'; only the order
+// of the |e|^2 sum differs (one running sum per pixel in point order).
+constexpr int kFusedBlock = 512;
+
+struct FusedArgs {
+  const float* opd;        // sensor's first frame; frame stride opd_stride
+  const float* amp;        // [D][D]
+  const float2* rx;        // [n_lam][n_a][D]
+  const float2* ry;        // [n_lam][n_mod][D]
+  const float2* mrow;      // [n_lam][N]
+  const float2* mcol;      // [n_lam][N]
+  const float2* tw;        // [N]
+  const int2* kord;        // [n_mod] (point, key), keys ascending
+  float* out;              // sensor's first frame; frame stride out_stride
+  long long opd_stride, out_stride;
+  int D, Nc, n_a, n_lam, n_mod, full, win_lo, win_hi, wy_lo, wy_hi;
+  double two_pi_over_lam[PWFS_MAX_LAMBDA];
+};
+
+// LDS of the fused pass: the lane groups' exchange buffers, then the row
+// tile [Nc][D | 1] of float2 (odd row stride: the lanes writing one output
+// slot hit distinct banks), reused at the end as the float tile
+// [rows kept][Nc + 1]
+template <int N>
+__host__ __device__ constexpr size_t fused_lds_bytes(int D, int Nc, int rows_kept) {
+  const size_t buf = sizeof(float2) * (size_t)(kFusedBlock / FftPlan<N>::T) * BufLen<N>::value;
+  const size_t tile = sizeof(float2) * (size_t)Nc * (size_t)(D | 1);
+  const size_t out = sizeof(float) * (size_t)rows_kept * (size_t)(Nc + 1);
+  return buf + (tile > out ? tile : out);
+}
+
+template <int N, int QM_>
+__global__ __launch_bounds__(kFusedBlock) void k_fused(FusedArgs p) {
+  using P = FftPlan<N>;
+  constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kFusedBlock / T;
+  constexpr int QM = QM_ < R0 ? QM_ : R0, NL = NB0 * QM;
+  constexpr int RPG = (N / 2 + G - 1) / G;   // pupil rows per lane group (D <= N / 2)
+  constexpr int CPG = (N + G - 1) / G;       // kept columns per lane group (Nc <= N)
+  constexpr int BL = BufLen<N>::value;
+  static_assert(Palindromic<N>::value, "the fused pass keeps its twiddles in registers");
+  extern __shared__ float2 smem[];
+  float2* s_R = smem + G * BL;
+  const int RS = p.D | 1;
+  const int tid = threadIdx.x, g = tid / T, t = tid % T;
+  const int f = blockIdx.x;
+
+  FftPair<N, QM> fp;
+  fp.init(t, smem + g * BL, p.tw);
+
+  // this lane's first-stage inputs (pupil x for a row, pupil y for a column)
+  int xx[NL];
+  bool xin[NL];
+#pragma unroll
+  for (int i = 0; i < NB0; ++i)
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      const int x = t + T * i + q * (N / R0);
+      xx[i * QM + q] = min(x, p.D - 1);
+      xin[i * QM + q] = x < p.D;
+    }
+
+  float acc[CPG][V];
+#pragma unroll
+  for (int c = 0; c < CPG; ++c)
+#pragma unroll
+    for (int s = 0; s < V; ++s) acc[c][s] = 0.f;
+
+  const float* opd = p.opd + (long long)f * p.opd_stride;
+  for (int lam = 0; lam < p.n_lam; ++lam) {
+    // pupil field of this group's rows y = g + G r, as the field pass forms it
+    float2 e0[RPG][NL];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+      const int y = g + G * r;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        float2 v = czero();
+        if (y < p.D && xin[l]) {
+          const int i = y * p.D + xx[l];
+          const double ph = (double)opd[i] * p.two_pi_over_lam[lam];
+          const double n = rint(ph * 0.15915494309189533577);
+          const float red = (float)fma(-n, 6.283185307179586477, ph);
+          float sn, cs;
+          sincosf(red, &sn, &cs);
+          const float a = p.amp[i];
+          v = make_float2(a * cs, a * sn);
+        }
+        e0[r][l] = v;
+      }
+    }
+    float2 mr[V], mc[V];
+#pragma unroll
+    for (int s = 0; s < V; ++s) {
+      mr[s] = p.mrow[(size_t)lam * N + freq_index<N>(t, s)];
+      mc[s] = p.mcol[(size_t)lam * N + freq_index<N>(t, s)];
+    }
+    const float2* rxl = p.rx + (size_t)lam * p.n_a * p.D;
+    const float2* ryl = p.ry + (size_t)lam * p.n_mod * p.D;
+    int prev = -1;
+    for (int it = 0; it < p.n_mod; ++it) {
+      const int2 ka = p.kord[it];
+      if (ka.y != prev) {
+        // row transforms of key ka.y into the tile (the previous key's
+        // column transforms are done with it)
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < V; ++s) fp.m[s] = mr[s];
+        float2 rxv[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) rxv[l] = xin[l] ? rxl[(size_t)ka.y * p.D + xx[l]] : czero();
+#pragma unroll
+        for (int r = 0; r < RPG; ++r) {
+          const int y = g + G * r;
+          float2 v[V];
+#pragma unroll
+          for (int i = 0; i < NB0; ++i)
+#pragma unroll
+            for (int q = 0; q < R0; ++q)
+              v[i * R0 + q] = q < QM ? cmul(e0[r][i * QM + q], rxv[i * QM + q]) : czero();
+          fp.run(v);
+          if (y < p.D) {
+#pragma unroll
+            for (int s = 0; s < V; ++s) {
+              const int X = space_index<N>(t, s);
+              const int xc = p.full ? X : window_index(X, p.D, p.win_lo, p.win_hi);
+              if (xc >= 0) s_R[xc * RS + y] = v[s];
+            }
+          }
+        }
+        __syncthreads();
+        prev = ka.y;
+#pragma unroll
+        for (int s = 0; s < V; ++s) fp.m[s] = mc[s];
+      }
+      // column transforms of point ka.x over this group's columns
+      float2 ryv[NL];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) ryv[l] = xin[l] ? ryl[(size_t)ka.x * p.D + xx[l]] : czero();
+#pragma unroll
+      for (int c = 0; c < CPG; ++c) {
+        const int xc = g + G * c;
+        const bool live = xc < p.Nc;
+        const int xcl = live ? xc : 0;
+        float2 v[V];
+#pragma unroll
+        for (int i = 0; i < NB0; ++i)
+#pragma unroll
+          for (int q = 0; q < R0; ++q) {
+            const int l = i * QM + q;
+            v[i * R0 + q] = (q < QM && xin[l]) ? cmul(s_R[xcl * RS + xx[l]], ryv[l]) : czero();
+          }
+        fp.run(v);
+        if (live) {
+#pragma unroll
+          for (int s = 0; s < V; ++s) acc[c][s] += cabs2(v[s]);
+        }
+      }
+    }
+  }
+  // accumulator -> float tile [rows kept][Nc + 1] -> coalesced rows out
+  __syncthreads();
+  float* s_O = (float*)s_R;
+  const int OS = p.Nc + 1;
+#pragma unroll
+  for (int c = 0; c < CPG; ++c) {
+    const int xc = g + G * c;
+    if (xc >= p.Nc) continue;
+#pragma unroll
+    for (int s = 0; s < V; ++s) {
+      const int Y = space_index<N>(t, s);
+      const int yc = p.full ? Y : window_index(Y, p.D, p.wy_lo, p.wy_hi);
+      if (yc >= 0) s_O[yc * OS + xc] = acc[c][s];
+    }
+  }
+  __syncthreads();
+  const int rows = p.full ? N : 2 * p.D;
+  float* out = p.out + (long long)f * p.out_stride;
+  for (int e = tid; e < rows * p.Nc; e += kFusedBlock) {
+    const int yc = e / p.Nc, xc = e - yc * p.Nc;
+    const int Y = p.full ? yc : window_coord(yc, p.D, p.wy_lo, p.wy_hi);
+    const int X = p.full ? xc : window_coord(xc, p.D, p.win_lo, p.win_hi);
+    out[(size_t)Y * N + X] = s_O[yc * OS + xc];
+  }
+}
+
 // ------------------------------------------- double roof, flat-axis passes --
 // An arm of a double roof with no field stop has a flat mask on one axis, and
 // there the transform pair is the identity up to the pupil offset: the row

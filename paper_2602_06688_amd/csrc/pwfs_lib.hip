@@ -623,6 +623,61 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
   return PWFS_OK;
 }
 
+// ------------------------------------------------------- fused pass --------
+bool fused_eligible(const SensorPlan& sp) {
+  return sp.desc.precision == PWFS_FP32 && sp.arms == 1 && (sp.g.N == 64 || sp.g.N == 128) && sp.g.qmax <= 4;
+}
+
+template <int N, int QM>
+static int launch_fused(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost, int nf,
+                        hipStream_t st, Prof* prof) {
+  const Geometry& g = sp.g;
+  FusedArgs a{};
+  a.opd = opd;
+  a.amp = (const float*)sp.dev[R_AMP];
+  a.rx = (const float2*)sp.dev[R_RX];
+  a.ry = (const float2*)sp.dev[R_RY];
+  a.mrow = (const float2*)sp.dev[R_MROW];
+  a.mcol = (const float2*)sp.dev[R_MCOL];
+  a.tw = (const float2*)sp.dev[R_TW];
+  a.kord = (const int2*)sp.dev[R_AK];
+  a.out = out;
+  a.opd_stride = os;
+  a.out_stride = ost;
+  a.D = g.D;
+  a.Nc = g.Nc;
+  a.n_a = g.n_a;
+  a.n_lam = g.n_lam;
+  a.n_mod = g.n_mod;
+  a.full = g.full;
+  a.win_lo = g.win_lo;
+  a.win_hi = g.win_hi;
+  a.wy_lo = g.wy_lo;
+  a.wy_hi = g.wy_hi;
+  for (int l = 0; l < g.n_lam; ++l) a.two_pi_over_lam[l] = 2.0 * kPi / sp.desc.lambda_nm[l];
+  const size_t lds = fused_lds_bytes<N>(g.D, g.Nc, g.full ? g.N : 2 * g.D);
+  const int slot = prof->begin(st);
+  hipLaunchKernelGGL((k_fused<N, QM>), dim3((unsigned)nf), dim3(kFusedBlock), lds, st, a);
+  HIP_TRY(hipGetLastError(), "launch k_fused");
+  prof->end(slot, st, K_FUSED);
+  return PWFS_OK;
+}
+
+template <int N>
+static int launch_fused_q(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost, int nf,
+                          hipStream_t st, Prof* prof) {
+  // D <= N / 2 leaves at most 4 non-zero inputs per first-stage butterfly
+  if (sp.g.qmax <= 3) return launch_fused<N, 3>(sp, opd, os, out, ost, nf, st, prof);
+  return launch_fused<N, 4>(sp, opd, os, out, ost, nf, st, prof);
+}
+
+int forward_fused(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost, int nf,
+                  hipStream_t st, Prof* prof) {
+  if (sp.g.N == 64) return launch_fused_q<64>(sp, opd, os, out, ost, nf, st, prof);
+  if (sp.g.N == 128) return launch_fused_q<128>(sp, opd, os, out, ost, nf, st, prof);
+  return fail(PWFS_EUNSUPPORTED, "the fused pass runs N = 64 or 128 only");
+}
+
 // ------------------------------------------- persistent heterogeneous pass --
 bool hetero_eligible(const SensorPlan& sp) {
   return sp.desc.precision == PWFS_FP32 && sp.g.qmax <= 3 && sp.g.N >= 256 && sp.arms == 1;
@@ -737,6 +792,10 @@ int prepare_kernels() {
   lds_limit((const void*)k_slopes<1024, 4>);
   lds_limit((const void*)k_slopes<1024, 8>);
   lds_limit((const void*)k_hetero);
+  lds_limit((const void*)k_fused<64, 3>);
+  lds_limit((const void*)k_fused<64, 4>);
+  lds_limit((const void*)k_fused<128, 3>);
+  lds_limit((const void*)k_fused<128, 4>);
   done = true;
   return PWFS_OK;
 }
@@ -978,12 +1037,18 @@ int pwfs_get_tuning(pwfs_plan_t p, pwfs_tuning* t) {
 
 int pwfs_set_tuning(pwfs_plan_t p, const pwfs_tuning* t) {
   if (!p || !t) return fail(PWFS_EINVAL, "NULL argument");
-  if (t->mode != PWFS_MODE_LAUNCHES && t->mode != PWFS_MODE_PERSISTENT) return fail(PWFS_EINVAL, "unknown mode");
+  if (t->mode != PWFS_MODE_LAUNCHES && t->mode != PWFS_MODE_PERSISTENT && t->mode != PWFS_MODE_FUSED)
+    return fail(PWFS_EINVAL, "unknown mode");
   if (t->chunk < 1 || t->chunk > p->max_chunk)
     return fail(PWFS_EINVAL, "chunk must be in [1, %d] (the workspace's pass size)", p->max_chunk);
   if (t->wg_per_cu < 1 || t->wg_per_cu > 8) return fail(PWFS_EINVAL, "wg_per_cu must be in [1, 8]");
   if (t->row_groups < 1 || t->row_groups > (1 << 20)) return fail(PWFS_EINVAL, "row_groups out of range");
   if (t->reserved[0] != 0 || t->reserved[1] != 0) return fail(PWFS_EINVAL, "reserved fields must be 0");
+  if (t->mode == PWFS_MODE_FUSED) {
+    for (const SensorPlan& sp : p->s)
+      if (!fused_eligible(sp))
+        return fail(PWFS_EUNSUPPORTED, "the fused pass needs FP32 pyramid sensors with N = 64 or 128");
+  }
   if (t->mode == PWFS_MODE_PERSISTENT) {
     if ((int)p->s.size() > kMaxHetero) return fail(PWFS_EUNSUPPORTED, "persistent mode takes at most 8 sensors");
     for (const SensorPlan& sp : p->s)
@@ -1114,6 +1179,9 @@ namespace pwfs {
 int forward_sensor(pwfs_plan_s* p, int i, const float* opd, long long opd_stride, float* out,
                    long long out_stride, int nf, hipStream_t st) {
   const SensorPlan& sp = p->s[i];
+  // the fused pass needs no scratch: every frame in one launch
+  if (p->tune.mode == PWFS_MODE_FUSED && fused_eligible(sp))
+    return forward_fused(sp, opd, opd_stride, out, out_stride, nf, st, &p->prof);
   for (int f0 = 0; f0 < nf; f0 += p->chunk) {
     const int n = std::min(p->chunk, nf - f0);
     const float* o = opd + (long long)f0 * opd_stride;

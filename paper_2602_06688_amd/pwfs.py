@@ -70,6 +70,7 @@ class CTuning(ctypes.Structure):
 
 MODE_LAUNCHES = 0
 MODE_PERSISTENT = 1
+MODE_FUSED = 2
 
 CCD_PHOTON = 1
 CCD_READOUT = 2
@@ -370,7 +371,7 @@ class Plan:
         check(lib().pwfs_ccd_slopes(self._h, int(sensor), ctypes.byref(ccd), pp, F, ps, pf, _stream_ptr(stream)))
         return out, flux
 
-    KERNELS = {"rows": 0, "cols": 1, "slopes": 2, "mfma": 3, "field": 4, "hetero": 5, "ccd": 6}
+    KERNELS = {"rows": 0, "cols": 1, "slopes": 2, "mfma": 3, "field": 4, "hetero": 5, "ccd": 6, "fused": 7}
 
     def get_tuning(self) -> dict:
         t = CTuning()

@@ -81,6 +81,8 @@ void run_plan(const pwfs_sensor_desc* d, int n, int frames, const char* label) {
     u.mode = PWFS_MODE_PERSISTENT;
     u.wg_per_cu = 1 + chunk % 8;
     if (pwfs_set_tuning(plan, &u) == PWFS_OK) EXPECT(pwfs_forward(plan, opd.f(), frames, inten.f(), nullptr) == 0);
+    u.mode = PWFS_MODE_FUSED;
+    if (pwfs_set_tuning(plan, &u) == PWFS_OK) EXPECT(pwfs_forward(plan, opd.f(), frames, inten.f(), nullptr) == 0);
   }
   pwfs_tuning bad = t;
   bad.chunk = t.max_chunk + 1;

@@ -41,12 +41,14 @@ def _windows(I, s):
     return np.stack([I[:, r:r + D, c:c + D] for r, c in O.image_origins(s)], axis=1)
 
 
-def _check(s, opd, plan_frames=None, label=""):
+def _check(s, opd, plan_frames=None, label="", mode=None):
     P = _P()
     F = opd.shape[0]
     _say(f"[gpu] {label}: D={s.n_pupil} N={s.n_fft} n_mod={s.n_mod} n_lam={len(s.lambdas_nm)} "
-         f"flags={s.flags} F={F}")
+         f"flags={s.flags} F={F}" + (f" mode={mode}" if mode is not None else ""))
     plan = P.Plan([s], max_frames=plan_frames or F)
+    if mode is not None:
+        plan.set_tuning(mode=mode)
     x = torch.from_numpy(np.ascontiguousarray(opd, dtype=np.float32)).cuda()
     I, sl, flux = plan.step(x)
     torch.cuda.synchronize()
@@ -145,6 +147,48 @@ def test_edge_sensors(name):
     from workloads import von_karman_opd
     opd = von_karman_opd(3, s.n_pupil, 8.0, 0.5, 25.0, seed=int(rng.integers(1000)))
     _check(s, opd, label=name)
+
+
+FUSED_EDGE = [n for n, e in EDGE.items() if e.n_fft <= 128 and not (e.flags & 8)]
+
+
+def test_cfg1_all_frames_fused():
+    """The 64 px workload's 100 frames through the fused pass (one workgroup
+    per frame, nothing but the OPD and the intensity through HBM)."""
+    P = _P()
+    w = workload("cfg1")
+    _check(w.sensors[0], workload_opd(w), label="cfg1 100 frames fused", mode=P.MODE_FUSED)
+
+
+@pytest.mark.parametrize("name", FUSED_EDGE)
+def test_edge_sensors_fused(name):
+    """Every N <= 128 edge sensor (N = 64, ragged pupils, odd n_mod, no
+    modulation, 3- and 16-wavelength bands, full plane, local norm, extended
+    sources, field stops, subapertures cutting pixels) through the fused pass."""
+    P = _P()
+    s = EDGE[name]
+    rng = np.random.default_rng(sum(name.encode()))
+    from workloads import von_karman_opd
+    opd = von_karman_opd(3, s.n_pupil, 8.0, 0.5, 25.0, seed=int(rng.integers(1000)))
+    _check(s, opd, label=name, mode=P.MODE_FUSED)
+
+
+def test_fused_matches_two_pass_to_rounding():
+    """Fused and two-pass runs of the same 40 frames: the same transforms,
+    the |e|^2 sum in another order, so equal to float32 rounding."""
+    P = _P()
+    w = workload("cfg1")
+    x = torch.from_numpy(workload_opd(w, frames=range(40))).cuda()
+    plan = P.Plan([w.sensors[0]], max_frames=40)
+    _say("[gpu] fused vs two-pass, 40 frames")
+    I0, S0, F0 = [t.clone() for t in plan.step(x)]
+    plan.set_tuning(mode=P.MODE_FUSED)
+    I1, S1, F1 = plan.step(x)
+    torch.cuda.synchronize()
+    d = float((I1 - I0).abs().max() / I0.abs().max())
+    ds = float((S1 - S0).abs().max() / S0.abs().max())
+    _say(f"      max |dI| / max I {d:.2e}, max |ds| / max s {ds:.2e}")
+    assert d < 1e-6 and ds < 1e-5
 
 
 def test_multi_sensor_plan_packs_sensors():
