@@ -722,7 +722,10 @@ def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
                                "bound": "alu", "achieved": round(ach, 2) if ach else None, "peak": FP32_PEAK_TFLOPS,
                                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4) if ach else None,
                                "flops_per_frame": fl["path"], "avg_launch_ms": round(fms / max(1, fn), 4),
-                               "traffic": None}
+                               "traffic": measured_traffic("k_fused", F),
+                               "traffic_unit": "bytes per 100-frame launch (HBM, copy-calibrated rocprofv3 "
+                                               "FETCH_SIZE/WRITE_SIZE)",
+                               "algorithmic_bytes": 4.0 * F * (sp.n_pupil ** 2 + 4 * sp.n_pupil ** 2)}
         elif prec == 0:
             fl = nominal_flops(sp)
             cms, cn = kern["cols"]
