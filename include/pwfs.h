@@ -215,6 +215,23 @@ int pwfs_get_tuning(pwfs_plan_t plan, pwfs_tuning* out);
 int pwfs_set_tuning(pwfs_plan_t plan, const pwfs_tuning* tuning);
 
 /*
+ * Row-pass tile of one FP32 sensor: rows of the field per row-pass
+ * workgroup.  Each N has a default and one alternative (N = 256, 512, 768:
+ * 8 and 16; N = 384: 16 and 8; N = 64 and 128 have one tile, 32 and 16).  A
+ * taller tile writes longer contiguous segments of the row-pass output (rows
+ * x 8 bytes per column) but holds more LDS, so fewer workgroups share a
+ * compute unit; the autotuner measures both.  Every tile gives bit-identical
+ * results, in both launch modes.  rows = 0 restores the default.
+ * PWFS_EINVAL for a sensor out of range, a tile not compiled for the
+ * sensor's N or one whose LDS would exceed 160 KiB; PWFS_EUNSUPPORTED for a
+ * sensor that is not on the FP32 path.  Takes effect at the next forward
+ * call; not to be called while a call on the plan is being enqueued.
+ */
+int pwfs_set_row_tile(pwfs_plan_t plan, int sensor, int rows);
+/* The tile sensor `sensor` runs with (its selection or the default). */
+int pwfs_get_row_tile(pwfs_plan_t plan, int sensor, int* rows);
+
+/*
  * Device-side status of the plan's work enqueued on hip_stream so far:
  * synchronises hip_stream, then returns PWFS_EHIP (message in
  * pwfs_last_error) if a persistent pass's dependency wait gave up since the

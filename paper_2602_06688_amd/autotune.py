@@ -1,11 +1,17 @@
-"""Autotuner of a plan's execution: searches the launch mode (per-sensor
-launches or one persistent launch for all sensors), frames per pass,
-persistent workgroups per CU and the row-pass split, timing whole forward
-passes with HIP events; the best setting is cached in a JSON file keyed by
-(GPU architecture, sensors, frames per call).
+"""Autotuner of a plan's execution, timing whole forward passes with HIP
+events.  Two stages:
 
-Candidates only change how the same arithmetic is scheduled, so every
-setting gives bit-identical results.
+1. schedule: the launch mode (per-sensor launches or one persistent launch
+   for all sensors), frames per pass, persistent workgroups per CU and the
+   row-pass split, every sensor at its default tile;
+2. tile shapes: for the best schedule of each mode, the row-pass tile (rows
+   of the field per workgroup) of each group of sensors with the same FFT
+   size, tried in turn and kept where it is faster (a greedy pass: the
+   groups are few and nearly independent).
+
+The winner is cached in a JSON file keyed by (GPU architecture, sensors,
+frames per call).  Candidates only change how the same arithmetic is
+scheduled and tiled, so every setting gives bit-identical results.
 """
 
 from __future__ import annotations
@@ -43,6 +49,44 @@ def candidates(plan) -> List[dict]:
             for w in (1, 2, 3):
                 out.append({"mode": P.MODE_PERSISTENT, "chunk": c, "wg_per_cu": w, "row_groups": 2048})
     return out
+
+
+ROW_TILES = (8, 16, 32)   # tried per FFT size; the library accepts the ones compiled for it
+
+
+def tile_groups(plan) -> Dict[int, List[int]]:
+    """Sensors grouped by FFT size (the row tiles compiled depend on it)."""
+    groups: Dict[int, List[int]] = {}
+    for i, s in enumerate(plan.sensors):
+        groups.setdefault(int(s.n_fft), []).append(i)
+    return groups
+
+
+def set_row_tiles(plan, tiles: List[int]) -> None:
+    """Applies one selection per sensor (0 = the sensor's default tile)."""
+    for i, r in enumerate(tiles):
+        plan.set_row_tile(i, r)
+
+
+def tile_options(plan, sensors: List[int], current: List[int]) -> List[int]:
+    """Row tiles other than the default that the library accepts for every
+    sensor of a group; the selection ``current`` is restored afterwards."""
+    set_row_tiles(plan, [0] * len(current))
+    default = plan.row_tile(sensors[0])
+    ok = []
+    for r in ROW_TILES:
+        if r == default:
+            continue
+        try:
+            for i in sensors:
+                plan.set_row_tile(i, r)
+            ok.append(r)
+        except P.PwfsError:
+            pass
+        finally:
+            set_row_tiles(plan, [0] * len(current))
+    set_row_tiles(plan, current)
+    return ok
 
 
 def measure(plan, run: Callable[[], None], reps: int = 3) -> float:
@@ -90,19 +134,47 @@ def autotune(plan, run: Callable[[], None], n_frames: int, arch: str = "gfx950",
     cache = load_cache(cache_path)
     if key in cache:
         plan.set_tuning(**{k: cache[key][k] for k in ("mode", "chunk", "wg_per_cu", "row_groups")})
+        if "row_tiles" in cache[key]:
+            set_row_tiles(plan, cache[key]["row_tiles"])
         return dict(cache[key], cached=True)
     timer = timer or (lambda: measure(plan, run, reps))
+    defaults = [0] * len(plan.sensors)
+    set_row_tiles(plan, defaults)
+    # stage 1: schedules at the default tiles
     results = []
     for c in (list(cands) if cands is not None else candidates(plan)):
         try:
             plan.set_tuning(**c)
         except P.PwfsError:
             continue
-        results.append((timer(), c))
+        results.append((timer(), c, defaults))
     results.sort(key=lambda r: r[0])
-    best_ms, best = results[0]
+    # stage 2: row tiles per FFT size, from the best schedule of each mode
+    tried_tiles = []
+    finals = []
+    for mode in sorted({c["mode"] for _, c, _ in results}):
+        ms, c, _ = next(r for r in results if r[1]["mode"] == mode)
+        plan.set_tuning(**c)
+        tiles = list(defaults)
+        set_row_tiles(plan, tiles)
+        for n_fft, group in sorted(tile_groups(plan).items()):
+            for r in tile_options(plan, group, tiles):
+                trial = list(tiles)
+                for i in group:
+                    trial[i] = r
+                set_row_tiles(plan, trial)
+                t = timer()
+                tried_tiles.append(dict(c, row_tiles=trial, ms=t))
+                if t < ms:
+                    ms, tiles = t, trial
+            set_row_tiles(plan, tiles)
+        finals.append((ms, c, tiles))
+    finals.sort(key=lambda r: r[0])
+    best_ms, best, best_tiles = finals[0]
     plan.set_tuning(**best)
-    rec = dict(best, ms=best_ms, tried=[dict(c, ms=ms) for ms, c in results])
+    set_row_tiles(plan, best_tiles)
+    rec = dict(best, row_tiles=best_tiles, ms=best_ms,
+               tried=[dict(c, row_tiles=tl, ms=ms) for ms, c, tl in results] + tried_tiles)
     cache[key] = rec
     save_cache(cache_path, cache)
     return dict(rec, cached=False)

@@ -39,6 +39,7 @@ struct SensorPlan {
   std::vector<uint8_t> valid_host;
   size_t opd_offset, int_offset, slope_offset;
   float2* rbuf = nullptr;   // this sensor's pass scratch
+  int row_tile = 0;         // row-pass tile rows (0: the default of its N)
 };
 
 struct Layout {

@@ -25,12 +25,16 @@
 namespace pwfs {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
+constexpr size_t kMaxLds = 160 * 1024;   // LDS a workgroup may hold on gfx950
 
-// rows of one row-pass workgroup tile
-template <int N> struct RowTile { static constexpr int RW = 8; };
-template <> struct RowTile<64> { static constexpr int RW = 32; };
-template <> struct RowTile<128> { static constexpr int RW = 16; };
-template <> struct RowTile<384> { static constexpr int RW = 16; };
+// Rows of one row-pass workgroup tile: the default RW and the alternative
+// ALT that a plan may select per sensor (pwfs_set_row_tile).  A taller tile
+// writes longer contiguous segments of the row-pass output (RW x 8 bytes per
+// column) but holds more LDS, so fewer workgroups fit on a compute unit.
+template <int N> struct RowTile { static constexpr int RW = 8, ALT = 16; };
+template <> struct RowTile<64> { static constexpr int RW = 32, ALT = 32; };
+template <> struct RowTile<128> { static constexpr int RW = 16, ALT = 16; };
+template <> struct RowTile<384> { static constexpr int RW = 16, ALT = 8; };
 
 // Slot of element (column xc, row yl) in the row pass's transpose tile
 // [Nc][RW].  Rows are unpadded; the row index is XOR-swizzled by bits of xc
@@ -161,12 +165,12 @@ __device__ __forceinline__ void field_body(const FieldArgs& p, int bid) {
 __global__ __launch_bounds__(kBlock) void k_field(FieldArgs p) { field_body(p, blockIdx.x); }
 
 // ---------------------------------------------------------------- rows ----
-template <int N, int QM_>
-__device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* smem) {
+template <int N, int QM_, int RW>
+__device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* smem, int tid) {
   using P = FftPlan<N>;
   constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
   constexpr int QM = QM_ < R0 ? QM_ : R0;
-  constexpr int RW = RowTile<N>::RW, RPG = RW / G, BL = BufLen<N>::value, NL = NB0 * QM;
+  constexpr int RPG = RW / G, BL = BufLen<N>::value, NL = NB0 * QM;
   static_assert(RPG >= 1 && RW % G == 0, "row tile");
 
   // palindromic plans take twiddles straight into registers; the others keep
@@ -177,7 +181,7 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
   float2* s_buf = s_tw + (PAL ? 0 : N);
   float2* s_tile = s_buf + G * BL;
 
-  const int tid = threadIdx.x, g = tid / T, t = tid % T;
+  const int g = tid / T, t = tid % T;
   const int agi = bid % p.n_agroups;
   bid /= p.n_agroups;
   const int rb = bid % p.rowblocks;
@@ -299,10 +303,10 @@ __device__ __forceinline__ void rows_body(const RowArgs& p, int bid, float2* sme
   }
 }
 
-template <int N, int QM>
+template <int N, int QM, int RW>
 __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
   extern __shared__ float2 smem[];
-  rows_body<N, QM>(p, blockIdx.x, smem);
+  rows_body<N, QM, RW>(p, blockIdx.x, smem, threadIdx.x);
 }
 
 // ------------------------------------------------------------- columns ----
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs p) {
 __device__ __forceinline__ int kgroup_lo(int g, int n_mod, int G) { return g * n_mod / G; }
 
 template <int N, int QM_, bool SPLIT>
-__device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* smem) {
+__device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* smem, int tid) {
   using P = FftPlan<N>;
   constexpr int T = P::T, V = N / T, R0 = P::r[0], NB0 = V / R0, G = kBlock / T;
   constexpr int QM = QM_ < R0 ? QM_ : R0;
@@ -330,7 +334,7 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
   float2* s_buf = s_tw + (PAL ? 0 : N);
   float* s_part = (float*)(s_buf + G * BL);              // SPLIT: [G][V][T]
 
-  const int tid = threadIdx.x, g = tid / T, t = tid % T;
+  const int g = tid / T, t = tid % T;
   int xc, f;
   if constexpr (SPLIT) {
     xc = bid % p.Nc;
@@ -459,7 +463,7 @@ __device__ __forceinline__ void cols_body(const ColArgs& p, int bid, float2* sme
 template <int N, int QM, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_cols(ColArgs p) {
   extern __shared__ float2 smem[];
-  cols_body<N, QM, SPLIT>(p, blockIdx.x, smem);
+  cols_body<N, QM, SPLIT>(p, blockIdx.x, smem, threadIdx.x);
 }
 
 // --------------------------------------------- fused pass (N = 64, 128) ----
@@ -862,6 +866,7 @@ struct HeteroArgs {
   RowArgs rows[kMaxHetero];
   ColArgs cols[kMaxHetero];
   int nfft[kMaxHetero];
+  int rw[kMaxHetero];   // row-pass tile rows per sensor
   int n_items[3][kMaxHetero];
   int order[kMaxHetero];
   int n_sensors, total, spin_limit;
@@ -877,21 +882,31 @@ __global__ void k_counter_reset(int* c, int n) {
 }
 
 template <int N>
-__device__ __forceinline__ void hetero_rows(const RowArgs& a, int bid, float2* smem) {
-  rows_body<N, 3>(a, bid, smem);
+__device__ __forceinline__ void hetero_rows(const RowArgs& a, int rw, int bid, float2* smem, int tid) {
+  if (rw == RowTile<N>::ALT && RowTile<N>::ALT != RowTile<N>::RW)
+    rows_body<N, 3, RowTile<N>::ALT>(a, bid, smem, tid);
+  else
+    rows_body<N, 3, RowTile<N>::RW>(a, bid, smem, tid);
 }
 template <int N>
-__device__ __forceinline__ void hetero_cols(const ColArgs& a, int bid, float2* smem) {
-  cols_body<N, 3, false>(a, bid, smem);
+__device__ __forceinline__ void hetero_cols(const ColArgs& a, int bid, float2* smem, int tid) {
+  cols_body<N, 3, false>(a, bid, smem, tid);
 }
 
-__global__ __launch_bounds__(kBlock, 1) void k_hetero(HeteroArgs p) {
+__global__ __launch_bounds__(kBlock, 2) void k_hetero(HeteroArgs p) {
   extern __shared__ float2 smem[];
-  __shared__ int s_item, s_skip;
+  __shared__ int s_item, s_skip, s_zero;
+  // The bodies' lane-dependent set-up (twiddles, addresses) does not depend
+  // on the item, so the compiler would hoist every body's set-up out of the
+  // claim loop and keep all of it live at once (256 VGPRs + 235 AGPRs, one
+  // wave per SIMD).  Deriving the lane index from an LDS word read after each
+  // claim keeps that set-up inside its own branch (247 VGPRs, two waves).
+  if (threadIdx.x == 0) s_zero = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&p.counters[0], 1);
     __syncthreads();
     int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: selects kernel arguments
+    const int tid = (int)threadIdx.x + __builtin_amdgcn_readfirstlane(s_zero);
     __syncthreads();
     if (item >= p.total) break;
     int kind = 0, s = 0;
@@ -930,17 +945,17 @@ __global__ __launch_bounds__(kBlock, 1) void k_hetero(HeteroArgs p) {
       field_body(p.field[s], item);
     } else if (kind == 1) {
       switch (p.nfft[s]) {
-        case 256: hetero_rows<256>(p.rows[s], item, smem); break;
-        case 384: hetero_rows<384>(p.rows[s], item, smem); break;
-        case 512: hetero_rows<512>(p.rows[s], item, smem); break;
-        default: hetero_rows<768>(p.rows[s], item, smem); break;
+        case 256: hetero_rows<256>(p.rows[s], p.rw[s], item, smem, tid); break;
+        case 384: hetero_rows<384>(p.rows[s], p.rw[s], item, smem, tid); break;
+        case 512: hetero_rows<512>(p.rows[s], p.rw[s], item, smem, tid); break;
+        default: hetero_rows<768>(p.rows[s], p.rw[s], item, smem, tid); break;
       }
     } else {
       switch (p.nfft[s]) {
-        case 256: hetero_cols<256>(p.cols[s], item, smem); break;
-        case 384: hetero_cols<384>(p.cols[s], item, smem); break;
-        case 512: hetero_cols<512>(p.cols[s], item, smem); break;
-        default: hetero_cols<768>(p.cols[s], item, smem); break;
+        case 256: hetero_cols<256>(p.cols[s], item, smem, tid); break;
+        case 384: hetero_cols<384>(p.cols[s], item, smem, tid); break;
+        case 512: hetero_cols<512>(p.cols[s], item, smem, tid); break;
+        default: hetero_cols<768>(p.cols[s], item, smem, tid); break;
       }
     }
     __syncthreads();   // every lane's stores of this item are issued and the LDS is free

@@ -463,6 +463,53 @@ int upload_tables(const pwfs_sensor_desc& d, char* ws, const size_t* off, hipStr
 }
 
 // ---------------------------------------------------- kernel launches ----
+// LDS of one row-pass workgroup: the twiddle table (plans that are not
+// palindromic), the lane groups' exchange buffers, the transpose tile and one
+// spare slot per lane.
+template <int N, int RW>
+static size_t row_lds_bytes(int Nc) {
+  constexpr int T = FftPlan<N>::T, G = kBlock / T;
+  return sizeof(float2) * ((Palindromic<N>::value ? 0 : N) + G * BufLen<N>::value + (size_t)Nc * RW + T);
+}
+
+// Row tile a sensor runs with: its selection if it is the alternative tile
+// of its N, else the default.
+template <int N>
+static int row_tile_of(const SensorPlan& sp) {
+  return sp.row_tile == RowTile<N>::ALT ? RowTile<N>::ALT : RowTile<N>::RW;
+}
+
+template <int N>
+static bool row_tile_fits(int rw, int Nc) {
+  if (rw == RowTile<N>::RW) return row_lds_bytes<N, RowTile<N>::RW>(Nc) <= kMaxLds;
+  if (rw == RowTile<N>::ALT) return row_lds_bytes<N, RowTile<N>::ALT>(Nc) <= kMaxLds;
+  return false;
+}
+
+static int row_tile(const SensorPlan& sp) {
+  switch (sp.g.N) {
+    case 64: return row_tile_of<64>(sp);
+    case 128: return row_tile_of<128>(sp);
+    case 256: return row_tile_of<256>(sp);
+    case 384: return row_tile_of<384>(sp);
+    case 512: return row_tile_of<512>(sp);
+    default: return row_tile_of<768>(sp);
+  }
+}
+
+// Whether `rw` is one of the compiled tiles of N and fits the LDS at Nc columns.
+static bool row_tile_ok(int N, int rw, int Nc) {
+  switch (N) {
+    case 64: return row_tile_fits<64>(rw, Nc);
+    case 128: return row_tile_fits<128>(rw, Nc);
+    case 256: return row_tile_fits<256>(rw, Nc);
+    case 384: return row_tile_fits<384>(rw, Nc);
+    case 512: return row_tile_fits<512>(rw, Nc);
+    case 768: return row_tile_fits<768>(rw, Nc);
+  }
+  return false;
+}
+
 // Arguments of the three passes of one sensor over `nf` frames.
 struct PassArgs {
   FieldArgs fa;
@@ -472,10 +519,10 @@ struct PassArgs {
   size_t lds_rows, lds_cols, lds_cols_split;
 };
 
-template <int N>
+template <int N, int RW>
 static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd_stride, float* out,
                            long long out_stride, int nf, float2* rbuf, int row_group_target) {
-  constexpr int T = FftPlan<N>::T, G = kBlock / T, RW = RowTile<N>::RW;
+  constexpr int T = FftPlan<N>::T, G = kBlock / T;
   const Geometry& g = sp.g;
   PassArgs pa{};
   float2* field = rbuf + rbuf_field_offset(sp.desc, nf);
@@ -514,7 +561,7 @@ static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd
   ra.win_hi = g.win_hi;
   ra.full = g.full;
   constexpr bool PAL = Palindromic<N>::value;   // tables in registers, not LDS
-  pa.lds_rows = sizeof(float2) * ((PAL ? 0 : N) + G * BufLen<N>::value + (size_t)g.Nc * RW + T);
+  pa.lds_rows = row_lds_bytes<N, RW>(g.Nc);
   pa.grid_rows = (unsigned)((long long)nf * ra.rowblocks * ra.n_agroups);
 
   ColArgs& ca = pa.ca;
@@ -545,15 +592,23 @@ static PassArgs build_pass(const SensorPlan& sp, const float* opd, long long opd
   return pa;
 }
 
+template <int N>
+static PassArgs build_pass_rw(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost,
+                              int nf, float2* rbuf, int target) {
+  if (row_tile_of<N>(sp) == RowTile<N>::ALT)
+    return build_pass<N, RowTile<N>::ALT>(sp, opd, os, out, ost, nf, rbuf, target);
+  return build_pass<N, RowTile<N>::RW>(sp, opd, os, out, ost, nf, rbuf, target);
+}
+
 static PassArgs build_pass_any(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost,
                                int nf, float2* rbuf, int target) {
   switch (sp.g.N) {
-    case 64: return build_pass<64>(sp, opd, os, out, ost, nf, rbuf, target);
-    case 128: return build_pass<128>(sp, opd, os, out, ost, nf, rbuf, target);
-    case 256: return build_pass<256>(sp, opd, os, out, ost, nf, rbuf, target);
-    case 384: return build_pass<384>(sp, opd, os, out, ost, nf, rbuf, target);
-    case 512: return build_pass<512>(sp, opd, os, out, ost, nf, rbuf, target);
-    default: return build_pass<768>(sp, opd, os, out, ost, nf, rbuf, target);
+    case 64: return build_pass_rw<64>(sp, opd, os, out, ost, nf, rbuf, target);
+    case 128: return build_pass_rw<128>(sp, opd, os, out, ost, nf, rbuf, target);
+    case 256: return build_pass_rw<256>(sp, opd, os, out, ost, nf, rbuf, target);
+    case 384: return build_pass_rw<384>(sp, opd, os, out, ost, nf, rbuf, target);
+    case 512: return build_pass_rw<512>(sp, opd, os, out, ost, nf, rbuf, target);
+    default: return build_pass_rw<768>(sp, opd, os, out, ost, nf, rbuf, target);
   }
 }
 
@@ -591,10 +646,10 @@ static IdentArgs ident_args(const SensorPlan& sp, const PassArgs& pa, int nf) {
 
 static unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-template <int N, int QM>
+template <int N, int QM, int RW>
 static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_stride, float* out,
                        long long out_stride, int nf, float2* rbuf, hipStream_t st, Prof* prof) {
-  const PassArgs pa = build_pass<N>(sp, opd, opd_stride, out, out_stride, nf, rbuf, 2048);
+  const PassArgs pa = build_pass<N, RW>(sp, opd, opd_stride, out, out_stride, nf, rbuf, 2048);
   int slot = prof->begin(st);
   hipLaunchKernelGGL(k_field, dim3(pa.grid_field), dim3(kBlock), 0, st, pa.fa);
   HIP_TRY(hipGetLastError(), "launch k_field");
@@ -605,7 +660,7 @@ static int launch_fp32(const SensorPlan& sp, const float* opd, long long opd_str
     hipLaunchKernelGGL(k_rows_ident, dim3(blocks_for((long long)nf * ia.n_lam * ia.n_a * ia.Nc * ia.D)),
                        dim3(kBlock), 0, st, ia);
   } else {
-    hipLaunchKernelGGL((k_rows<N, QM>), dim3(pa.grid_rows), dim3(kBlock), pa.lds_rows, st, pa.ra);
+    hipLaunchKernelGGL((k_rows<N, QM, RW>), dim3(pa.grid_rows), dim3(kBlock), pa.lds_rows, st, pa.ra);
   }
   HIP_TRY(hipGetLastError(), "launch k_rows");
   prof->end(slot, st, K_ROWS);
@@ -698,6 +753,7 @@ int forward_hetero(pwfs_plan_s* p, const float* opd, int f0, int nf, float* out,
     ha.rows[i] = pa.ra;
     ha.cols[i] = pa.ca;
     ha.nfft[i] = sp.g.N;
+    ha.rw[i] = row_tile(sp);
     ha.n_items[0][i] = (int)pa.grid_field;
     ha.n_items[1][i] = (int)pa.grid_rows;
     ha.n_items[2][i] = (int)pa.grid_cols;
@@ -723,24 +779,32 @@ int forward_hetero(pwfs_plan_s* p, const float* opd, int f0, int nf, float* out,
   return PWFS_OK;
 }
 
-template <int N>
+template <int N, int RW>
 static int launch_fp32_q(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost,
                          int nf, float2* rbuf, hipStream_t st, Prof* pr) {
   const int q = sp.g.qmax;
-  if (q <= 3) return launch_fp32<N, 3>(sp, opd, os, out, ost, nf, rbuf, st, pr);
-  if (q == 4) return launch_fp32<N, 4>(sp, opd, os, out, ost, nf, rbuf, st, pr);
-  return launch_fp32<N, 8>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+  if (q <= 3) return launch_fp32<N, 3, RW>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+  if (q == 4) return launch_fp32<N, 4, RW>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+  return launch_fp32<N, 8, RW>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+}
+
+template <int N>
+static int launch_fp32_rw(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost,
+                          int nf, float2* rbuf, hipStream_t st, Prof* pr) {
+  if (row_tile_of<N>(sp) == RowTile<N>::ALT)
+    return launch_fp32_q<N, RowTile<N>::ALT>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+  return launch_fp32_q<N, RowTile<N>::RW>(sp, opd, os, out, ost, nf, rbuf, st, pr);
 }
 
 int forward_fp32(const SensorPlan& sp, const float* opd, long long os, float* out, long long ost, int nf,
                  float2* rbuf, hipStream_t st, Prof* pr) {
   switch (sp.g.N) {
-    case 64: return launch_fp32_q<64>(sp, opd, os, out, ost, nf, rbuf, st, pr);
-    case 128: return launch_fp32_q<128>(sp, opd, os, out, ost, nf, rbuf, st, pr);
-    case 256: return launch_fp32_q<256>(sp, opd, os, out, ost, nf, rbuf, st, pr);
-    case 384: return launch_fp32_q<384>(sp, opd, os, out, ost, nf, rbuf, st, pr);
-    case 512: return launch_fp32_q<512>(sp, opd, os, out, ost, nf, rbuf, st, pr);
-    case 768: return launch_fp32_q<768>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 64: return launch_fp32_rw<64>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 128: return launch_fp32_rw<128>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 256: return launch_fp32_rw<256>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 384: return launch_fp32_rw<384>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 512: return launch_fp32_rw<512>(sp, opd, os, out, ost, nf, rbuf, st, pr);
+    case 768: return launch_fp32_rw<768>(sp, opd, os, out, ost, nf, rbuf, st, pr);
   }
   return fail(PWFS_EUNSUPPORTED, "n_fft %d", sp.g.N);
 }
@@ -749,13 +813,14 @@ int forward_fp32(const SensorPlan& sp, const float* opd, long long os, float* ou
 // launch that needs more than the default fails and is reported by
 // hipGetLastError at that launch.
 static void lds_limit(const void* fn) {
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
     (void)hipGetLastError();
 }
 
 template <int N, int QM>
 static int set_lds_limits() {
-  lds_limit((const void*)k_rows<N, QM>);
+  lds_limit((const void*)k_rows<N, QM, RowTile<N>::RW>);
+  lds_limit((const void*)k_rows<N, QM, RowTile<N>::ALT>);
   lds_limit((const void*)k_cols<N, QM, false>);
   lds_limit((const void*)k_cols<N, QM, true>);
   return PWFS_OK;
@@ -1059,6 +1124,32 @@ int pwfs_set_tuning(pwfs_plan_t p, const pwfs_tuning* t) {
   p->tune = *t;
   p->tune.max_chunk = p->max_chunk;
   p->chunk = t->chunk;
+  return PWFS_OK;
+}
+
+int pwfs_set_row_tile(pwfs_plan_t p, int sensor, int rows) {
+  if (!p) return fail(PWFS_EINVAL, "plan is NULL");
+  if (sensor < 0 || sensor >= (int)p->s.size()) return fail(PWFS_EINVAL, "sensor %d out of range", sensor);
+  SensorPlan& sp = p->s[sensor];
+  if (rows == 0) {
+    sp.row_tile = 0;
+    return PWFS_OK;
+  }
+  if (sp.desc.precision != PWFS_FP32)
+    return fail(PWFS_EUNSUPPORTED, "the row tile applies to the FP32 path only");
+  int nc = sp.g.Nc;
+  for (int a = 0; a < sp.arms; ++a) nc = std::max(nc, sp.arm_g[a].Nc);
+  if (!row_tile_ok(sp.g.N, rows, nc))
+    return fail(PWFS_EINVAL, "row tile %d is not compiled for N = %d or does not fit the LDS at %d columns", rows,
+                sp.g.N, nc);
+  sp.row_tile = rows;
+  return PWFS_OK;
+}
+
+int pwfs_get_row_tile(pwfs_plan_t p, int sensor, int* rows) {
+  if (!p || !rows) return fail(PWFS_EINVAL, "NULL argument");
+  if (sensor < 0 || sensor >= (int)p->s.size()) return fail(PWFS_EINVAL, "sensor %d out of range", sensor);
+  *rows = row_tile(p->s[sensor]);
   return PWFS_OK;
 }
 

@@ -153,6 +153,8 @@ def lib() -> ctypes.CDLL:
     L.pwfs_sh_destroy.restype = None
     L.pwfs_get_tuning.argtypes = [vp, P(CTuning)]
     L.pwfs_set_tuning.argtypes = [vp, P(CTuning)]
+    L.pwfs_set_row_tile.argtypes = [vp, i32, i32]
+    L.pwfs_get_row_tile.argtypes = [vp, i32, P(ctypes.c_int32)]
     ll = ctypes.c_longlong
     L.pwfs_gemm_workspace_size.argtypes = [i32, i32, i32, i32, P(ctypes.c_size_t)]
     L.pwfs_gemm.argtypes = [vp, ll, vp, ll, vp, ll, i32, i32, i32, ctypes.c_float, ctypes.c_float, i32, vp,
@@ -173,7 +175,7 @@ def lib() -> ctypes.CDLL:
     L.pwfs_mlp_destroy.argtypes = [vp]
     L.pwfs_mlp_destroy.restype = None
     for name in ("pwfs_validate", "pwfs_workspace_size", "pwfs_plan", "pwfs_forward", "pwfs_slopes",
-                 "pwfs_query", "pwfs_device_status", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
+                 "pwfs_query", "pwfs_device_status", "pwfs_set_row_tile", "pwfs_get_row_tile", "pwfs_valid_map", "pwfs_profile", "pwfs_profile_read",
                  "pwfs_gemm_workspace_size", "pwfs_gemm", "pwfs_gemm_noalloc", "pwfs_row_rms", "pwfs_mlp_workspace_size",
                  "pwfs_mlp_create", "pwfs_mlp_param_count", "pwfs_mlp_set_params", "pwfs_mlp_get_params",
                  "pwfs_mlp_get_state", "pwfs_mlp_set_state", "pwfs_mlp_set_linear",
@@ -386,6 +388,16 @@ class Plan:
                     int(cur["max_chunk"]), int(cur["spin_limit"]))
         check(lib().pwfs_set_tuning(self._h, ctypes.byref(t)))
         return self.get_tuning()
+
+    def row_tile(self, sensor: int) -> int:
+        """Rows per row-pass workgroup that ``sensor`` runs with (pwfs_get_row_tile)."""
+        r = ctypes.c_int32()
+        check(lib().pwfs_get_row_tile(self._h, int(sensor), ctypes.byref(r)))
+        return r.value
+
+    def set_row_tile(self, sensor: int, rows: int) -> None:
+        """Selects the row-pass tile of one FP32 sensor (0 = its default; pwfs_set_row_tile)."""
+        check(lib().pwfs_set_row_tile(self._h, int(sensor), int(rows)))
 
     def status(self, stream=None) -> None:
         """Synchronises the stream and raises PwfsError (PWFS_EHIP) if a

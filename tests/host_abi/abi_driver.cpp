@@ -91,6 +91,21 @@ void run_plan(const pwfs_sensor_desc* d, int n, int frames, const char* label) {
   bad.reserved[0] = 1;
   EXPECT(pwfs_set_tuning(plan, &bad) == PWFS_EINVAL);
   EXPECT(pwfs_set_tuning(plan, &t) == PWFS_OK);
+  // row tiles: every value the autotuner tries, per sensor; forward with each accepted one
+  for (int i = 0; i < n; ++i) {
+    int rows = -1;
+    EXPECT(pwfs_get_row_tile(plan, i, &rows) == PWFS_OK);
+    EXPECT(rows == 8 || rows == 16 || rows == 32);
+    for (int r : {4, 8, 16, 32}) {
+      const int rc2 = pwfs_set_row_tile(plan, i, r);
+      EXPECT(rc2 == PWFS_OK || rc2 == PWFS_EINVAL || rc2 == PWFS_EUNSUPPORTED);
+      if (rc2 == PWFS_OK) EXPECT(pwfs_forward(plan, opd.f(), frames, inten.f(), nullptr) == PWFS_OK);
+    }
+    EXPECT(pwfs_set_row_tile(plan, i, 0) == PWFS_OK);
+  }
+  EXPECT(pwfs_set_row_tile(plan, n, 8) == PWFS_EINVAL);
+  EXPECT(pwfs_get_row_tile(plan, 0, nullptr) == PWFS_EINVAL);
+  EXPECT(pwfs_set_row_tile(nullptr, 0, 8) == PWFS_EINVAL);
   EXPECT(pwfs_profile(plan, 7) == PWFS_OK);
   EXPECT(pwfs_forward(plan, opd.f(), frames, inten.f(), nullptr) == PWFS_OK);
   EXPECT(pwfs_slopes(plan, inten.f(), frames, slopes.f(), nullptr, nullptr) == PWFS_OK);

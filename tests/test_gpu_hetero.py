@@ -134,3 +134,38 @@ def test_persistent_wait_timeout_is_reported():
     I1, S1, _ = plan.step(x)
     plan.status()
     assert torch.equal(I0, I1) and torch.equal(S0, S1)
+
+
+def test_row_tiles_give_identical_bits_in_both_modes():
+    """Every compiled row tile (8 or 16 rows per row-pass workgroup, chosen
+    per sensor) gives the default tile's bits, with per-sensor launches and
+    in the persistent launch; tiles that are not compiled for a sensor's N
+    are refused."""
+    from paper_2602_06688_amd import pwfs as P
+    sensors = _small_hetero()
+    F = 2
+    opds = [von_karman_opd(F, s.n_pupil, 38.5, 0.157, 25.0, seed=40 + i) for i, s in enumerate(sensors)]
+    x = torch.from_numpy(_packed(opds)).cuda()
+    plan = P.Plan(sensors, max_frames=F)
+    assert [plan.row_tile(i) for i in range(6)] == [8, 16, 8, 8, 8, 8]
+    I0, S0, _ = [t.clone() for t in plan.step(x)]
+    alt = [16, 8, 16, 16, 16, 16]
+    for mode in (P.MODE_LAUNCHES, P.MODE_PERSISTENT):
+        for pick in ([1, 1, 1, 1, 1, 1], [0, 1, 0, 1, 0, 1]):
+            tiles = [a if p else 0 for a, p in zip(alt, pick)]
+            print(f"[gpu] hetero small: mode {mode} row tiles {tiles}", flush=True)
+            for i, r in enumerate(tiles):
+                plan.set_row_tile(i, r)
+            plan.set_tuning(mode=mode)
+            I1, S1, _ = plan.step(x)
+            torch.cuda.synchronize()
+            assert torch.equal(I0, I1) and torch.equal(S0, S1)
+    for i in range(6):
+        plan.set_row_tile(i, 0)
+    assert [plan.row_tile(i) for i in range(6)] == [8, 16, 8, 8, 8, 8]
+    for bad in (4, 12, 32):
+        with pytest.raises(P.PwfsError) as ei:
+            plan.set_row_tile(2, bad)
+        assert ei.value.code == P.PWFS_EINVAL
+    with pytest.raises(P.PwfsError):
+        plan.set_row_tile(6, 8)
