@@ -59,14 +59,19 @@ __device__ __forceinline__ void split16(float x, uint16_t& hi, uint16_t& lo) {
 }
 
 // --------------------------------------------------------------- engine ---
-template <int NPLANES, bool F16, int BK = kGemmBK>
+// BN: columns of C per workgroup tile (128, or 256 for the wave-specialised
+// kernels, whose consumer waves then form 2 x 4 quarters of 64 x 64).
+template <int NPLANES, bool F16, int BK = kGemmBK, int BN = kGemmTile>
 struct MfmaTile {
   static_assert(BK == 32 || BK == 64, "K step of 32 or 64");
+  static_assert(BN == 128 || BN == 256, "128 or 256 columns per tile");
   static constexpr bool SCALED = F16 && NPLANES == 2;   // accumulator holds 2^11 C
   static constexpr int BK_ = BK;
+  static constexpr int NPL_ = NPLANES;
   static constexpr int LROW = BK + 8;     // 16-bit elements per padded LDS row
   static constexpr int H = BK / 16;       // 16-byte chunks per lane and operand plane in one K step
-  static constexpr int STAGE = 2 * NPLANES * kGemmTile * LROW;  // uint16 per stage (A and B)
+  static constexpr int BROW0 = NPLANES * kGemmTile;              // first B row of a stage
+  static constexpr int STAGE = NPLANES * (kGemmTile + BN) * LROW;  // uint16 per stage (A planes, then B planes)
   static constexpr size_t lds_bytes() { return sizeof(uint16_t) * 2 * STAGE; }
 
   f32x16_t acc[2][2];
@@ -85,6 +90,9 @@ struct MfmaTile {
     if constexpr (SCALED) return acc[i][j][e] * (1.f / 2048.f);
     else return acc[i][j][e];
   }
+
+  // element offset, within a stage, of element k of stage row r
+  __device__ __forceinline__ static int slot(int r, int k) { return r * LROW + k; }
 
   __device__ __forceinline__ static f32x16_t mma(u32x4_t a, u32x4_t b, f32x16_t c) {
     if constexpr (F16)
@@ -152,8 +160,8 @@ struct MfmaTile {
       fetch_slot(tid, h, row, kq);
 #pragma unroll
       for (int pl = 0; pl < NPLANES; ++pl) {
-        *(u32x4_t*)(stage + (pl * kGemmTile + row) * LROW + kq) = p.a[pl][h];
-        *(u32x4_t*)(stage + ((NPLANES + pl) * kGemmTile + row) * LROW + kq) = p.b[pl][h];
+        *(u32x4_t*)(stage + slot(pl * kGemmTile + row, kq)) = p.a[pl][h];
+        *(u32x4_t*)(stage + slot(BROW0 + pl * BN + row, kq)) = p.b[pl][h];
       }
     }
   }
@@ -168,23 +176,32 @@ struct MfmaTile {
       for (int pl = 0; pl < NPLANES; ++pl)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          fa[pl][i] = *(const u32x4_t*)(stage + (pl * kGemmTile + wm * 64 + i * 32 + r) * LROW + s * 16 + kh);
-          fb[pl][i] =
-              *(const u32x4_t*)(stage + ((NPLANES + pl) * kGemmTile + wn * 64 + i * 32 + r) * LROW + s * 16 + kh);
+          fa[pl][i] = *(const u32x4_t*)(stage + slot(pl * kGemmTile + wm * 64 + i * 32 + r, s * 16 + kh));
+          fb[pl][i] = *(const u32x4_t*)(stage + slot(BROW0 + pl * BN + wn * 64 + i * 32 + r, s * 16 + kh));
         }
+      // term-major: the products that accumulate into one tile are four
+      // MFMAs apart, so none waits for the one before it; each tile still
+      // adds hi*hi, hi*lo, lo*hi in that order
+      u32x4_t hi_a[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        u32x4_t hi_a = fa[0][i];
+        hi_a[i] = fa[0][i];
         if constexpr (SCALED)
-          hi_a = __builtin_bit_cast(u32x4_t, __builtin_bit_cast(f16x8_t, hi_a) * (_Float16)2048.0f);
+          hi_a[i] = __builtin_bit_cast(u32x4_t, __builtin_bit_cast(f16x8_t, hi_a[i]) * (_Float16)2048.0f);
+      }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = mma(hi_a, fb[0][j], acc[i][j]);
-          if constexpr (NPLANES == 2) {
-            acc[i][j] = mma(fa[0][i], fb[1][j], acc[i][j]);
-            acc[i][j] = mma(fa[1][i], fb[0][j], acc[i][j]);
-          }
-        }
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mma(hi_a[i], fb[0][j], acc[i][j]);
+      if constexpr (NPLANES == 2) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = mma(fa[0][i], fb[1][j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = mma(fa[1][i], fb[0][j], acc[i][j]);
       }
     }
   }

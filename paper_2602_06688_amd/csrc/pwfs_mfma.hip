@@ -33,11 +33,9 @@ namespace pwfs {
 
 namespace {
 
-// The one-term form runs K steps of 64 (8 products per wavefront between
-// barriers rather than 4, so that load latency hides behind them); the
-// split forms' three products already give 12 per step of 32.
-template <int NPL, bool F16>
-using Engine = MfmaTile<NPL, F16, NPL == 1 ? 64 : 32>;
+// K steps the producer waves of the wave-specialised stages keep in flight,
+// and the columns of a workgroup tile
+constexpr int kWsDepth = 2, kWsCols = 256;
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
@@ -173,64 +171,258 @@ __device__ __forceinline__ int xcd_major_block() {
   return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + idx;
 }
 
-// One workgroup owns a tile of (wavelength, output rows, field rows) and runs
-// the n_a products T_a of that tile (same field rows, one Qx_a each) as one
-// stream of K steps; each product is stored as it completes, while the
-// next product's first operands are in flight.
-template <int NPL, bool F16>
-__global__ __launch_bounds__(256) void k_mfma_rows(G1Args p) {
+struct G2Args {
+  const uint16_t* a;      // Qy'' plane 0 [n_lam][n_mod][M][Kp]; plane 1 at +a_plane
+  const uint16_t* t;      // T as written by stage 1
+  const int2* kord;       // [n_mod] (k, a)
+  float* out;             // first frame of the pass, frame stride out_stride
+  long long a_plane, t_plane, out_stride;
+  int M, F, Nc, N, D, Kp, n_a, n_lam, n_mod, win_lo, win_hi, full;
+  int mtiles, ntiles;     // tiles over the M rows of e and over all F Nc columns of the pass
+  float scale[PWFS_MAX_LAMBDA];
+};
+
+// Wave-specialised stages (one workgroup per CU).  The consumer waves (2 x
+// BN/64 of them, each a 64 x 64 quarter of a 128 x BN tile) run the MFMAs
+// and the epilogue, reading each K step from one of two LDS stages.  Four producer waves only move operands: every producer
+// lane owns CH 16-byte chunks of a K step and keeps DEPTH steps of them in
+// flight in registers; at each step it stores the oldest into the stage the
+// consumers read next and issues the loads of the step DEPTH further on.  A
+// step's loads thus have DEPTH steps of matrix work to arrive (a 256-lane
+// workgroup whose waves both fetch and compute could keep only one step in
+// flight within its registers).  The two roles live in separate loops, so their
+// registers are not held at the same time; both pass the same workgroup
+// barriers, one per K step.  A wider tile (BN = 256) reads each row of A
+// once for twice the columns.
+// The one-term form runs K steps of 64 (16 products per consumer wave
+// between barriers), the split forms K steps of 32 (their three products
+// already give 24).
+template <int NPL, bool F16, int BN>
+using WsEngine = MfmaTile<NPL, F16, NPL == 1 ? 64 : 32, BN>;
+
+// Chunk layout of one K step for the producers: part h (lane pt moves chunk
+// pt + 256 h) covers RPP whole rows of one plane block of A or of B.
+template <class E, int BN>
+struct WsParts {
+  static constexpr int NPL = E::NPL_;
+  static constexpr int CPR = E::BK_ / 8;                   // 16-byte chunks per row and step
+  static constexpr int ROWS = NPL * (kGemmTile + BN);      // A planes, then B planes
+  static constexpr int RPP = 256 / CPR;                    // rows per part
+  static constexpr int CH = ROWS / RPP;                    // parts
+  static_assert(CH * RPP == ROWS && kGemmTile % RPP == 0 && BN % RPP == 0,
+                "each producer part lies in one plane block of A or B");
+  // plane block of part h: A planes 0..NPL-1, then B planes (compile-time per h)
+  static constexpr bool is_a(int h) { return h * RPP < NPL * kGemmTile; }
+  static constexpr int plane(int h) { return is_a(h) ? h * RPP / kGemmTile : (h * RPP - NPL * kGemmTile) / BN; }
+  // tile row (within its operand) of lane pt's chunk in part h, and its K offset
+  __device__ static int row(int pt, int h) {
+    const int rr = (pt + 256 * h) / CPR;
+    return is_a(h) ? rr % kGemmTile : (rr - NPL * kGemmTile) % BN;
+  }
+  __device__ static int kq(int pt, int h) { return ((pt + 256 * h) % CPR) * 8; }
+  __device__ static int lds_offset(int pt, int h) { return E::slot((pt + 256 * h) / CPR, kq(pt, h)); }
+};
+
+// The producer loop.  fetch(buf, s) issues the loads of step s into buf;
+// every fetch is issued unconditionally (steps past the end re-load the last
+// step, unused), so the compiler's in-order load counter sees the same DEPTH
+// sets in flight on every path and waits only for the oldest.
+template <class E, int DEPTH, int CH, class Fetch>
+__device__ __forceinline__ void ws_produce(uint16_t* lds, const int (&loff)[CH], int steps, Fetch fetch) {
+  u32x4_t buf[DEPTH][CH];
+  auto stash = [&](const u32x4_t (&b)[CH], uint16_t* stage) {
+#pragma unroll
+    for (int h = 0; h < CH; ++h) *(u32x4_t*)(stage + loff[h]) = b[h];
+  };
+#pragma unroll
+  for (int u = 0; u < DEPTH; ++u) fetch(buf[u], min(u, steps - 1));
+  stash(buf[0], lds);
+  fetch(buf[0], min(DEPTH, steps - 1));
+  __syncthreads();
+  int st = 0;
+  for (; st + DEPTH <= steps; st += DEPTH) {
+#pragma unroll
+    for (int u = 0; u < DEPTH; ++u) {
+      // step st + u + 1 waits in buf[(u + 1) % DEPTH]: it goes to the stage
+      // the consumers read after this barrier, and the buffer takes the step
+      // DEPTH further on
+      stash(buf[(u + 1) % DEPTH], lds + ((st + u + 1) & 1) * E::STAGE);
+      fetch(buf[(u + 1) % DEPTH], min(st + u + 1 + DEPTH, steps - 1));
+      __syncthreads();
+    }
+  }
+  // the last steps (fewer than DEPTH) are already in flight
+#pragma unroll
+  for (int u = 0; u < DEPTH - 1; ++u) {
+    if (st + u >= steps) break;
+    if (st + u + 1 < steps) stash(buf[(u + 1) % DEPTH], lds + ((st + u + 1) & 1) * E::STAGE);
+    __syncthreads();
+  }
+}
+
+// Stage 2: columns of C run over all frames of the pass (n = f Nc + c), so a
+// tile may straddle two frames and only the pass's last tile is ragged.  The
+// n_lam x n_mod products of one tile form one stream of K steps, and a
+// product's |e|^2 is accumulated as it completes.
+template <int NPL, bool F16, int DEPTH, int BN>
+__global__ __launch_bounds__(64 * (2 * BN / 64 + 4)) void k_mfma_cols_ws(G2Args p) {
   extern __shared__ uint4 lds_raw[];
   uint16_t* lds = (uint16_t*)lds_raw;
-  using E = Engine<NPL, F16>;
+  using E = WsEngine<NPL, F16, BN>;
+  using W = WsParts<E, BN>;
+  constexpr int NC = 2 * BN / 64, BK = E::BK_, CH = W::CH;
   const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int bid = xcd_major_block();
+  const int mt = bid % p.mtiles;
+  const int nt = bid / p.mtiles;
+  const int m0 = mt * kGemmTile, n0 = nt * BN;
+  const int NT = p.F * p.Nc;
+  const int nk = p.Kp / BK;
+  const int steps = p.n_lam * p.n_mod * nk;
+
+  if (wave >= NC) {
+    const int pt = tid - 64 * NC;
+    const long long t_frame = (long long)p.n_lam * p.n_a * p.Nc * p.Kp;
+    long long goff[CH];   // element offset of chunk h within its plane's operand block
+    int loff[CH];
+#pragma unroll
+    for (int h = 0; h < CH; ++h) {
+      const int row = W::row(pt, h), kq = W::kq(pt, h);
+      if (W::is_a(h)) {
+        goff[h] = (long long)min(m0 + row, p.M - 1) * p.Kp + kq;
+      } else {
+        const int n = min(n0 + row, NT - 1);
+        const int fr = n / p.Nc;
+        goff[h] = fr * t_frame + (long long)(n - fr * p.Nc) * p.Kp + kq;
+      }
+      loff[h] = W::lds_offset(pt, h);
+    }
+    ws_produce<E, DEPTH>(lds, loff, steps, [&](u32x4_t (&b)[CH], int s) {
+      const int prod = s / nk, kt = s - prod * nk;
+      const int lam = prod / p.n_mod;
+      // through the scalar cache: a vector load here would have to wait for
+      // every load in flight before it (the counter is in order)
+      const long long kv =
+          *((const __attribute__((address_space(4))) long long*)p.kord + (prod - lam * p.n_mod));
+      const int kx = (int)(kv & 0xffffffffLL), ky = (int)(kv >> 32);   // (k, a) of the product
+      const uint16_t* abase = p.a + ((long long)lam * p.n_mod + kx) * p.M * p.Kp + kt * BK;
+      const uint16_t* bbase = p.t + ((long long)lam * p.n_a + ky) * p.Nc * p.Kp + kt * BK;
+#pragma unroll
+      for (int h = 0; h < CH; ++h) {
+        const uint16_t* base = W::is_a(h) ? abase + W::plane(h) * p.a_plane : bbase + W::plane(h) * p.t_plane;
+        b[h] = *(const u32x4_t*)(base + goff[h]);
+      }
+    });
+    return;
+  }
+
+  // -------------------------------------------------------------- consumer
+  const int lane = tid & 63;
+  const int wm = wave & 1, wn = wave >> 1;
+  float inten[2][2][8];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) inten[i][j][e] = 0.f;
+  E eng;
+  eng.zero();
+  __syncthreads();
+  int prod = 0, kt = 0;
+  for (int st = 0; st < steps; ++st) {
+    eng.compute(lds + (st & 1) * E::STAGE, wm, wn, lane);
+    if (kt == nk - 1) {
+      const float sc = p.scale[prod / p.n_mod];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int e = 0; e < 16; e += 2) {
+            const float re = eng.value(i, j, e), im = eng.value(i, j, e + 1);
+            inten[i][j][e >> 1] += sc * (re * re + im * im);
+          }
+      eng.zero();
+      kt = 0;
+      ++prod;
+    } else {
+      ++kt;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; e += 2) {
+        // accumulator layout of the 32 x 32 tile (i, j) of this quarter
+        const int row = wm * 64 + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const int col = wn * 64 + j * 32 + (lane & 31);
+        const int Yc = (m0 + row) >> 1, n = n0 + col;
+        if (Yc >= p.Nc || n >= NT) continue;
+        const int fr = n / p.Nc, Xc = n - fr * p.Nc;
+        const int Y = p.full ? Yc : window_coord(Yc, p.D, p.win_lo, p.win_hi);
+        const int X = p.full ? Xc : window_coord(Xc, p.D, p.win_lo, p.win_hi);
+        p.out[(long long)fr * p.out_stride + (long long)Y * p.N + X] = inten[i][j][e >> 1];
+      }
+}
+
+// Stage 1: the tile of (wavelength, 128 output rows, BN field rows) runs the
+// n_a products T_a of its field rows (one Qx_a each) as one stream of K
+// steps; each product is stored by the consumers as it completes.
+template <int NPL, bool F16, int DEPTH, int BN>
+__global__ __launch_bounds__(64 * (2 * BN / 64 + 4)) void k_mfma_rows_ws(G1Args p) {
+  extern __shared__ uint4 lds_raw[];
+  uint16_t* lds = (uint16_t*)lds_raw;
+  using E = WsEngine<NPL, F16, BN>;
+  using W = WsParts<E, BN>;
+  constexpr int NC = 2 * BN / 64, BK = E::BK_, CH = W::CH;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   int bid = xcd_major_block();
   const int mt = bid % p.mtiles;
   bid /= p.mtiles;
   const int nt = bid % p.ntiles;
   const int lam = bid / p.ntiles;
-  const int m0 = mt * kGemmTile, n0 = nt * kGemmTile;
+  const int m0 = mt * kGemmTile, n0 = nt * BN;
   const int NF = p.F * p.D;
-  long long ao[E::H], bo[E::H];
-#pragma unroll
-  for (int h = 0; h < E::H; ++h) {
-    int row, kq;
-    E::fetch_slot(tid, h, row, kq);
-    ao[h] = (long long)min(m0 + row, p.M - 1) * p.Kp + kq;
-    bo[h] = (long long)min(n0 + row, NF - 1) * p.Kp + kq;
-  }
-  auto ops_of = [&](int a) {
-    typename E::Ops o;
-#pragma unroll
-    for (int pl = 0; pl < NPL; ++pl) {
-      o.a[pl] = p.a + pl * p.a_plane + ((long long)lam * p.n_a + a) * p.M * p.Kp;
-      o.b[pl] = p.b + pl * p.b_plane + (long long)lam * NF * p.Kp;
-    }
-    return o;
-  };
-  const int wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int nk = p.Kp / E::BK_;
+  const int nk = p.Kp / BK;
   const int steps = p.n_a * nk;
 
+  if (wave >= NC) {
+    const int pt = tid - 64 * NC;
+    long long goff[CH];
+    int loff[CH];
+#pragma unroll
+    for (int h = 0; h < CH; ++h) {
+      const int row = W::row(pt, h), kq = W::kq(pt, h);
+      goff[h] = (long long)(W::is_a(h) ? min(m0 + row, p.M - 1) : min(n0 + row, NF - 1)) * p.Kp + kq;
+      loff[h] = W::lds_offset(pt, h);
+    }
+    ws_produce<E, DEPTH>(lds, loff, steps, [&](u32x4_t (&b)[CH], int s) {
+      const int a = s / nk, kt = s - a * nk;
+      const uint16_t* abase = p.a + ((long long)lam * p.n_a + a) * p.M * p.Kp + kt * BK;
+      const uint16_t* bbase = p.b + (long long)lam * NF * p.Kp + kt * BK;
+#pragma unroll
+      for (int h = 0; h < CH; ++h) {
+        const uint16_t* base = W::is_a(h) ? abase + W::plane(h) * p.a_plane : bbase + W::plane(h) * p.b_plane;
+        b[h] = *(const u32x4_t*)(base + goff[h]);
+      }
+    });
+    return;
+  }
+
+  // -------------------------------------------------------------- consumer
+  const int lane = tid & 63;
+  const int wm = wave & 1, wn = wave >> 1;
   E eng;
   eng.zero();
-  typename E::Pref pf;
-  typename E::Ops cur_ops = ops_of(0);
-  E::fetch_at(pf, cur_ops, ao, bo, 0);
-  E::stash(pf, lds, tid);
   __syncthreads();
   int a = 0, kt = 0;
   for (int st = 0; st < steps; ++st) {
-    int na = a, nkt = kt + 1;
-    if (nkt == nk) {
-      nkt = 0;
-      ++na;
-    }
-    const bool more = st + 1 < steps;
-    if (more) {
-      if (nkt == 0) cur_ops = ops_of(na);
-      E::fetch_at(pf, cur_ops, ao, bo, nkt * E::BK_);
-    }
     eng.compute(lds + (st & 1) * E::STAGE, wm, wn, lane);
     if (kt == nk - 1) {
       // output offset = column part (frame, y; j only) + row part (X, c)
@@ -277,136 +469,13 @@ __global__ __launch_bounds__(256) void k_mfma_rows(G1Args p) {
           }
         }
       eng.zero();
+      kt = 0;
+      ++a;
+    } else {
+      ++kt;
     }
-    if (more) E::stash(pf, lds + ((st + 1) & 1) * E::STAGE, tid);
     __syncthreads();
-    a = na;
-    kt = nkt;
   }
-}
-
-struct G2Args {
-  const uint16_t* a;      // Qy'' plane 0 [n_lam][n_mod][M][Kp]; plane 1 at +a_plane
-  const uint16_t* t;      // T as written by stage 1
-  const int2* kord;       // [n_mod] (k, a)
-  float* out;             // first frame of the pass, frame stride out_stride
-  long long a_plane, t_plane, out_stride;
-  int M, F, Nc, N, D, Kp, n_a, n_lam, n_mod, win_lo, win_hi, full;
-  int mtiles, ntiles;     // tiles over the M rows of e and over all F Nc columns of the pass
-  float scale[PWFS_MAX_LAMBDA];
-};
-
-// Columns of C run over all frames of the pass (n = f Nc + c), so a tile may
-// straddle two frames and only the pass's last tile is ragged.  The
-// n_lam x n_mod products of one tile form one stream of K steps: the next
-// step's operands (possibly the next product's first) are fetched while the
-// current step runs, and a product's |e|^2 is accumulated as it completes.
-template <int NPL, bool F16>
-__global__ __launch_bounds__(256) void k_mfma_cols(G2Args p) {
-  extern __shared__ uint4 lds_raw[];
-  uint16_t* lds = (uint16_t*)lds_raw;
-  using E = Engine<NPL, F16>;
-  const int tid = threadIdx.x;
-  // the mtiles row tiles that read the same columns of T are neighbours, so
-  // they share one XCD's L2
-  const int bid = xcd_major_block();
-  const int mt = bid % p.mtiles;
-  const int nt = bid / p.mtiles;
-  const int m0 = mt * kGemmTile, n0 = nt * kGemmTile;
-  const int NT = p.F * p.Nc;
-  const long long t_frame = (long long)p.n_lam * p.n_a * p.Nc * p.Kp;
-
-  // per-lane row offsets of the two rows this lane moves (rows past the end
-  // are clamped; their products are never stored)
-  long long ao[E::H], bo[E::H];
-#pragma unroll
-  for (int h = 0; h < E::H; ++h) {
-    int row, kq;
-    E::fetch_slot(tid, h, row, kq);
-    ao[h] = (long long)min(m0 + row, p.M - 1) * p.Kp + kq;
-    const int n = min(n0 + row, NT - 1);
-    const int fr = n / p.Nc;
-    bo[h] = fr * t_frame + (long long)(n - fr * p.Nc) * p.Kp + kq;
-  }
-
-  float inten[2][2][8];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) inten[i][j][e] = 0.f;
-
-  const int wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int nk = p.Kp / E::BK_;
-  const int steps = p.n_lam * p.n_mod * nk;
-  auto ops_of = [&](int prod) {
-    const int lam = prod / p.n_mod;
-    const int2 ka = p.kord[prod - lam * p.n_mod];
-    typename E::Ops o;
-#pragma unroll
-    for (int pl = 0; pl < NPL; ++pl) {
-      o.a[pl] = p.a + pl * p.a_plane + ((long long)lam * p.n_mod + ka.x) * p.M * p.Kp;
-      o.b[pl] = p.t + pl * p.t_plane + ((long long)lam * p.n_a + ka.y) * p.Nc * p.Kp;
-    }
-    return o;
-  };
-
-  E eng;
-  eng.zero();
-  typename E::Pref pf;
-  typename E::Ops cur_ops = ops_of(0);
-  E::fetch_at(pf, cur_ops, ao, bo, 0);
-  E::stash(pf, lds, tid);
-  __syncthreads();
-  int prod = 0, kt = 0;
-  for (int st = 0; st < steps; ++st) {
-    // the step after this one
-    int nprod = prod, nkt = kt + 1;
-    if (nkt == nk) {
-      nkt = 0;
-      ++nprod;
-    }
-    const bool more = st + 1 < steps;
-    if (more) {
-      if (nkt == 0) cur_ops = ops_of(nprod);
-      E::fetch_at(pf, cur_ops, ao, bo, nkt * E::BK_);
-    }
-    eng.compute(lds + (st & 1) * E::STAGE, wm, wn, lane);
-    if (kt == nk - 1) {
-      const float sc = p.scale[prod / p.n_mod];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int e = 0; e < 16; e += 2) {
-            const float re = eng.value(i, j, e), im = eng.value(i, j, e + 1);
-            inten[i][j][e >> 1] += sc * (re * re + im * im);
-          }
-      eng.zero();
-    }
-    if (more) E::stash(pf, lds + ((st + 1) & 1) * E::STAGE, tid);
-    __syncthreads();
-    prod = nprod;
-    kt = nkt;
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; e += 2) {
-        int row, col;
-        E::coord(tid, i, j, e, row, col);
-        const int Yc = (m0 + row) >> 1, n = n0 + col;
-        if (Yc >= p.Nc || n >= NT) continue;
-        const int fr = n / p.Nc, Xc = n - fr * p.Nc;
-        const int Y = p.full ? Yc : window_coord(Yc, p.D, p.win_lo, p.win_hi);
-        const int X = p.full ? Xc : window_coord(Xc, p.D, p.win_lo, p.win_hi);
-        p.out[(long long)fr * p.out_stride + (long long)Y * p.N + X] = inten[i][j][e >> 1];
-      }
 }
 
 template <int NPL, bool F16>
@@ -442,7 +511,8 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
   if (e != hipSuccess) return PWFS_EHIP;
   prof->end(slot, st, K_FIELD);
 
-  const size_t lds = Engine<NPL, F16>::lds_bytes();
+  const size_t lds = WsEngine<NPL, F16, kWsCols>::lds_bytes();
+  constexpr unsigned block = 64 * (2 * kWsCols / 64 + 4);
   G1Args a1{};
   a1.a = qx;
   a1.b = field;
@@ -458,10 +528,10 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
   a1.n_a = m.n_a;
   a1.n_lam = m.n_lam;
   a1.mtiles = (m.M + kGemmTile - 1) / kGemmTile;
-  a1.ntiles = (nf * m.D + kGemmTile - 1) / kGemmTile;
+  a1.ntiles = (nf * m.D + kWsCols - 1) / kWsCols;
   const unsigned g1 = (unsigned)(m.n_lam * a1.mtiles * a1.ntiles);
   slot = prof->begin(st);
-  hipLaunchKernelGGL((k_mfma_rows<NPL, F16>), dim3(g1), dim3(256), lds, st, a1);
+  hipLaunchKernelGGL((k_mfma_rows_ws<NPL, F16, kWsDepth, kWsCols>), dim3(g1), dim3(block), lds, st, a1);
   if ((e = hipGetLastError()) != hipSuccess) return PWFS_EHIP;
   prof->end(slot, st, K_ROWS);
 
@@ -483,7 +553,7 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
   a2.n_lam = m.n_lam;
   a2.n_mod = m.n_mod;
   a2.mtiles = (m.M + kGemmTile - 1) / kGemmTile;
-  a2.ntiles = (int)(((long long)nf * m.Nc + kGemmTile - 1) / kGemmTile);
+  a2.ntiles = (int)(((long long)nf * m.Nc + kWsCols - 1) / kWsCols);
   a2.win_lo = g.win_lo;
   a2.win_hi = g.win_hi;
   a2.full = g.full;
@@ -491,7 +561,7 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
     a2.scale[l] = (float)(sp.desc.lambda_weight[l] / ((double)sp.g.n_mod * sp.sumA2));
   const unsigned g2 = (unsigned)(a2.mtiles * a2.ntiles);
   slot = prof->begin(st);
-  hipLaunchKernelGGL((k_mfma_cols<NPL, F16>), dim3(g2), dim3(256), lds, st, a2);
+  hipLaunchKernelGGL((k_mfma_cols_ws<NPL, F16, kWsDepth, kWsCols>), dim3(g2), dim3(block), lds, st, a2);
   if ((e = hipGetLastError()) != hipSuccess) return PWFS_EHIP;
   prof->end(slot, st, K_MFMA);
   return PWFS_OK;
@@ -499,12 +569,12 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
 
 template <int NPL, bool F16>
 void set_lds() {
-  const int lds = (int)Engine<NPL, F16>::lds_bytes();
-  if (hipFuncSetAttribute((const void*)k_mfma_rows<NPL, F16>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
-      hipSuccess)
+  const int lds_ws = (int)WsEngine<NPL, F16, kWsCols>::lds_bytes();
+  if (hipFuncSetAttribute((const void*)k_mfma_cols_ws<NPL, F16, kWsDepth, kWsCols>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds_ws) != hipSuccess)
     (void)hipGetLastError();
-  if (hipFuncSetAttribute((const void*)k_mfma_cols<NPL, F16>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
-      hipSuccess)
+  if (hipFuncSetAttribute((const void*)k_mfma_rows_ws<NPL, F16, kWsDepth, kWsCols>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds_ws) != hipSuccess)
     (void)hipGetLastError();
 }
 
