@@ -477,24 +477,50 @@ def hetero_form(P, torch, dev, stream, steps: int, graph_reps: int = 200):
     S = plan.new_slopes(F)
     Fl = torch.zeros((F, len(w.sensors)), dtype=torch.float32, device=dev)
     tune = autotune(plan, lambda: plan.forward(x, I, stream=stream), F, reps=2)
-    for _ in range(1):
-        plan.step(x, I, S, Fl, stream=stream)
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.step(x, I, S, Fl, stream=stream)
-    torch.cuda.synchronize(dev)
-    dt = time.perf_counter() - t0
-    # kernel durations from one more step with every launch timed (a run of
-    # its own: the events would slow the timed steps)
-    plan.profile(1 << 16)
-    plan.step(x, I, S, Fl, stream=stream)
-    torch.cuda.synchronize(dev)
-    kms = {k: plan.profile_read(k) for k in ("field", "rows", "cols", "slopes", "hetero")}
-    plan.profile(0)
-    gpu_ms = sum(v[0] for v in kms.values())
+    best_by_mode = {}
+    for c in tune.get("tried", []):
+        name = {P.MODE_LAUNCHES: "launches", P.MODE_PERSISTENT: "persistent"}.get(c["mode"], str(c["mode"]))
+        best_by_mode[name] = round(min(best_by_mode.get(name, c["ms"]), c["ms"]), 3)
     path = sum(nominal_flops(s)["path"] for s in w.sensors)
-    ach = path * F / (gpu_ms / 1e3) / 1e12
+
+    def timed():
+        """Timesteps/s over ``steps`` steps, then the kernel durations of one
+        more step with every launch timed (a run of its own: the events would
+        slow the timed steps)."""
+        plan.step(x, I, S, Fl, stream=stream)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.step(x, I, S, Fl, stream=stream)
+        torch.cuda.synchronize(dev)
+        dt = time.perf_counter() - t0
+        plan.profile(1 << 16)
+        plan.step(x, I, S, Fl, stream=stream)
+        torch.cuda.synchronize(dev)
+        kms = {k: plan.profile_read(k) for k in ("field", "rows", "cols", "slopes", "hetero")}
+        plan.profile(0)
+        gpu_ms = sum(v[0] for v in kms.values())
+        return dt, kms, path * F / (gpu_ms / 1e3) / 1e12
+
+    # the best persistent setting the tuner found, measured as a form of its
+    # own (one persistent launch per pass for all six sensors), then the tuned one
+    persistent = None
+    pers = [c for c in tune.get("tried", []) if c["mode"] == P.MODE_PERSISTENT]
+    if pers:
+        pb = min(pers, key=lambda c: c["ms"])
+        plan.set_tuning(**{k: pb[k] for k in ("mode", "chunk", "wg_per_cu", "row_groups")})
+        for i, r in enumerate(pb.get("row_tiles", [])):
+            plan.set_row_tile(i, r)
+        pdt, pkms, pach = timed()
+        persistent = {"value": round(F * steps / pdt, 2), "unit": "timesteps/s",
+                      "tuning": {k: pb[k] for k in ("chunk", "wg_per_cu", "row_groups", "row_tiles") if k in pb},
+                      "roofline_frac": round(pach / FP32_PEAK_TFLOPS, 4),
+                      "kernel_ms_per_step": {k: round(v[0], 3) for k, v in pkms.items() if v[1]},
+                      "launches_per_step": sum(v[1] for v in pkms.values())}
+        plan.set_tuning(**{k: tune[k] for k in ("mode", "chunk", "wg_per_cu", "row_groups")})
+        for i, r in enumerate(tune.get("row_tiles", [])):
+            plan.set_row_tile(i, r)
+    dt, kms, ach = timed()
     # one timestep (frame 0 of every sensor) captured in a graph, replayed
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream(device=dev)
@@ -513,11 +539,16 @@ def hetero_form(P, torch, dev, stream, steps: int, graph_reps: int = 200):
         g.replay()
     torch.cuda.synchronize(dev)
     lat = (time.perf_counter() - t0) / graph_reps * 1e3
+    if persistent:
+        print(f"# hetero persistent: {persistent['value']:.1f} timesteps/s, frac {persistent['roofline_frac']:.3f}",
+              file=sys.stderr, flush=True)
     print(f"# hetero: {F * steps / dt:.1f} timesteps/s ({tune.get('mode')}, chunk {tune.get('chunk')}), "
           f"graph timestep {lat:.3f} ms", file=sys.stderr, flush=True)
     return {"value": round(F * steps / dt, 2), "unit": "timesteps/s",
             "workload": w.name, "frames": F, "ms_per_step": round(dt / steps * 1e3, 3),
-            "tuning": {k: tune[k] for k in ("mode", "chunk", "wg_per_cu", "row_groups") if k in tune},
+            "tuning": {k: tune[k] for k in ("mode", "chunk", "wg_per_cu", "row_groups", "row_tiles") if k in tune},
+            "best_ms_by_mode": best_by_mode,
+            "persistent": persistent,
             "graph_timestep_ms": round(lat, 4), "graph_replay_matches_eager": same,
             "roofline": {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(ach / FP32_PEAK_TFLOPS, 4), "flops_per_timestep": path, "traffic": None,
