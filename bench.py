@@ -133,7 +133,7 @@ def time_form(P, torch, s, x, n_frames, steps, warmup, ref_I, ref_S, dev, stream
            "errors_vs_oracle": ev,
            "at_stated_error": (ev["slope_rel_rms"] <= 1e-3) if ev else None,
            "intensity_rel_err_max_vs_fp32": ie, "slope_rel_rms_vs_fp32": se,
-           "roofline": {"kernel": "k_mfma_cols (stage 2: e_k = Qy_k T, |e|^2 accumulate)", "bound": "mfma",
+           "roofline": {"kernel": "k_mfma_cols_ws (stage 2: e_k = Qy_k T, |e|^2 accumulate)", "bound": "mfma",
                         "achieved": round(ach, 2) if ach else None, "peak": peak, "unit": "TFLOP/s",
                         "frac": round(ach / peak, 4) if ach else None, "traffic": None,
                         "avg_launch_ms": round(g2_ms / max(1, g2_n), 4), "flops_per_frame": fl["stage2"]},
@@ -776,7 +776,7 @@ def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
             g2, n2 = kern["mfma"]
             fpl = F * reps / max(1, n2)
             ach = fl["stage2"] * fpl / (g2 / max(1, n2) / 1e3) / 1e12 if g2 > 0 else None
-            rec["roofline"] = {"kernel": "k_mfma_cols (stage 2)", "bound": "mfma",
+            rec["roofline"] = {"kernel": "k_mfma_cols_ws (stage 2)", "bound": "mfma",
                                "achieved": round(ach, 2) if ach else None, "peak": MFMA_PEAK_TFLOPS["bf16"],
                                "unit": "TFLOP/s", "frac": round(ach / MFMA_PEAK_TFLOPS["bf16"], 4) if ach else None,
                                "flops_per_frame": fl["stage2"], "traffic": None}
