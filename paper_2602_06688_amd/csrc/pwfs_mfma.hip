@@ -12,6 +12,13 @@
 // 2 forms e_k = Qy_k T_a(k) and accumulates c_lambda |e_k|^2 over k and
 // wavelength in registers (c_lambda = w_lambda / (n_mod sum A^2)).
 //
+// Operand layout: every 16-bit operand block of R rows by Kp columns (a
+// plane of a table, of the split field, of T) is stored K-blocked, [Kp/BK][R]
+// [BK] with BK the K step of the engine (32 for the split forms, 64 for the
+// one-term form), so that one K step of consecutive rows is contiguous: the
+// producers' 16-byte loads then use whole 128-byte lines within one step
+// instead of half of a line in each of two steps.
+//
 // Complex products run as real products on an interleaved block form: the
 // left operand's rows come in pairs (Re Q[X][.], -Im Q[X][.]) and
 // (Im Q[X][.], Re Q[X][.]) over K = (real parts, imaginary parts) of the
@@ -40,7 +47,7 @@ constexpr int kWsDepth = 2, kWsCols = 256;
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
 struct MGeom {
-  int D, N, Nc, Kp, M, n_a, n_lam, n_mod, planes;
+  int D, N, Nc, Kp, M, n_a, n_lam, n_mod, planes, bk;
   bool f16;
 };
 
@@ -51,6 +58,7 @@ MGeom mgeom(const pwfs_sensor_desc& d) {
   m.N = g.N;
   m.Nc = g.Nc;
   const int bk = d.precision == PWFS_BF16 ? 64 : 32;   // the K step of the engine used
+  m.bk = bk;
   m.Kp = (2 * g.D + bk - 1) / bk * bk;
   m.M = 2 * g.Nc;
   m.n_a = g.n_a;
@@ -117,23 +125,25 @@ void host_split(float x, bool f16, uint16_t& hi, uint16_t& lo) {
 struct SplitFieldArgs {
   const float* opd;       // first frame of the pass, frame stride opd_stride
   const float* amp;       // [D][D]
-  uint16_t* out;          // plane 0 [n_lam][F][D][Kp], plane 1 follows at +plane
+  uint16_t* out;          // plane 0 [n_lam][Kp/BK][F D][BK] (rows f D + y), plane 1 follows at +plane
   long long opd_stride, plane;
-  int D, Kp, F, n_lam, planes;
+  int D, Kp, BK, F, n_lam, planes;
   double two_pi_over_lam[PWFS_MAX_LAMBDA];
 };
 
 template <bool F16>
 __global__ __launch_bounds__(256) void k_field_split(SplitFieldArgs p) {
   const long long total = (long long)p.n_lam * p.F * p.D * p.Kp;
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;   // output element, in output order
   if (i >= total) return;
-  const int kk = (int)(i % p.Kp);
-  long long r = i / p.Kp;
-  const int y = (int)(r % p.D);
-  r /= p.D;
-  const int f = (int)(r % p.F);
-  const int lam = (int)(r / p.F);
+  const int rows = p.F * p.D;
+  const int kr = (int)(i % p.BK);
+  long long r = i / p.BK;
+  const int row = (int)(r % rows);
+  r /= rows;
+  const int kb = (int)(r % (p.Kp / p.BK));
+  const int lam = (int)(r / (p.Kp / p.BK));
+  const int kk = kb * p.BK + kr, y = row % p.D, f = row / p.D;
   float v = 0.f;
   if (kk < 2 * p.D) {
     const int x = kk % p.D;
@@ -155,9 +165,9 @@ __global__ __launch_bounds__(256) void k_field_split(SplitFieldArgs p) {
 }
 
 struct G1Args {
-  const uint16_t* a;      // Qx'' plane 0 [n_lam][n_a][M][Kp]; plane 1 at +a_plane
-  const uint16_t* b;      // split field plane 0 [n_lam][F][D][Kp]; plane 1 at +b_plane
-  uint16_t* t;            // T plane 0 [F][n_lam][n_a][Nc][Kp]; plane 1 at +t_plane
+  const uint16_t* a;      // Qx'' plane 0 [n_lam][n_a] blocks of M x Kp; plane 1 at +a_plane
+  const uint16_t* b;      // split field plane 0 [n_lam] blocks of F D x Kp; plane 1 at +b_plane
+  uint16_t* t;            // T plane 0 [F][n_lam][n_a] blocks of Nc x Kp; plane 1 at +t_plane
   long long a_plane, b_plane, t_plane;
   int M, F, D, Kp, Nc, n_a, n_lam;
   int mtiles, ntiles;     // tiles over the M output rows and over all F D field rows of the pass
@@ -172,7 +182,7 @@ __device__ __forceinline__ int xcd_major_block() {
 }
 
 struct G2Args {
-  const uint16_t* a;      // Qy'' plane 0 [n_lam][n_mod][M][Kp]; plane 1 at +a_plane
+  const uint16_t* a;      // Qy'' plane 0 [n_lam][n_mod] blocks of M x Kp; plane 1 at +a_plane
   const uint16_t* t;      // T as written by stage 1
   const int2* kord;       // [n_mod] (k, a)
   float* out;             // first frame of the pass, frame stride out_stride
@@ -211,16 +221,34 @@ struct WsParts {
   static constexpr int CH = ROWS / RPP;                    // parts
   static_assert(CH * RPP == ROWS && kGemmTile % RPP == 0 && BN % RPP == 0,
                 "each producer part lies in one plane block of A or B");
+  static_assert(CPR != 4 || RPP == 64, "the row order of a part covers 64 rows");
   // plane block of part h: A planes 0..NPL-1, then B planes (compile-time per h)
   static constexpr bool is_a(int h) { return h * RPP < NPL * kGemmTile; }
   static constexpr int plane(int h) { return is_a(h) ? h * RPP / kGemmTile : (h * RPP - NPL * kGemmTile) / BN; }
-  // tile row (within its operand) of lane pt's chunk in part h, and its K offset
+  // Stage row and K offset of lane pt's chunk in part h.  Four consecutive
+  // lanes move the four chunks (64 contiguous bytes) of one row.  With K
+  // steps of 32 the padded rows are 80 bytes (5 16-byte bank quads) apart,
+  // so the 32 lanes of one store are given the rows a + 4m, m = 0..7: their
+  // chunks then fill distinct quads of the 512 bytes of LDS banks (and so of
+  // each 256-byte half), where eight consecutive rows would overlap.
+  __device__ static int stage_row(int pt, int h) {
+    if constexpr (CPR == 4) {
+      const int grp = pt >> 5, w = pt & 31;
+      return h * RPP + ((grp >> 2) << 5) + (grp & 3) + 4 * (w >> 2);
+    } else {
+      return (pt + 256 * h) / CPR;
+    }
+  }
+  __device__ static int kq(int pt, int h) {
+    if constexpr (CPR == 4) return (pt & 3) * 8;
+    else return ((pt + 256 * h) % CPR) * 8;
+  }
+  // tile row of the chunk within its operand
   __device__ static int row(int pt, int h) {
-    const int rr = (pt + 256 * h) / CPR;
+    const int rr = stage_row(pt, h);
     return is_a(h) ? rr % kGemmTile : (rr - NPL * kGemmTile) % BN;
   }
-  __device__ static int kq(int pt, int h) { return ((pt + 256 * h) % CPR) * 8; }
-  __device__ static int lds_offset(int pt, int h) { return E::slot((pt + 256 * h) / CPR, kq(pt, h)); }
+  __device__ static int lds_offset(int pt, int h) { return E::slot(stage_row(pt, h), kq(pt, h)); }
 };
 
 // The producer loop.  fetch(buf, s) issues the loads of step s into buf;
@@ -284,17 +312,17 @@ __global__ __launch_bounds__(64 * (2 * BN / 64 + 4)) void k_mfma_cols_ws(G2Args 
   if (wave >= NC) {
     const int pt = tid - 64 * NC;
     const long long t_frame = (long long)p.n_lam * p.n_a * p.Nc * p.Kp;
-    long long goff[CH];   // element offset of chunk h within its plane's operand block
+    long long goff[CH];   // element offset of chunk h within its operand block's first K block
     int loff[CH];
 #pragma unroll
     for (int h = 0; h < CH; ++h) {
       const int row = W::row(pt, h), kq = W::kq(pt, h);
       if (W::is_a(h)) {
-        goff[h] = (long long)min(m0 + row, p.M - 1) * p.Kp + kq;
+        goff[h] = (long long)min(m0 + row, p.M - 1) * BK + kq;
       } else {
         const int n = min(n0 + row, NT - 1);
         const int fr = n / p.Nc;
-        goff[h] = fr * t_frame + (long long)(n - fr * p.Nc) * p.Kp + kq;
+        goff[h] = fr * t_frame + (long long)(n - fr * p.Nc) * BK + kq;
       }
       loff[h] = W::lds_offset(pt, h);
     }
@@ -306,8 +334,9 @@ __global__ __launch_bounds__(64 * (2 * BN / 64 + 4)) void k_mfma_cols_ws(G2Args 
       const long long kv =
           *((const __attribute__((address_space(4))) long long*)p.kord + (prod - lam * p.n_mod));
       const int kx = (int)(kv & 0xffffffffLL), ky = (int)(kv >> 32);   // (k, a) of the product
-      const uint16_t* abase = p.a + ((long long)lam * p.n_mod + kx) * p.M * p.Kp + kt * BK;
-      const uint16_t* bbase = p.t + ((long long)lam * p.n_a + ky) * p.Nc * p.Kp + kt * BK;
+      // K block kt of the product's blocks (M rows of Qy, Nc rows of T per frame)
+      const uint16_t* abase = p.a + ((long long)lam * p.n_mod + kx) * p.M * p.Kp + (long long)kt * p.M * BK;
+      const uint16_t* bbase = p.t + ((long long)lam * p.n_a + ky) * p.Nc * p.Kp + (long long)kt * p.Nc * BK;
 #pragma unroll
       for (int h = 0; h < CH; ++h) {
         const uint16_t* base = W::is_a(h) ? abase + W::plane(h) * p.a_plane : bbase + W::plane(h) * p.t_plane;
@@ -399,13 +428,14 @@ __global__ __launch_bounds__(64 * (2 * BN / 64 + 4)) void k_mfma_rows_ws(G1Args 
 #pragma unroll
     for (int h = 0; h < CH; ++h) {
       const int row = W::row(pt, h), kq = W::kq(pt, h);
-      goff[h] = (long long)(W::is_a(h) ? min(m0 + row, p.M - 1) : min(n0 + row, NF - 1)) * p.Kp + kq;
+      goff[h] = (long long)(W::is_a(h) ? min(m0 + row, p.M - 1) : min(n0 + row, NF - 1)) * BK + kq;
       loff[h] = W::lds_offset(pt, h);
     }
     ws_produce<E, DEPTH>(lds, loff, steps, [&](u32x4_t (&b)[CH], int s) {
       const int a = s / nk, kt = s - a * nk;
-      const uint16_t* abase = p.a + ((long long)lam * p.n_a + a) * p.M * p.Kp + kt * BK;
-      const uint16_t* bbase = p.b + (long long)lam * NF * p.Kp + kt * BK;
+      // K block kt of the product's Qx block (M rows) and of the field (F D rows)
+      const uint16_t* abase = p.a + ((long long)lam * p.n_a + a) * p.M * p.Kp + (long long)kt * p.M * BK;
+      const uint16_t* bbase = p.b + (long long)lam * NF * p.Kp + (long long)kt * NF * BK;
 #pragma unroll
       for (int h = 0; h < CH; ++h) {
         const uint16_t* base = W::is_a(h) ? abase + W::plane(h) * p.a_plane : bbase + W::plane(h) * p.b_plane;
@@ -425,16 +455,20 @@ __global__ __launch_bounds__(64 * (2 * BN / 64 + 4)) void k_mfma_rows_ws(G1Args 
   for (int st = 0; st < steps; ++st) {
     eng.compute(lds + (st & 1) * E::STAGE, wm, wn, lane);
     if (kt == nk - 1) {
-      // output offset = column part (frame, y; j only) + row part (X, c)
-      long long cofs[2];
+      // output element (row X of T, column c D + y) of the product's block
+      // (frame f) in the K-blocked layout
+      long long fb[2];
       int ys[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int n = min(n0 + wn * 64 + j * 32 + (lane & 31), NF - 1);
         const int f = n / p.D;
         ys[j] = n - f * p.D;
-        cofs[j] = (((long long)f * p.n_lam + lam) * p.n_a + a) * p.Nc * p.Kp + ys[j];
+        fb[j] = (((long long)f * p.n_lam + lam) * p.n_a + a) * p.Nc * p.Kp;
       }
+      auto t_at = [&](int j, int X, int kidx) {
+        return fb[j] + (long long)(kidx / BK) * p.Nc * BK + X * BK + (kidx % BK);
+      };
       int mb = m0 + wm * 64 + 4 * (lane >> 5);   // even: element e has c = e & 1
       // opaque, so that the 32 row offsets below are formed here and not kept
       // live across the whole K stream
@@ -445,12 +479,11 @@ __global__ __launch_bounds__(64 * (2 * BN / 64 + 4)) void k_mfma_rows_ws(G1Args 
         for (int e = 0; e < 16; ++e) {
           const int m = mb + i * 32 + 8 * (e >> 2) + (e & 3);
           if (m >= p.M) continue;
-          const int c = e & 1;
-          const int rofs = (m >> 1) * p.Kp + c * p.D;
+          const int c = e & 1, X = m >> 1;
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             if (n0 + wn * 64 + j * 32 + (lane & 31) >= NF) continue;
-            const long long o = cofs[j] + rofs;
+            const long long o = t_at(j, X, c * p.D + ys[j]);
             const float v = eng.value(i, j, e);
             if constexpr (NPL == 2) {
               uint16_t hi, lo;
@@ -462,9 +495,10 @@ __global__ __launch_bounds__(64 * (2 * BN / 64 + 4)) void k_mfma_rows_ws(G1Args 
             }
             // the K padding [2D, Kp) of this row must hold zeros for stage 2
             if (c == 1)
-              for (int z = ys[j]; z < p.Kp - 2 * p.D; z += p.D) {
-                p.t[o + p.D + z - ys[j]] = 0;
-                if constexpr (NPL == 2) p.t[p.t_plane + o + p.D + z - ys[j]] = 0;
+              for (int kz = 2 * p.D + ys[j]; kz < p.Kp; kz += p.D) {
+                const long long oz = t_at(j, X, kz);
+                p.t[oz] = 0;
+                if constexpr (NPL == 2) p.t[p.t_plane + oz] = 0;
               }
           }
         }
@@ -500,6 +534,7 @@ int launch(const SensorPlan& sp, const MGeom& m, const float* opd, long long os,
   fa.plane = field_plane;
   fa.D = m.D;
   fa.Kp = m.Kp;
+  fa.BK = m.bk;
   fa.F = nf;
   fa.n_lam = m.n_lam;
   fa.planes = m.planes;
@@ -631,8 +666,9 @@ int upload_mfma_tables(const pwfs_sensor_desc& d, char* dst, hipStream_t st, std
       for (int x = 0; x < D; ++x) {
         const std::complex<double> q = P[(size_t)xc * D + x] * ramp[x];
         const float vals[4] = {(float)q.real(), (float)-q.imag(), (float)q.imag(), (float)q.real()};
-        const size_t idx[4] = {(size_t)(2 * xc) * m.Kp + x, (size_t)(2 * xc) * m.Kp + D + x,
-                               (size_t)(2 * xc + 1) * m.Kp + x, (size_t)(2 * xc + 1) * m.Kp + D + x};
+        // element (row, col) of the K-blocked M x Kp block
+        auto at = [&](int row, int col) { return (size_t)(col / m.bk) * m.M * m.bk + (size_t)row * m.bk + col % m.bk; };
+        const size_t idx[4] = {at(2 * xc, x), at(2 * xc, D + x), at(2 * xc + 1, x), at(2 * xc + 1, D + x)};
         for (int t = 0; t < 4; ++t) {
           uint16_t hi, lo;
           if (m.planes == 2) {
