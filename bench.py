@@ -703,13 +703,13 @@ def host_info(torch, dev) -> dict:
 
 def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
     """The 64 px sensor (N=128, 16 points, 16 x 16, 100 frames): the plain
-    FP32 path and its precision forms (bf16 x3, fp16 x3, bf16) on the same
+    FP32 path and its precision forms (bf16 x3, fp16 x3, bf16, fp16) on the same
     shapes and inputs.  frames/s from the median of graph replays of the
     100-frame batch, errors against the oracle on all 100 frames, kernel
     durations from HIP events over eager steps."""
     import numpy as np
     from oracle import pwfs as O
-    from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16X3, workload, workload_opd
+    from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16, PREC_FP16X3, workload, workload_opd
     w = workload("cfg1")
     s = w.sensors[0]
     F = w.n_frames
@@ -724,7 +724,7 @@ def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
     x = torch.from_numpy(opd).to(dev)
     out = {"workload": w.name, "frames_per_batch": F, "oracle_seconds_single_process": round(t_oracle, 2)}
     for label, prec in (("fp32", 0), ("fp32_fused", 0), ("mfma_bf16x3", PREC_BF16X3),
-                        ("mfma_fp16x3", PREC_FP16X3), ("mfma_bf16", PREC_BF16)):
+                        ("mfma_fp16x3", PREC_FP16X3), ("mfma_bf16", PREC_BF16), ("mfma_fp16", PREC_FP16)):
         sp = s.with_(precision=prec)
         plan = P.Plan([sp], max_frames=F, device=dev, stream=stream)
         if label == "fp32_fused":
@@ -771,7 +771,7 @@ def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
                                     "frac": round(fl["path"] * F / (gpu_ms / 1e3) / 1e12 / FP32_PEAK_TFLOPS, 4),
                                     "flops_per_frame": fl["path"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
         else:
-            terms = 1 if prec == PREC_BF16 else 3
+            terms = 1 if prec in (PREC_BF16, PREC_FP16) else 3
             fl = mfma_flops(sp, terms)
             g2, n2 = kern["mfma"]
             fpl = F * reps / max(1, n2)
@@ -786,7 +786,7 @@ def small_sensor_forms(P, torch, dev, stream, reps: int) -> dict:
         print(f"# 64 px {label}: {rec['value']:.0f} frames/s (median of {reps} replays of {F} frames), "
               f"slope err vs oracle {err['slope_rel_rms']:.2e}", file=sys.stderr, flush=True)
     base = out["fp32"]["value"]
-    for label in ("fp32_fused", "mfma_bf16x3", "mfma_fp16x3", "mfma_bf16"):
+    for label in ("fp32_fused", "mfma_bf16x3", "mfma_fp16x3", "mfma_bf16", "mfma_fp16"):
         out[label]["vs_fp32_plain"] = round(out[label]["value"] / base, 3)
     return out
 
@@ -899,10 +899,11 @@ def main() -> int:
 
     forms = {}
     if not args.no_forms:
-        from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16X3
+        from workloads import PREC_BF16, PREC_BF16X3, PREC_FP16, PREC_FP16X3
         for label, prec, terms, dt_name in (("mfma_bf16x3", PREC_BF16X3, 3, "bf16"),
                                             ("mfma_fp16x3", PREC_FP16X3, 3, "fp16"),
-                                            ("mfma_bf16", PREC_BF16, 1, "bf16")):
+                                            ("mfma_bf16", PREC_BF16, 1, "bf16"),
+                                            ("mfma_fp16", PREC_FP16, 1, "fp16")):
             forms[label] = time_form(P, torch, s.with_(precision=prec), x, w.n_frames, max(20, args.steps // 2),
                                      1, I, S, dev, stream, label, terms, dt_name, refs)
     if not args.no_small:

@@ -60,7 +60,9 @@ typedef enum {
   PWFS_FP32 = 0,    /* radix FFTs in float32 on the vector ALUs            */
   PWFS_BF16 = 1,    /* dense DFT operator as bf16 MFMA products, 1 term     */
   PWFS_BF16X3 = 2,  /* bf16 MFMA with hi/lo split, 3 products, fp32 accum   */
-  PWFS_FP16X3 = 3   /* fp16 MFMA with scaled hi/lo split, 3 products        */
+  PWFS_FP16X3 = 3,  /* fp16 MFMA with scaled hi/lo split, 3 products        */
+  PWFS_FP16 = 4     /* dense DFT operator as fp16 MFMA products, 1 term:
+                       the bf16 form's speed with 3 more mantissa bits      */
 } pwfs_precision;
 
 enum {

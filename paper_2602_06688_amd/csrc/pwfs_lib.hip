@@ -92,7 +92,7 @@ int validate_one(const pwfs_sensor_desc& d, int idx) {
   if (Si & 1) return bad("pupil_sep_px must be even");
   if (Si < d.n_pupil) return bad("pupil images overlap (pupil_sep_px < n_pupil)");
   if (Si + d.n_pupil > d.n_fft) return bad("pupil images fall outside the grid (pupil_sep_px + n_pupil > n_fft)");
-  if (d.precision < PWFS_FP32 || d.precision > PWFS_FP16X3) return bad("unknown precision");
+  if (d.precision < PWFS_FP32 || d.precision > PWFS_FP16) return bad("unknown precision");
   if (d.n_subap > 64) return fail(PWFS_EUNSUPPORTED, "sensor %d: n_subap > 64 not supported", idx);
   if (!supported_fft(d.n_fft))
     return fail(PWFS_EUNSUPPORTED, "sensor %d: n_fft %d has no radix plan (64,128,256,384,512,768)", idx, d.n_fft);

@@ -57,15 +57,16 @@ MGeom mgeom(const pwfs_sensor_desc& d) {
   m.D = g.D;
   m.N = g.N;
   m.Nc = g.Nc;
-  const int bk = d.precision == PWFS_BF16 ? 64 : 32;   // the K step of the engine used
+  const bool one_term = d.precision == PWFS_BF16 || d.precision == PWFS_FP16;
+  const int bk = one_term ? 64 : 32;   // the K step of the engine used
   m.bk = bk;
   m.Kp = (2 * g.D + bk - 1) / bk * bk;
   m.M = 2 * g.Nc;
   m.n_a = g.n_a;
   m.n_lam = g.n_lam;
   m.n_mod = g.n_mod;
-  m.planes = d.precision == PWFS_BF16 ? 1 : 2;
-  m.f16 = d.precision == PWFS_FP16X3;
+  m.planes = one_term ? 1 : 2;
+  m.f16 = d.precision == PWFS_FP16X3 || d.precision == PWFS_FP16;
   return m;
 }
 
@@ -616,7 +617,8 @@ void set_lds() {
 }  // namespace
 
 bool mfma_supported(const pwfs_sensor_desc& d) {
-  return d.precision == PWFS_BF16 || d.precision == PWFS_BF16X3 || d.precision == PWFS_FP16X3;
+  return d.precision == PWFS_BF16 || d.precision == PWFS_BF16X3 || d.precision == PWFS_FP16X3 ||
+         d.precision == PWFS_FP16;
 }
 
 size_t mfma_table_bytes(const pwfs_sensor_desc& d) {
@@ -718,6 +720,7 @@ int upload_mfma_tables(const pwfs_sensor_desc& d, char* dst, hipStream_t st, std
     set_lds<1, false>();
     set_lds<2, false>();
     set_lds<2, true>();
+    set_lds<1, true>();
     lds_set = true;
   }
   return PWFS_OK;
@@ -727,6 +730,7 @@ int forward_mfma(const SensorPlan& sp, const float* opd, long long os, float* ou
                  void* scratch, hipStream_t st, Prof* prof) {
   const MGeom m = mgeom(sp.desc);
   if (sp.desc.precision == PWFS_BF16) return launch<1, false>(sp, m, opd, os, out, ost, nf, scratch, st, prof);
+  if (sp.desc.precision == PWFS_FP16) return launch<1, true>(sp, m, opd, os, out, ost, nf, scratch, st, prof);
   if (sp.desc.precision == PWFS_BF16X3) return launch<2, false>(sp, m, opd, os, out, ost, nf, scratch, st, prof);
   return launch<2, true>(sp, m, opd, os, out, ost, nf, scratch, st, prof);
 }

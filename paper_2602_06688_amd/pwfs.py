@@ -29,7 +29,7 @@ F_FULL_PLANE = 2
 F_LOCAL_NORM = 4
 F_DOUBLE_ROOF = 8
 
-FP32, BF16, BF16X3, FP16X3 = 0, 1, 2, 3
+FP32, BF16, BF16X3, FP16X3, FP16 = 0, 1, 2, 3, 4
 MAX_LAMBDA = 16
 
 

@@ -27,6 +27,7 @@ PREC_FP32 = 0
 PREC_BF16 = 1
 PREC_BF16X3 = 2
 PREC_FP16X3 = 3
+PREC_FP16 = 4
 
 
 @dataclass(frozen=True)
