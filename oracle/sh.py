@@ -86,3 +86,58 @@ def forward(opd_nm, D, n, M, rebin, obstruction, lambda_nm):
     """(detector pixels [F][n][n][M/rebin][M/rebin], slopes [F][2][n][n])."""
     pix = detector(spots(opd_nm, D, n, M, obstruction, lambda_nm), rebin)
     return pix, centroids(pix, valid_subapertures(D, n, obstruction))
+
+
+# ----------------------------------------------------------- polychromatic --
+# The paper lists a polychromatic Shack-Hartmann sensor (Table 4,
+# ``PolyChromSH``) without its equations.  Reading used here, the same as for
+# the polychromatic pyramid (a weighted sum of monochromatic sensors over the
+# sampled band):
+#   * the focal samples are fixed in angle: n_fft of them span the field that
+#     the pixelated pupil gives at the reference wavelength lambda_ref
+#     (lambda_ref b / d), so at a wavelength lambda the block is transformed
+#     at the frequencies (u - M/2 + 1/2) s / M cycles per pupil pixel,
+#     s = lambda_ref / lambda (s = 1: the monochromatic sensor);
+#   * lambda_ref may not exceed any sampled wavelength (s <= 1), so that the
+#     grid never reaches past one period of the pixel-sampled spectrum;
+#   * a sample stands for a fixed solid angle, so the intensity of wavelength
+#     lambda carries the factor s^2: |F|^2 s^2 / (M^2 sum A^2) (a flat frame's
+#     spots then hold the fraction of the light that falls on the grid);
+#   * the spot image is sum_lambda w_lambda spot_lambda.
+# A non-integer frequency scale has no FFT, so each block's transform is the
+# two matrix products of the definition, F = W E W^T with
+# W[u][x] = exp(-2 pi i (u - M/2 + 1/2)(x - (b-1)/2) s / M).
+
+def dft_matrix(b: int, M: int, s: float) -> np.ndarray:
+    """W [M][b] of the scaled half-integer-frequency transform."""
+    f = (np.arange(M) - M / 2.0 + 0.5) * s / M
+    c = np.arange(b) - (b - 1) / 2.0
+    return np.exp(-2j * np.pi * f[:, None] * c[None, :])
+
+
+def spots_poly(opd_nm: np.ndarray, D: int, n: int, M: int, obstruction: float, lambda_ref_nm: float,
+               lambdas_nm, weights) -> np.ndarray:
+    """Polychromatic spots [F][n][n][M][M] of OPD frames [F][D][D]."""
+    opd = np.asarray(opd_nm, np.float64)
+    if opd.ndim == 2:
+        opd = opd[None]
+    b = D // n
+    A = O.pupil_amplitude(D, obstruction)
+    sA2 = float((A * A).sum())
+    out = np.zeros((opd.shape[0], n, n, M, M))
+    for lam, w in zip(lambdas_nm, weights):
+        s = lambda_ref_nm / lam
+        W = dft_matrix(b, M, s)
+        for f in range(opd.shape[0]):
+            E = A * np.exp(1j * 2.0 * np.pi * opd[f] / lam)
+            for i in range(n):
+                for j in range(n):
+                    F = W @ E[i * b:(i + 1) * b, j * b:(j + 1) * b] @ W.T
+                    out[f, i, j] += w * (F.real ** 2 + F.imag ** 2) * (s * s) / (M * M * sA2)
+    return out
+
+
+def forward_poly(opd_nm, D, n, M, rebin, obstruction, lambda_ref_nm, lambdas_nm, weights):
+    """(detector pixels, slopes) of the polychromatic sensor."""
+    pix = detector(spots_poly(opd_nm, D, n, M, obstruction, lambda_ref_nm, lambdas_nm, weights), rebin)
+    return pix, centroids(pix, valid_subapertures(D, n, obstruction))

@@ -79,3 +79,59 @@ def test_scao_valid_count():
     # pupil's symmetry, so 314 is not reachable with it): within 1 %
     nv = SH.valid_subapertures(160, 20, 0.0).sum()
     assert nv == 316 and abs(nv / 314 - 1) < 0.01
+
+
+# ------------------------------------------------- polychromatic sensor ----
+
+def test_poly_at_the_reference_wavelength_is_the_fft_sensor():
+    """One wavelength equal to the reference (s = 1): the matrix products of
+    the definition reproduce the FFT-based monochromatic oracle."""
+    D, n, M = 24, 3, 20
+    rng = np.random.default_rng(21)
+    opd = rng.normal(0, 80.0, (2, D, D))
+    want = SH.spots(opd, D, n, M, 0.2, 700.0)
+    got = SH.spots_poly(opd, D, n, M, 0.2, 700.0, [700.0], [1.0])
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13 * want.max())
+
+
+def test_poly_is_the_weighted_sum_of_its_wavelengths():
+    D, n, M = 16, 2, 16
+    rng = np.random.default_rng(22)
+    opd = rng.normal(0, 60.0, (D, D))
+    lams, ws = [600.0, 750.0, 900.0], [0.2, 0.3, 0.5]
+    got = SH.spots_poly(opd, D, n, M, 0.0, 600.0, lams, ws)
+    parts = [SH.spots_poly(opd, D, n, M, 0.0, 600.0, [l], [1.0]) for l in lams]
+    np.testing.assert_allclose(got, sum(w * p for w, p in zip(ws, parts)), rtol=1e-12, atol=1e-16)
+
+
+def test_poly_centroid_is_achromatic():
+    """A pure tilt moves the spot by the same angle at every wavelength (the
+    phase gradient 2 pi t / lambda is sampled at frequencies scaled by
+    lambda_ref / lambda), so the centre of gravity agrees at 600, 750 and
+    900 nm to within the bias of the grid truncating each spot's wings (the
+    spot widens with lambda): 1.11, 1.13, 1.12 px against the geometric 1.2.
+    Frequencies left unscaled would give 1.2 x 600 / 900 = 0.8 px at 900 nm.
+    At the reference wavelength it equals the monochromatic sensor's."""
+    D, n, M, rebin = 32, 4, 32, 2
+    opd = tilt_opd(D, 0.6 * n, 0.0, 600.0)     # 0.6 lambda_ref / d of tip (0.6 n lambda_ref / D)
+    cents = []
+    for lam in (600.0, 750.0, 900.0):
+        pix, sl = SH.forward_poly(opd, D, n, M, rebin, 0.0, 600.0, [lam], [1.0])
+        cents.append(sl[0, 0][SH.valid_subapertures(D, n, 0.0)].mean())
+    _, sl_mono = SH.forward(opd, D, n, M, rebin, 0.0, 600.0)
+    assert abs(cents[0] - sl_mono[0, 0][SH.valid_subapertures(D, n, 0.0)].mean()) < 1e-12
+    assert 1.0 < cents[0] < 1.2
+    for c in cents[1:]:
+        assert abs(c / cents[0] - 1) < 2.5e-2
+
+
+def test_poly_flat_frame_keeps_the_light_on_the_grid():
+    """Flat wavefront: at the reference wavelength the spots hold all the
+    light (Parseval); at longer wavelengths the s^2 factor keeps each spot's
+    energy equal to the fraction that falls on the grid, just below 1 for a
+    grid that spans several diffraction widths."""
+    D, n, M = 32, 4, 64
+    opd = np.zeros((D, D))
+    for lam, lo in ((600.0, 1.0 - 1e-12), (900.0, 0.93)):
+        tot = SH.spots_poly(opd, D, n, M, 0.0, 600.0, [lam], [1.0]).sum()
+        assert lo <= tot <= 1.0 + 1e-12, (lam, tot)
