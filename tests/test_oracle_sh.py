@@ -135,3 +135,21 @@ def test_poly_flat_frame_keeps_the_light_on_the_grid():
     for lam, lo in ((600.0, 1.0 - 1e-12), (900.0, 0.93)):
         tot = SH.spots_poly(opd, D, n, M, 0.0, 600.0, [lam], [1.0]).sum()
         assert lo <= tot <= 1.0 + 1e-12, (lam, tot)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_poly_at_an_integer_fraction_is_the_centre_of_a_finer_fft_sensor(k):
+    """At s = 1/k (lambda = k lambda_ref) the frequencies (u - M/2 + 1/2) / (k M)
+    are those of the FFT sensor on k M samples at indices u + (k - 1) M / 2, and
+    s^2 / M^2 = 1 / (k M)^2: the scaled grid is exactly the central M x M block
+    of that finer sensor's spot (an FFT of a zero-padded block, a different
+    method), which pins the frequency scale, its sign and the s^2 factor."""
+    D, n, M = 24, 3, 12
+    rng = np.random.default_rng(30 + k)
+    opd = rng.normal(0, 90.0, (2, D, D))
+    lam = 600.0 * k
+    got = SH.spots_poly(opd, D, n, M, 0.15, 600.0, [lam], [1.0])
+    fine = SH.spots(opd, D, n, k * M, 0.15, lam)
+    o = (k - 1) * M // 2
+    want = fine[..., o:o + M, o:o + M]
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13 * want.max())
