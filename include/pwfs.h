@@ -385,6 +385,14 @@ int pwfs_gemv(const float* d_A, long long lda, const float* d_x, float* d_y, int
  * subaperture is valid when at least half of its pupil pixels are lit
  * (pupil pixel centres at i - (D-1)/2, lit for eps R <= r <= R); invalid
  * ones get zero slopes and pixels.
+ *
+ * Polychromatic sensor (Table 4: PolyChromSH), n_lambda >= 2: the spot image
+ * is sum_l w_l spot_l over the sampled wavelengths.  The focal samples are
+ * fixed in angle: the n_fft samples span the pixel-limited field at the
+ * reference wavelength lambda_nm, so at lambda_l the block is transformed at
+ * the frequencies (u - n_fft/2 + 1/2) s / n_fft with s = lambda_nm / lambda_l
+ * (<= 1: lambda_nm may not exceed any lambda_l), and spot_l carries s^2 for
+ * the fixed solid angle of a sample.
  * ------------------------------------------------------------------------ */
 
 typedef struct pwfs_sh_s* pwfs_sh_t;
@@ -394,10 +402,15 @@ typedef struct {
   int32_t n_subap;        /* subapertures across; b = D / n_subap <= 32         */
   int32_t n_fft;          /* focal samples per subaperture and axis, 2..512     */
   int32_t rebin;          /* focal samples per detector pixel; divides n_fft    */
-  int32_t reserved;       /* must be 0                                         */
+  int32_t n_lambda;       /* 0 or 1: monochromatic at lambda_nm; 2 ..
+                             PWFS_MAX_LAMBDA: polychromatic over lambdas_nm   */
   int32_t pad_;           /* must be 0                                         */
   double obstruction;     /* linear central obstruction ratio, [0, 1)          */
-  double lambda_nm;       /* wavelength, > 0                                   */
+  double lambda_nm;       /* wavelength (monochromatic), or the reference that
+                             fixes the angular sampling (polychromatic), > 0  */
+  double lambdas_nm[PWFS_MAX_LAMBDA];      /* polychromatic: >= lambda_nm      */
+  double lambda_weights[PWFS_MAX_LAMBDA];  /* polychromatic: >= 0, summing to 1
+                                              (to 1e-9)                        */
 } pwfs_sh_desc;
 
 /* Host-only check: PWFS_EINVAL for a malformed description,

@@ -15,6 +15,12 @@
 // M x M samples as two small products costs 2 b M (b + M) real multiply-adds
 // (per complex term 4): for b << M (8 vs 56, 7 vs 240) that is less than a
 // zero-padded M-point FFT, and it needs no radix plan for M = 56 or 240.
+//
+// Polychromatic sensor (Table 4: PolyChromSH): the workgroup runs the three
+// steps once per sampled wavelength lambda_l, with that wavelength's phase and
+// its table W_l (frequencies scaled by s = lambda_ref / lambda_l: the focal
+// samples are fixed in angle), and adds w_l s^2 |F_l|^2 / (M^2 sum A^2) into
+// the pixels in wavelength order before the centre of gravity.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,13 +54,13 @@ int sfail(int code, const char* fmt, ...) {
 struct ShArgs {
   const float* opd;        // [frames][D][D]
   const float* amp;        // [D][D]
-  const float2* W;         // [M][b]
+  const float2* W;         // [n_lam][M][b]
   const uint8_t* valid;    // [n][n]
   float* pixels;           // [frames][n][n][k][k] or nullptr
   float* slopes;           // [frames][2][n][n]
-  int D, n, b, M, r, k;
-  float norm;              // 1 / (M^2 sum A^2)
-  double two_pi_over_lam;
+  int D, n, b, M, r, k, n_lam;
+  float wnorm[PWFS_MAX_LAMBDA];             // w_l s_l^2 / (M^2 sum A^2) (monochromatic: 1 / (M^2 sum A^2))
+  double two_pi_over_lam[PWFS_MAX_LAMBDA];
 };
 
 // BB: the subaperture width b at compile time (its row of DFT coefficients
@@ -85,81 +91,85 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
   float* sP = (float*)(sT + b * M);    // [kk] pixel values, then [kShBlock] partials
   float* sR = sP + kk;
 
-  for (int i = tid; i < M * b; i += kShBlock) sW[i] = p.W[i];
   const float* opd = p.opd + (size_t)f * p.D * p.D;
-  for (int i = tid; i < b * b; i += kShBlock) {
-    const int y = i / b, x = i % b;
-    const size_t g = (size_t)(si * b + y) * p.D + sj * b + x;
-    const double ph = (double)opd[g] * p.two_pi_over_lam;
-    const double nn = rint(ph * 0.15915494309189533577);
-    const float rr = (float)fma(-nn, 6.283185307179586477, ph);
-    float sn, cs;
-    sincosf(rr, &sn, &cs);
-    const float a = p.amp[g];
-    sE[i] = make_float2(a * cs, a * sn);
-  }
-  __syncthreads();
-  // T[y][u] = sum_x E[y][x] W[u][x]
-  for (int i = tid; i < b * M; i += kShBlock) {
-    const int y = i / M, u = i % M;
-    float re = 0.f, im = 0.f;
-    for (int x = 0; x < b; ++x) {
-      const float2 e = sE[y * b + x], w = sW[u * b + x];
-      re = fmaf(e.x, w.x, fmaf(-e.y, w.y, re));
-      im = fmaf(e.x, w.y, fmaf(e.y, w.x, im));
+  // one pass per wavelength; the pixel loop's last barrier frees sW, sE and
+  // sT for the next one
+  for (int l = 0; l < p.n_lam; ++l) {
+    for (int i = tid; i < M * b; i += kShBlock) sW[i] = p.W[(size_t)l * M * b + i];
+    for (int i = tid; i < b * b; i += kShBlock) {
+      const int y = i / b, x = i % b;
+      const size_t g = (size_t)(si * b + y) * p.D + sj * b + x;
+      const double ph = (double)opd[g] * p.two_pi_over_lam[l];
+      const double nn = rint(ph * 0.15915494309189533577);
+      const float rr = (float)fma(-nn, 6.283185307179586477, ph);
+      float sn, cs;
+      sincosf(rr, &sn, &cs);
+      const float a = p.amp[g];
+      sE[i] = make_float2(a * cs, a * sn);
     }
-    sT[i] = make_float2(re, im);
-  }
-  __syncthreads();
-  // pixels: TPP threads per pixel share its r rows of focal samples (fixed order)
-  int tpp = 1;
-  while (tpp * 2 * kk <= kShBlock && tpp * 2 <= r) tpp *= 2;
-  for (int base = 0; base < kk * tpp; base += kShBlock) {
-    const int slot = base + tid;
-    const int P = slot / tpp, s = slot % tpp;
-    float acc = 0.f;
-    if (P < kk) {
-      const int pr = P / k, pc = P % k;
-      for (int vv = s; vv < r; vv += tpp) {
-        const int v = pr * r + vv;
-        if constexpr (BB > 0) {
-          float2 wv[BB];
-#pragma unroll
-          for (int y = 0; y < BB; ++y) wv[y] = sW[v * BB + y];
-          for (int uu = 0; uu < r; ++uu) {
-            const int u = pc * r + uu;
-            float re = 0.f, im = 0.f;
-#pragma unroll
-            for (int y = 0; y < BB; ++y) {
-              const float2 t = sT[y * M + u];
-              re = fmaf(wv[y].x, t.x, fmaf(-wv[y].y, t.y, re));
-              im = fmaf(wv[y].x, t.y, fmaf(wv[y].y, t.x, im));
+    __syncthreads();
+    // T[y][u] = sum_x E[y][x] W[u][x]
+    for (int i = tid; i < b * M; i += kShBlock) {
+      const int y = i / M, u = i % M;
+      float re = 0.f, im = 0.f;
+      for (int x = 0; x < b; ++x) {
+        const float2 e = sE[y * b + x], w = sW[u * b + x];
+        re = fmaf(e.x, w.x, fmaf(-e.y, w.y, re));
+        im = fmaf(e.x, w.y, fmaf(e.y, w.x, im));
+      }
+      sT[i] = make_float2(re, im);
+    }
+    __syncthreads();
+    // pixels: TPP threads per pixel share its r rows of focal samples (fixed order)
+    int tpp = 1;
+    while (tpp * 2 * kk <= kShBlock && tpp * 2 <= r) tpp *= 2;
+    for (int base = 0; base < kk * tpp; base += kShBlock) {
+      const int slot = base + tid;
+      const int P = slot / tpp, s = slot % tpp;
+      float acc = 0.f;
+      if (P < kk) {
+        const int pr = P / k, pc = P % k;
+        for (int vv = s; vv < r; vv += tpp) {
+          const int v = pr * r + vv;
+          if constexpr (BB > 0) {
+            float2 wv[BB];
+  #pragma unroll
+            for (int y = 0; y < BB; ++y) wv[y] = sW[v * BB + y];
+            for (int uu = 0; uu < r; ++uu) {
+              const int u = pc * r + uu;
+              float re = 0.f, im = 0.f;
+  #pragma unroll
+              for (int y = 0; y < BB; ++y) {
+                const float2 t = sT[y * M + u];
+                re = fmaf(wv[y].x, t.x, fmaf(-wv[y].y, t.y, re));
+                im = fmaf(wv[y].x, t.y, fmaf(wv[y].y, t.x, im));
+              }
+              acc = fmaf(re, re, fmaf(im, im, acc));
             }
-            acc = fmaf(re, re, fmaf(im, im, acc));
-          }
-        } else {
-          for (int uu = 0; uu < r; ++uu) {
-            const int u = pc * r + uu;
-            float re = 0.f, im = 0.f;
-            for (int y = 0; y < b; ++y) {
-              const float2 w = sW[v * b + y], t = sT[y * M + u];
-              re = fmaf(w.x, t.x, fmaf(-w.y, t.y, re));
-              im = fmaf(w.x, t.y, fmaf(w.y, t.x, im));
+          } else {
+            for (int uu = 0; uu < r; ++uu) {
+              const int u = pc * r + uu;
+              float re = 0.f, im = 0.f;
+              for (int y = 0; y < b; ++y) {
+                const float2 w = sW[v * b + y], t = sT[y * M + u];
+                re = fmaf(w.x, t.x, fmaf(-w.y, t.y, re));
+                im = fmaf(w.x, t.y, fmaf(w.y, t.x, im));
+              }
+              acc = fmaf(re, re, fmaf(im, im, acc));
             }
-            acc = fmaf(re, re, fmaf(im, im, acc));
           }
         }
       }
+      sR[tid] = acc;
+      __syncthreads();
+      if (s == 0 && P < kk) {
+        float v = sR[tid];
+        for (int q = 1; q < tpp; ++q) v += sR[tid + q];
+        sP[P] = (l == 0 ? 0.f : sP[P]) + v * p.wnorm[l];
+      }
+      __syncthreads();
     }
-    sR[tid] = acc;
-    __syncthreads();
-    if (s == 0 && P < kk) {
-      float v = sR[tid];
-      for (int q = 1; q < tpp; ++q) v += sR[tid + q];
-      sP[P] = v * p.norm;
-    }
-    __syncthreads();
-  }
+  }   // wavelengths
   // centre of gravity: the first wavefront sums the pixels lane-strided,
   // then a fixed butterfly of cross-lane adds (no workgroup barriers)
   if (tid >= 64) return;
@@ -193,8 +203,9 @@ using namespace pwfs;
 
 struct pwfs_sh_s {
   pwfs_sh_desc d;
-  int D, n, b, M, r, k, max_frames, n_valid;
-  float norm;
+  int D, n, b, M, r, k, max_frames, n_valid, n_lam;
+  float wnorm[PWFS_MAX_LAMBDA];
+  double two_pi_over_lam[PWFS_MAX_LAMBDA];
   float* amp = nullptr;
   float2* W = nullptr;
   uint8_t* valid = nullptr;
@@ -203,7 +214,9 @@ struct pwfs_sh_s {
 
 extern "C" int pwfs_sh_validate(const pwfs_sh_desc* d) {
   if (!d) return sfail(PWFS_EINVAL, "NULL description");
-  if (d->reserved != 0 || d->pad_ != 0) return sfail(PWFS_EINVAL, "reserved fields must be 0");
+  if (d->pad_ != 0) return sfail(PWFS_EINVAL, "reserved fields must be 0");
+  if (d->n_lambda < 0 || d->n_lambda > PWFS_MAX_LAMBDA)
+    return sfail(PWFS_EINVAL, "n_lambda must be in [0, %d]", PWFS_MAX_LAMBDA);
   if (d->n_pupil < 2 || d->n_subap < 1 || d->n_pupil % d->n_subap)
     return sfail(PWFS_EINVAL, "n_pupil must be a positive multiple of n_subap");
   const int b = d->n_pupil / d->n_subap;
@@ -212,6 +225,16 @@ extern "C" int pwfs_sh_validate(const pwfs_sh_desc* d) {
   if (d->rebin < 1 || d->n_fft % d->rebin) return sfail(PWFS_EINVAL, "rebin must divide n_fft");
   if (!(d->obstruction >= 0.0 && d->obstruction < 1.0)) return sfail(PWFS_EINVAL, "obstruction must be in [0, 1)");
   if (!(d->lambda_nm > 0.0) || !std::isfinite(d->lambda_nm)) return sfail(PWFS_EINVAL, "lambda_nm must be > 0");
+  if (d->n_lambda >= 2) {
+    double wsum = 0.0;
+    for (int l = 0; l < d->n_lambda; ++l) {
+      if (!(d->lambdas_nm[l] >= d->lambda_nm) || !std::isfinite(d->lambdas_nm[l]))
+        return sfail(PWFS_EINVAL, "lambdas_nm[%d] must be finite and >= lambda_nm (the reference)", l);
+      if (!(d->lambda_weights[l] >= 0.0)) return sfail(PWFS_EINVAL, "lambda_weights[%d] must be >= 0", l);
+      wsum += d->lambda_weights[l];
+    }
+    if (std::fabs(wsum - 1.0) > 1e-9) return sfail(PWFS_EINVAL, "lambda_weights must sum to 1");
+  }
   const int k = d->n_fft / d->rebin;
   const size_t lds = sizeof(float2) * ((size_t)d->n_fft * b * 2 + (size_t)b * b) + sizeof(float) * ((size_t)k * k + kShBlock);
   if (lds > 150 * 1024) return sfail(PWFS_EUNSUPPORTED, "subaperture tables exceed the LDS (n_fft x b too large)");
@@ -223,7 +246,8 @@ extern "C" int pwfs_sh_workspace_size(const pwfs_sh_desc* d, int max_frames, siz
   if (rc) return rc;
   if (!bytes || max_frames < 1) return sfail(PWFS_EINVAL, "bad arguments");
   const int D = d->n_pupil, n = d->n_subap, b = D / n;
-  *bytes = a256(sizeof(float) * D * D) + a256(sizeof(float2) * d->n_fft * b) + a256((size_t)n * n);
+  const int nl = d->n_lambda >= 2 ? d->n_lambda : 1;
+  *bytes = a256(sizeof(float) * D * D) + a256(sizeof(float2) * nl * d->n_fft * b) + a256((size_t)n * n);
   return PWFS_OK;
 }
 
@@ -257,12 +281,21 @@ extern "C" int pwfs_sh_plan(const pwfs_sh_desc* d, int max_frames, void* ws, siz
       nv += V[(size_t)i * n + j];
     }
   if (nv == 0) return sfail(PWFS_EINVAL, "no valid subaperture");
-  std::vector<float2> W((size_t)M * b);
-  for (int u = 0; u < M; ++u)
-    for (int x = 0; x < b; ++x) {
-      const double a = -2.0 * kPiSh * (u - M / 2.0 + 0.5) * (x - (b - 1) / 2.0) / M;
-      W[(size_t)u * b + x] = make_float2((float)std::cos(a), (float)std::sin(a));
-    }
+  // per wavelength: W_l[u][x] with the frequency scale s_l = lambda_ref / lambda_l
+  const int nl = d->n_lambda >= 2 ? d->n_lambda : 1;
+  std::vector<float2> W((size_t)nl * M * b);
+  std::vector<double> scale(nl, 1.0), lam(nl, d->lambda_nm), wgt(nl, 1.0);
+  for (int l = 0; l < nl && d->n_lambda >= 2; ++l) {
+    lam[l] = d->lambdas_nm[l];
+    wgt[l] = d->lambda_weights[l];
+    scale[l] = d->lambda_nm / d->lambdas_nm[l];
+  }
+  for (int l = 0; l < nl; ++l)
+    for (int u = 0; u < M; ++u)
+      for (int x = 0; x < b; ++x) {
+        const double a = -2.0 * kPiSh * (u - M / 2.0 + 0.5) * (x - (b - 1) / 2.0) * scale[l] / M;
+        W[((size_t)l * M + u) * b + x] = make_float2((float)std::cos(a), (float)std::sin(a));
+      }
   pwfs_sh_s* s = new (std::nothrow) pwfs_sh_s();
   if (!s) return sfail(PWFS_EINVAL, "out of host memory");
   s->d = *d;
@@ -274,12 +307,16 @@ extern "C" int pwfs_sh_plan(const pwfs_sh_desc* d, int max_frames, void* ws, siz
   s->k = M / d->rebin;
   s->max_frames = max_frames;
   s->n_valid = nv;
-  s->norm = (float)(1.0 / ((double)M * M * sA2));
+  s->n_lam = nl;
+  for (int l = 0; l < nl; ++l) {
+    s->wnorm[l] = (float)(wgt[l] * scale[l] * scale[l] / ((double)M * M * sA2));
+    s->two_pi_over_lam[l] = 2.0 * kPiSh / lam[l];
+  }
   char* p = (char*)ws;
   s->amp = (float*)p;
   p += a256(sizeof(float) * D * D);
   s->W = (float2*)p;
-  p += a256(sizeof(float2) * M * b);
+  p += a256(sizeof(float2) * nl * M * b);
   s->valid = (uint8_t*)p;
   s->lds = sizeof(float2) * ((size_t)M * b * 2 + (size_t)b * b) + sizeof(float) * ((size_t)s->k * s->k + kShBlock);
   hipStream_t st = (hipStream_t)stream;
@@ -320,8 +357,11 @@ extern "C" int pwfs_sh_forward(pwfs_sh_t s, const float* opd, int nf, float* pix
   a.M = s->M;
   a.r = s->r;
   a.k = s->k;
-  a.norm = s->norm;
-  a.two_pi_over_lam = 2.0 * kPiSh / s->d.lambda_nm;
+  a.n_lam = s->n_lam;
+  for (int l = 0; l < s->n_lam; ++l) {
+    a.wnorm[l] = s->wnorm[l];
+    a.two_pi_over_lam[l] = s->two_pi_over_lam[l];
+  }
   const unsigned grid = (unsigned)((long long)nf * s->n * s->n);
   hipStream_t st = (hipStream_t)stream;
   switch (s->b) {

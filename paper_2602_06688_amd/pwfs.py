@@ -85,8 +85,9 @@ class CCcdDesc(ctypes.Structure):
 
 class CShDesc(ctypes.Structure):
     _fields_ = [("n_pupil", ctypes.c_int32), ("n_subap", ctypes.c_int32), ("n_fft", ctypes.c_int32),
-                ("rebin", ctypes.c_int32), ("reserved", ctypes.c_int32), ("pad_", ctypes.c_int32),
-                ("obstruction", ctypes.c_double), ("lambda_nm", ctypes.c_double)]
+                ("rebin", ctypes.c_int32), ("n_lambda", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("obstruction", ctypes.c_double), ("lambda_nm", ctypes.c_double),
+                ("lambdas_nm", ctypes.c_double * MAX_LAMBDA), ("lambda_weights", ctypes.c_double * MAX_LAMBDA)]
 
 
 class CLayer(ctypes.Structure):
@@ -536,8 +537,16 @@ def row_rms(x, out=None, stream=None):
 
 
 def sh_desc(n_pupil: int, n_subap: int, n_fft: int, rebin: int, obstruction: float = 0.0,
-            lambda_nm: float = 750.0) -> CShDesc:
-    return CShDesc(int(n_pupil), int(n_subap), int(n_fft), int(rebin), 0, 0, float(obstruction), float(lambda_nm))
+            lambda_nm: float = 750.0, lambdas_nm=None, lambda_weights=None) -> CShDesc:
+    """Monochromatic at lambda_nm, or polychromatic over lambdas_nm with
+    lambda_nm the reference that fixes the angular sampling."""
+    d = CShDesc(int(n_pupil), int(n_subap), int(n_fft), int(rebin), 0, 0, float(obstruction), float(lambda_nm))
+    if lambdas_nm is not None:
+        d.n_lambda = len(lambdas_nm)
+        for i, (lam, w) in enumerate(list(zip(lambdas_nm, lambda_weights))[:MAX_LAMBDA]):   # the library checks the count
+            d.lambdas_nm[i] = float(lam)
+            d.lambda_weights[i] = float(w)
+    return d
 
 
 class SH:

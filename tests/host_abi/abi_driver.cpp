@@ -145,8 +145,15 @@ void run_plan(const pwfs_sensor_desc* d, int n, int frames, const char* label) {
 }
 
 void run_sh() {
-  const pwfs_sh_desc cases[] = {{160, 20, 56, 7, 0, 0, 0.0, 750.0}, {476, 68, 240, 15, 0, 0, 0.28, 750.0},
-                                {64, 8, 16, 2, 0, 0, 0.1, 600.0}};
+  pwfs_sh_desc poly = {64, 8, 16, 2, 3, 0, 0.1, 600.0, {}, {}};
+  const double lams[3] = {600.0, 750.0, 900.0}, ws3[3] = {0.25, 0.25, 0.5};
+  for (int l = 0; l < 3; ++l) {
+    poly.lambdas_nm[l] = lams[l];
+    poly.lambda_weights[l] = ws3[l];
+  }
+  const pwfs_sh_desc cases[] = {{160, 20, 56, 7, 0, 0, 0.0, 750.0, {}, {}},
+                                {476, 68, 240, 15, 0, 0, 0.28, 750.0, {}, {}},
+                                {64, 8, 16, 2, 0, 0, 0.1, 600.0, {}, {}}, poly};
   for (const auto& sh : cases) {
     EXPECT(pwfs_sh_validate(&sh) == PWFS_OK);
     size_t bytes = 0;
@@ -167,7 +174,16 @@ void run_sh() {
   bad.rebin = 5;  // does not divide 56
   EXPECT(pwfs_sh_validate(&bad) == PWFS_EINVAL);
   bad = cases[0];
-  bad.reserved = 1;
+  bad.pad_ = 1;
+  EXPECT(pwfs_sh_validate(&bad) == PWFS_EINVAL);
+  bad = poly;
+  bad.n_lambda = PWFS_MAX_LAMBDA + 1;
+  EXPECT(pwfs_sh_validate(&bad) == PWFS_EINVAL);
+  bad = poly;
+  bad.lambdas_nm[0] = 500.0;   // below the reference
+  EXPECT(pwfs_sh_validate(&bad) == PWFS_EINVAL);
+  bad = poly;
+  bad.lambda_weights[2] = 0.4;   // weights sum to 0.9
   EXPECT(pwfs_sh_validate(&bad) == PWFS_EINVAL);
   printf("  shack-hartmann: ok\n");
 }

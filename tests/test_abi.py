@@ -138,6 +138,9 @@ def test_ctypes_structs_match_header_layout(tmp_path):
     (dict(obstruction=1.0), P.PWFS_EINVAL),
     (dict(lambda_nm=0.0), P.PWFS_EINVAL),
     (dict(n_pupil=512, n_subap=16, n_fft=512, rebin=8), P.PWFS_EUNSUPPORTED),   # tables beyond the LDS
+    (dict(lambdas_nm=[700.0, 800.0], lambda_weights=[0.5, 0.5]), P.PWFS_EINVAL),  # below the 750 nm reference
+    (dict(lambdas_nm=[750.0, 800.0], lambda_weights=[0.5, 0.6]), P.PWFS_EINVAL),  # weights sum to 1.1
+    (dict(lambdas_nm=[750.0] * 17, lambda_weights=[1 / 17] * 17), P.PWFS_EINVAL),  # more than 16
 ])
 def test_sh_validate_rejects(kw, code):
     base = dict(n_pupil=160, n_subap=20, n_fft=56, rebin=7, obstruction=0.0, lambda_nm=750.0)

@@ -84,3 +84,65 @@ def test_errors():
     with pytest.raises(P.PwfsError) as e:
         sh.forward(torch.zeros((3, 160, 160), device="cuda"))
     assert e.value.code == P.PWFS_ESTATE
+
+
+# ------------------------------------------------- polychromatic sensor ----
+
+def _compare_poly(D, n, M, r, ob, lam_ref, lams, ws, opd, label, frames=None):
+    P = _P()
+    F = opd.shape[0]
+    print(f"[gpu] sh poly {label}: D={D} n={n} M={M} rebin={r} lambdas={lams} F={F}", flush=True)
+    sh = P.SH(P.sh_desc(D, n, M, r, ob, lam_ref, lambdas_nm=lams, lambda_weights=ws), max_frames=F)
+    x = torch.from_numpy(np.ascontiguousarray(opd, np.float32)).cuda()
+    sl, pix = sh.forward(x, want_pixels=True)
+    torch.cuda.synchronize()
+    idx = list(range(F)) if frames is None else frames
+    want_pix, want_sl = SH.forward_poly(opd[idx].astype(np.float32).astype(np.float64), D, n, M, r, ob, lam_ref,
+                                        lams, ws)
+    gp = pix.cpu().numpy()[idx]
+    gs = sl.cpu().numpy()[idx]
+    valid = SH.valid_subapertures(D, n, ob)
+    assert (gp[:, ~valid] == 0).all()
+    pe = np.abs(gp[:, valid] - want_pix[:, valid]).max() / np.abs(want_pix[:, valid]).max()
+    se = np.abs(gs - want_sl).max()
+    print(f"      pixels max rel {pe:.2e}, slopes max abs {se:.2e} px", flush=True)
+    assert pe < 1e-5
+    assert se < 1e-5
+    return sl, pix
+
+
+@pytest.mark.parametrize("D,n,M,r,ob", [
+    (40, 5, 32, 4, 0.3),     # b = 8
+    (28, 4, 60, 15, 0.1),    # b = 7, 15 x 15 samples per pixel
+    (20, 4, 20, 4, 0.0),     # b = 5: run-time width
+])
+def test_polychromatic_small_sensors_match_oracle(D, n, M, r, ob):
+    """Three wavelengths (600, 750, 900 nm; the grid fixed at 600 nm) against
+    the oracle's weighted sum of scaled-frequency transforms."""
+    opd = von_karman_opd(2, D, 2.0, 0.3, 25.0, seed=D + M)
+    _compare_poly(D, n, M, r, ob, 600.0, [600.0, 750.0, 900.0], [0.25, 0.25, 0.5], opd, "small")
+
+
+def test_polychromatic_scao_shape_sampled_frames():
+    """The SCAO SH shape over the 600-900 nm band (the heterogeneous pyramid
+    batch's band) on sampled frames of a 200-frame launch."""
+    w = workload("cfg2")
+    opd = workload_opd(w, frames=range(200))
+    _compare_poly(160, 20, 56, 7, 0.0, 600.0, [600.0, 750.0, 900.0], [1 / 3, 1 / 3, 1 / 3], opd, "SCAO band",
+                  frames=[0, 199])
+
+
+def test_polychromatic_split_reference_line_is_the_monochromatic_sensor():
+    """Two halves of weight at the reference wavelength: each pass adds
+    0.5 x (the monochromatic value), exactly, so pixels and slopes are the
+    monochromatic sensor's bits."""
+    P = _P()
+    opd = von_karman_opd(2, 40, 2.0, 0.3, 25.0, seed=9)
+    x = torch.from_numpy(np.ascontiguousarray(opd, np.float32)).cuda()
+    mono = P.SH(P.sh_desc(40, 5, 32, 4, 0.3, 750.0), max_frames=2)
+    poly = P.SH(P.sh_desc(40, 5, 32, 4, 0.3, 750.0, lambdas_nm=[750.0, 750.0], lambda_weights=[0.5, 0.5]),
+                max_frames=2)
+    s0, p0 = mono.forward(x, want_pixels=True)
+    s1, p1 = poly.forward(x, want_pixels=True)
+    torch.cuda.synchronize()
+    assert torch.equal(p0, p1) and torch.equal(s0, s1)
