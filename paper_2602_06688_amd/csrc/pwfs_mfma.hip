@@ -193,102 +193,6 @@ struct G2Args {
   float scale[PWFS_MAX_LAMBDA];
 };
 
-// Wave-specialised stages (one workgroup per CU).  The consumer waves (2 x
-// BN/64 of them, each a 64 x 64 quarter of a 128 x BN tile) run the MFMAs
-// and the epilogue, reading each K step from one of two LDS stages.  Four producer waves only move operands: every producer
-// lane owns CH 16-byte chunks of a K step and keeps DEPTH steps of them in
-// flight in registers; at each step it stores the oldest into the stage the
-// consumers read next and issues the loads of the step DEPTH further on.  A
-// step's loads thus have DEPTH steps of matrix work to arrive (a 256-lane
-// workgroup whose waves both fetch and compute could keep only one step in
-// flight within its registers).  The two roles live in separate loops, so their
-// registers are not held at the same time; both pass the same workgroup
-// barriers, one per K step.  A wider tile (BN = 256) reads each row of A
-// once for twice the columns.
-// The one-term form runs K steps of 64 (16 products per consumer wave
-// between barriers), the split forms K steps of 32 (their three products
-// already give 24).
-template <int NPL, bool F16, int BN>
-using WsEngine = MfmaTile<NPL, F16, NPL == 1 ? 64 : 32, BN>;
-
-// Chunk layout of one K step for the producers: part h (lane pt moves chunk
-// pt + 256 h) covers RPP whole rows of one plane block of A or of B.
-template <class E, int BN>
-struct WsParts {
-  static constexpr int NPL = E::NPL_;
-  static constexpr int CPR = E::BK_ / 8;                   // 16-byte chunks per row and step
-  static constexpr int ROWS = NPL * (kGemmTile + BN);      // A planes, then B planes
-  static constexpr int RPP = 256 / CPR;                    // rows per part
-  static constexpr int CH = ROWS / RPP;                    // parts
-  static_assert(CH * RPP == ROWS && kGemmTile % RPP == 0 && BN % RPP == 0,
-                "each producer part lies in one plane block of A or B");
-  static_assert(CPR != 4 || RPP == 64, "the row order of a part covers 64 rows");
-  // plane block of part h: A planes 0..NPL-1, then B planes (compile-time per h)
-  static constexpr bool is_a(int h) { return h * RPP < NPL * kGemmTile; }
-  static constexpr int plane(int h) { return is_a(h) ? h * RPP / kGemmTile : (h * RPP - NPL * kGemmTile) / BN; }
-  // Stage row and K offset of lane pt's chunk in part h.  Four consecutive
-  // lanes move the four chunks (64 contiguous bytes) of one row.  With K
-  // steps of 32 the padded rows are 80 bytes (5 16-byte bank quads) apart,
-  // so the 32 lanes of one store are given the rows a + 4m, m = 0..7: their
-  // chunks then fill distinct quads of the 512 bytes of LDS banks (and so of
-  // each 256-byte half), where eight consecutive rows would overlap.
-  __device__ static int stage_row(int pt, int h) {
-    if constexpr (CPR == 4) {
-      const int grp = pt >> 5, w = pt & 31;
-      return h * RPP + ((grp >> 2) << 5) + (grp & 3) + 4 * (w >> 2);
-    } else {
-      return (pt + 256 * h) / CPR;
-    }
-  }
-  __device__ static int kq(int pt, int h) {
-    if constexpr (CPR == 4) return (pt & 3) * 8;
-    else return ((pt + 256 * h) % CPR) * 8;
-  }
-  // tile row of the chunk within its operand
-  __device__ static int row(int pt, int h) {
-    const int rr = stage_row(pt, h);
-    return is_a(h) ? rr % kGemmTile : (rr - NPL * kGemmTile) % BN;
-  }
-  __device__ static int lds_offset(int pt, int h) { return E::slot(stage_row(pt, h), kq(pt, h)); }
-};
-
-// The producer loop.  fetch(buf, s) issues the loads of step s into buf;
-// every fetch is issued unconditionally (steps past the end re-load the last
-// step, unused), so the compiler's in-order load counter sees the same DEPTH
-// sets in flight on every path and waits only for the oldest.
-template <class E, int DEPTH, int CH, class Fetch>
-__device__ __forceinline__ void ws_produce(uint16_t* lds, const int (&loff)[CH], int steps, Fetch fetch) {
-  u32x4_t buf[DEPTH][CH];
-  auto stash = [&](const u32x4_t (&b)[CH], uint16_t* stage) {
-#pragma unroll
-    for (int h = 0; h < CH; ++h) *(u32x4_t*)(stage + loff[h]) = b[h];
-  };
-#pragma unroll
-  for (int u = 0; u < DEPTH; ++u) fetch(buf[u], min(u, steps - 1));
-  stash(buf[0], lds);
-  fetch(buf[0], min(DEPTH, steps - 1));
-  __syncthreads();
-  int st = 0;
-  for (; st + DEPTH <= steps; st += DEPTH) {
-#pragma unroll
-    for (int u = 0; u < DEPTH; ++u) {
-      // step st + u + 1 waits in buf[(u + 1) % DEPTH]: it goes to the stage
-      // the consumers read after this barrier, and the buffer takes the step
-      // DEPTH further on
-      stash(buf[(u + 1) % DEPTH], lds + ((st + u + 1) & 1) * E::STAGE);
-      fetch(buf[(u + 1) % DEPTH], min(st + u + 1 + DEPTH, steps - 1));
-      __syncthreads();
-    }
-  }
-  // the last steps (fewer than DEPTH) are already in flight
-#pragma unroll
-  for (int u = 0; u < DEPTH - 1; ++u) {
-    if (st + u >= steps) break;
-    if (st + u + 1 < steps) stash(buf[(u + 1) % DEPTH], lds + ((st + u + 1) & 1) * E::STAGE);
-    __syncthreads();
-  }
-}
-
 // Stage 2: columns of C run over all frames of the pass (n = f Nc + c), so a
 // tile may straddle two frames and only the pass's last tile is ragged.  The
 // n_lam x n_mod products of one tile form one stream of K steps, and a

@@ -92,6 +92,40 @@ __device__ __forceinline__ void put16(uint16_t* base, long long plane, long long
   }
 }
 
+// the epilogue of one output element (m, n) of a product whose accumulated
+// value is v; lsum collects the squared error (E_OUTPUT with a target)
+template <int EPI>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& p, int m, int n, float v, double& lsum) {
+  if constexpr (EPI == E_STORE) {
+    float* cp = p.c + (long long)m * p.ldc + n;
+    *cp = (p.beta != 0.f) ? p.alpha * v + p.beta * *cp : p.alpha * v;
+  } else if constexpr (EPI == E_HIDDEN) {
+    const float zz = v + p.bias[n];
+    const float hv = gelu_f(zz);
+    put16(p.h, p.h_plane, (long long)m * p.ldh + n, hv, p.planes_out);
+    // the pre-activation and the transposed copy serve the backward
+    // pass only (absent in inference)
+    if (p.z) p.z[(long long)m * p.ldz + n] = zz;
+    if (p.ht) put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, hv, p.planes_out);
+  } else if constexpr (EPI == E_OUTPUT) {
+    const float y = v + p.bias[n];
+    if (p.c) p.c[(long long)m * p.ldc + n] = p.alpha * y;
+    if (p.target) {
+      const float d = y - p.target[(long long)m * p.ldt + n] * p.tscale;
+      lsum += (double)d * d;
+      const float g = p.gscale * d;
+      p.z[(long long)m * p.ldz + n] = g;
+      put16(p.h, p.h_plane, (long long)m * p.ldh + n, g, p.planes_out);
+      put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, g, p.planes_out);
+    }
+  } else {  // E_DHIDDEN
+    const float g = v * gelu_grad_f(p.zprev[(long long)m * p.ldzp + n]);
+    p.z[(long long)m * p.ldz + n] = g;
+    put16(p.h, p.h_plane, (long long)m * p.ldh + n, g, p.planes_out);
+    put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, g, p.planes_out);
+  }
+}
+
 template <int NPL, int EPI, int BK>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
   extern __shared__ u32x4_t lds_raw[];
@@ -130,35 +164,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
         E::coord(tid, i, j, e, row, col);
         const int m = m0 + row, n = n0 + col;
         if (m >= p.M || n >= p.N) continue;
-        const float v = eng.value(i, j, e);
-        if constexpr (EPI == E_STORE) {
-          float* cp = p.c + (long long)m * p.ldc + n;
-          *cp = (p.beta != 0.f) ? p.alpha * v + p.beta * *cp : p.alpha * v;
-        } else if constexpr (EPI == E_HIDDEN) {
-          const float zz = v + p.bias[n];
-          const float hv = gelu_f(zz);
-          put16(p.h, p.h_plane, (long long)m * p.ldh + n, hv, p.planes_out);
-          // the pre-activation and the transposed copy serve the backward
-          // pass only (absent in inference)
-          if (p.z) p.z[(long long)m * p.ldz + n] = zz;
-          if (p.ht) put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, hv, p.planes_out);
-        } else if constexpr (EPI == E_OUTPUT) {
-          const float y = v + p.bias[n];
-          if (p.c) p.c[(long long)m * p.ldc + n] = p.alpha * y;
-          if (p.target) {
-            const float d = y - p.target[(long long)m * p.ldt + n] * p.tscale;
-            lsum += (double)d * d;
-            const float g = p.gscale * d;
-            p.z[(long long)m * p.ldz + n] = g;
-            put16(p.h, p.h_plane, (long long)m * p.ldh + n, g, p.planes_out);
-            put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, g, p.planes_out);
-          }
-        } else {  // E_DHIDDEN
-          const float g = v * gelu_grad_f(p.zprev[(long long)m * p.ldzp + n]);
-          p.z[(long long)m * p.ldz + n] = g;
-          put16(p.h, p.h_plane, (long long)m * p.ldh + n, g, p.planes_out);
-          put16(p.ht, p.ht_plane, (long long)n * p.ldht + m, g, p.planes_out);
-        }
+        gemm_epilogue<EPI>(p, m, n, eng.value(i, j, e), lsum);
       }
   if constexpr (EPI == E_OUTPUT) {
     if (p.loss_part) {
@@ -172,6 +178,84 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
       if (tid == 0) p.loss_part[blockIdx.x] = red[0];
     }
   }
+}
+
+// Large one-plane products (inference passes of the network, big plain
+// GEMMs): the wave-specialised workgroup of mfma_gemm.hpp, a 128 x BN tile
+// per workgroup with two K steps of operands in flight.  The K segments run
+// as one stream of steps (the second segment's after the first's), and the
+// consumers' products are those of k_gemm in the same order, so both give
+// the same bits.  No loss partials (the product has no target).
+constexpr int kGemmWsDepth = 2;
+
+template <int EPI, int BN>
+__global__ __launch_bounds__(64 * (2 * BN / 64 + 4)) void k_gemm_ws(GemmArgs p) {
+  extern __shared__ u32x4_t lds_raw[];
+  uint16_t* lds = (uint16_t*)lds_raw;
+  using E = WsEngine<1, false, BN>;
+  using W = WsParts<E, BN>;
+  constexpr int NC = 2 * BN / 64, BK = E::BK_, CH = W::CH;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nt = blockIdx.x % p.ntiles;
+  const int mt = blockIdx.x / p.ntiles;
+  const int m0 = mt * kGemmTile, n0 = nt * BN;
+  const int nk1 = p.K / BK;
+  const int steps = nk1 + p.K2 / BK;
+
+  if (wave >= NC) {
+    const int pt = tid - 64 * NC;
+    long long off1[CH], off2[CH];   // element offset of chunk h in segment 1 and 2 (K step 0)
+    int loff[CH];
+#pragma unroll
+    for (int h = 0; h < CH; ++h) {
+      const int row = W::row(pt, h), kq = W::kq(pt, h);
+      if (W::is_a(h)) {
+        const long long r = min(m0 + row, p.M - 1);
+        off1[h] = r * p.lda + kq;
+        off2[h] = r * p.lda2 + kq;
+      } else {
+        const long long r = min(n0 + row, p.N - 1);
+        off1[h] = r * p.ldb + kq;
+        off2[h] = r * p.ldb2 + kq;
+      }
+      loff[h] = W::lds_offset(pt, h);
+    }
+    ws_produce<E, kGemmWsDepth>(lds, loff, steps, [&](u32x4_t (&b)[CH], int s) {
+      const bool seg2 = s >= nk1;
+      const long long k0 = (long long)(seg2 ? s - nk1 : s) * BK;
+      const uint16_t* A = seg2 ? p.a2 : p.a;
+      const uint16_t* B = seg2 ? p.b2 : p.b;
+#pragma unroll
+      for (int h = 0; h < CH; ++h)
+        b[h] = *(const u32x4_t*)((W::is_a(h) ? A : B) + (seg2 ? off2[h] : off1[h]) + k0);
+    });
+    return;
+  }
+
+  // -------------------------------------------------------------- consumer
+  const int lane = tid & 63;
+  const int wm = wave & 1, wn = wave >> 1;
+  E eng;
+  eng.zero();
+  __syncthreads();
+  for (int st = 0; st < steps; ++st) {
+    eng.compute(lds + (st & 1) * E::STAGE, wm, wn, lane);
+    __syncthreads();
+  }
+  double lsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        // accumulator layout of the 32 x 32 tile (i, j) of this quarter
+        const int m = m0 + wm * 64 + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+        if (m >= p.M || n >= p.N) continue;
+        gemm_epilogue<EPI>(p, m, n, eng.value(i, j, e), lsum);
+      }
 }
 
 // fp32 [rows][cols] (row stride ld) -> 16-bit planes [rows][Kp], zero padding;
@@ -289,10 +373,45 @@ int gemm_launch(const GemmArgs& a0, hipStream_t st) {
 // latency hides behind them; same products in the same order, same bits).
 // Two-plane products keep steps of 32 (their 80 KB stages allow two
 // workgroups per CU; 64 would allow one).
+template <int EPI, int BN>
+int gemm_ws_launch(const GemmArgs& a0, hipStream_t st) {
+  GemmArgs a = a0;
+  a.mtiles = (a.M + kGemmTile - 1) / kGemmTile;
+  a.ntiles = (a.N + BN - 1) / BN;
+  const size_t lds = WsEngine<1, false, BN>::lds_bytes();
+  static bool lds_set = false;
+  if (!lds_set) {
+    if (hipFuncSetAttribute((const void*)k_gemm_ws<EPI, BN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+      (void)hipGetLastError();
+    lds_set = true;
+  }
+  hipLaunchKernelGGL((k_gemm_ws<EPI, BN>), dim3((unsigned)(a.mtiles * a.ntiles)), dim3(64 * (2 * BN / 64 + 4)), lds,
+                     st, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return mfail(PWFS_EHIP, "launch k_gemm_ws: %s", hipGetErrorString(e));
+  return PWFS_OK;
+}
+
+// One-plane products with at least two rounds of wave-specialised
+// workgroups on the chip (one per CU) and no loss epilogue take the
+// wave-specialised tiles: 128 x 256 where that still gives four rounds,
+// else 128 x 128.  The rest (training batches, two-plane checks, the loss
+// and gradient epilogues) take the 256-lane tiles.
+constexpr int kWsMinTiles = 512, kWsWideTiles = 1024;
+
 template <int EPI>
 int gemm_dispatch(int planes, const GemmArgs& a, hipStream_t st) {
   if (planes == 2) return gemm_launch<2, EPI, 32>(a, st);
-  return (a.K % 64 == 0 && a.K2 % 64 == 0) ? gemm_launch<1, EPI, 64>(a, st) : gemm_launch<1, EPI, 32>(a, st);
+  if (a.K % 64 != 0 || a.K2 % 64 != 0) return gemm_launch<1, EPI, 32>(a, st);
+  if constexpr (EPI != E_DHIDDEN) {
+    if (EPI != E_OUTPUT || !a.target) {
+      const long long mt = (a.M + kGemmTile - 1) / kGemmTile;
+      if (mt * ((a.N + 255) / 256) >= kWsWideTiles) return gemm_ws_launch<EPI, 256>(a, st);
+      if (mt * ((a.N + 127) / 128) >= kWsMinTiles) return gemm_ws_launch<EPI, 128>(a, st);
+    }
+  }
+  return gemm_launch<1, EPI, 64>(a, st);
 }
 
 int split_launch(const float* src, long long ld, int rows, int cols, int Kp, uint16_t* dst, long long plane,
