@@ -187,7 +187,7 @@ def surrogate_form(torch, dev, n_train, n_test, epochs, reps):
             "train_seconds": round(rep.seconds, 2), "data_seconds": round(t_data, 2),
             "loss_first_last": [rep.losses[0], rep.losses[-1]],
             "form": "IM z + r_rms * net(z): push-pull interaction matrix plus the trained correction",
-            "roofline": {"kernel": "k_gemm (network and linear part bf16; fp32 accumulation)", "bound": "mfma",
+            "roofline": {"kernel": "k_gemm_ws (inference products: network and folded linear part, bf16, fp32 accumulation)", "bound": "mfma",
                          "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                          "frac": round(ach / MFMA_PEAK_TFLOPS["bf16"], 4), "flops_per_frame": fl,
                          "traffic": None}}
