@@ -123,6 +123,14 @@ def test_polychromatic_small_sensors_match_oracle(D, n, M, r, ob):
     _compare_poly(D, n, M, r, ob, 600.0, [600.0, 750.0, 900.0], [0.25, 0.25, 0.5], opd, "small")
 
 
+def test_polychromatic_every_wavelength_above_the_reference():
+    """No sampled wavelength at the reference (every table scaled, s < 1),
+    one of them with zero weight, and a run-time subaperture width (b = 5)."""
+    opd = von_karman_opd(2, 30, 2.0, 0.3, 25.0, seed=77)
+    _compare_poly(30, 6, 24, 3, 0.2, 500.0, [550.0, 700.0, 850.0, 1000.0], [0.4, 0.0, 0.35, 0.25], opd,
+                  "all scaled")
+
+
 def test_polychromatic_scao_shape_sampled_frames():
     """The SCAO SH shape over the 600-900 nm band (the heterogeneous pyramid
     batch's band) on sampled frames of a 200-frame launch."""
