@@ -63,6 +63,13 @@ struct ShArgs {
   double two_pi_over_lam[PWFS_MAX_LAMBDA];
 };
 
+// Row stride (in complex values) of the DFT table W [M][b] in LDS: an even
+// b is padded by one, so that the rows that a wavefront's lanes read
+// together (consecutive u in the T product, the rows v of a pixel's samples)
+// start on different banks; with b = 8 unpadded rows are 16 words apart and
+// eight of them share two banks of 32.
+__host__ __device__ constexpr int sw_stride(int b) { return (b % 2 == 0) ? b + 1 : b; }
+
 // BB: the subaperture width b at compile time (its row of DFT coefficients
 // then stays in registers while a thread sweeps a row of focal samples:
 // one LDS load per complex multiply-add), 0 for a run-time b.
@@ -85,8 +92,10 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
       for (int i = tid; i < kk; i += kShBlock) pix_out[i] = 0.f;
     return;
   }
-  float2* sW = sh_mem;                 // [M][b]
-  float2* sE = sW + M * b;             // [b][b]
+  constexpr int BW = BB > 0 ? sw_stride(BB) : 0;
+  const int bw = BB > 0 ? BW : sw_stride(b);
+  float2* sW = sh_mem;                 // [M][bw], row u holds W[u][0 .. b)
+  float2* sE = sW + M * bw;            // [b][b]
   float2* sT = sE + b * b;             // [b][M]
   float* sP = (float*)(sT + b * M);    // [kk] pixel values, then [kShBlock] partials
   float* sR = sP + kk;
@@ -95,7 +104,7 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
   // one pass per wavelength; the pixel loop's last barrier frees sW, sE and
   // sT for the next one
   for (int l = 0; l < p.n_lam; ++l) {
-    for (int i = tid; i < M * b; i += kShBlock) sW[i] = p.W[(size_t)l * M * b + i];
+    for (int i = tid; i < M * b; i += kShBlock) sW[(i / b) * bw + i % b] = p.W[(size_t)l * M * b + i];
     for (int i = tid; i < b * b; i += kShBlock) {
       const int y = i / b, x = i % b;
       const size_t g = (size_t)(si * b + y) * p.D + sj * b + x;
@@ -113,7 +122,7 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
       const int y = i / M, u = i % M;
       float re = 0.f, im = 0.f;
       for (int x = 0; x < b; ++x) {
-        const float2 e = sE[y * b + x], w = sW[u * b + x];
+        const float2 e = sE[y * b + x], w = sW[u * bw + x];
         re = fmaf(e.x, w.x, fmaf(-e.y, w.y, re));
         im = fmaf(e.x, w.y, fmaf(e.y, w.x, im));
       }
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
           if constexpr (BB > 0) {
             float2 wv[BB];
   #pragma unroll
-            for (int y = 0; y < BB; ++y) wv[y] = sW[v * BB + y];
+            for (int y = 0; y < BB; ++y) wv[y] = sW[v * BW + y];
             for (int uu = 0; uu < r; ++uu) {
               const int u = pc * r + uu;
               float re = 0.f, im = 0.f;
@@ -151,7 +160,7 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
               const int u = pc * r + uu;
               float re = 0.f, im = 0.f;
               for (int y = 0; y < b; ++y) {
-                const float2 w = sW[v * b + y], t = sT[y * M + u];
+                const float2 w = sW[v * bw + y], t = sT[y * M + u];
                 re = fmaf(w.x, t.x, fmaf(-w.y, t.y, re));
                 im = fmaf(w.x, t.y, fmaf(w.y, t.x, im));
               }
@@ -236,7 +245,8 @@ extern "C" int pwfs_sh_validate(const pwfs_sh_desc* d) {
     if (std::fabs(wsum - 1.0) > 1e-9) return sfail(PWFS_EINVAL, "lambda_weights must sum to 1");
   }
   const int k = d->n_fft / d->rebin;
-  const size_t lds = sizeof(float2) * ((size_t)d->n_fft * b * 2 + (size_t)b * b) + sizeof(float) * ((size_t)k * k + kShBlock);
+  const size_t lds = sizeof(float2) * ((size_t)d->n_fft * (sw_stride(b) + b) + (size_t)b * b) +
+                     sizeof(float) * ((size_t)k * k + kShBlock);
   if (lds > 150 * 1024) return sfail(PWFS_EUNSUPPORTED, "subaperture tables exceed the LDS (n_fft x b too large)");
   return PWFS_OK;
 }
@@ -318,7 +328,8 @@ extern "C" int pwfs_sh_plan(const pwfs_sh_desc* d, int max_frames, void* ws, siz
   s->W = (float2*)p;
   p += a256(sizeof(float2) * nl * M * b);
   s->valid = (uint8_t*)p;
-  s->lds = sizeof(float2) * ((size_t)M * b * 2 + (size_t)b * b) + sizeof(float) * ((size_t)s->k * s->k + kShBlock);
+  s->lds = sizeof(float2) * ((size_t)M * (sw_stride(b) + b) + (size_t)b * b) +
+           sizeof(float) * ((size_t)s->k * s->k + kShBlock);
   hipStream_t st = (hipStream_t)stream;
   if (hipMemcpyAsync(s->amp, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(s->W, W.data(), W.size() * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
