@@ -70,10 +70,20 @@ struct ShArgs {
 // eight of them share two banks of 32.
 __host__ __device__ constexpr int sw_stride(int b) { return (b % 2 == 0) ? b + 1 : b; }
 
+// Row stride (in complex values) of the row products T [b][M] in LDS: 257
+// for M <= 256, fixed at compile time, so that the loads of a column of T
+// in the pixel loop take their row offsets as immediates (one LDS load and
+// no address arithmetic per term).  2056 bytes is beyond the reach of both
+// paired-load forms (whose two rows collided on banks: a stride that is a
+// multiple of 512 bytes puts both on one bank), and consecutive rows start
+// two banks apart.  M above 256 keeps M.
+constexpr int kTFixed = 256, kTStride = 257;
+__host__ __device__ constexpr int t_stride(int M) { return M <= kTFixed ? kTStride : M; }
+
 // BB: the subaperture width b at compile time (its row of DFT coefficients
 // then stays in registers while a thread sweeps a row of focal samples:
 // one LDS load per complex multiply-add), 0 for a run-time b.
-template <int BB>
+template <int BB, bool FIXT>
 __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
   extern __shared__ float2 sh_mem[];
   const int tid = threadIdx.x;
@@ -96,8 +106,9 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
   const int bw = BB > 0 ? BW : sw_stride(b);
   float2* sW = sh_mem;                 // [M][bw], row u holds W[u][0 .. b)
   float2* sE = sW + M * bw;            // [b][b]
-  float2* sT = sE + b * b;             // [b][M]
-  float* sP = (float*)(sT + b * M);    // [kk] pixel values, then [kShBlock] partials
+  const int ts = FIXT ? kTStride : M;   // T row stride (t_stride(M))
+  float2* sT = sE + b * b;             // [b][ts], row y holds T[y][0 .. M)
+  float* sP = (float*)(sT + b * ts);   // [kk] pixel values, then [kShBlock] partials
   float* sR = sP + kk;
 
   const float* opd = p.opd + (size_t)f * p.D * p.D;
@@ -126,7 +137,7 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
         re = fmaf(e.x, w.x, fmaf(-e.y, w.y, re));
         im = fmaf(e.x, w.y, fmaf(e.y, w.x, im));
       }
-      sT[i] = make_float2(re, im);
+      sT[y * ts + u] = make_float2(re, im);
     }
     __syncthreads();
     // pixels: TPP threads per pixel share its r rows of focal samples (fixed order)
@@ -149,7 +160,7 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
               float re = 0.f, im = 0.f;
   #pragma unroll
               for (int y = 0; y < BB; ++y) {
-                const float2 t = sT[y * M + u];
+                const float2 t = sT[y * ts + u];
                 re = fmaf(wv[y].x, t.x, fmaf(-wv[y].y, t.y, re));
                 im = fmaf(wv[y].x, t.y, fmaf(wv[y].y, t.x, im));
               }
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
               const int u = pc * r + uu;
               float re = 0.f, im = 0.f;
               for (int y = 0; y < b; ++y) {
-                const float2 w = sW[v * bw + y], t = sT[y * M + u];
+                const float2 w = sW[v * bw + y], t = sT[y * ts + u];
                 re = fmaf(w.x, t.x, fmaf(-w.y, t.y, re));
                 im = fmaf(w.x, t.y, fmaf(w.y, t.x, im));
               }
@@ -245,7 +256,7 @@ extern "C" int pwfs_sh_validate(const pwfs_sh_desc* d) {
     if (std::fabs(wsum - 1.0) > 1e-9) return sfail(PWFS_EINVAL, "lambda_weights must sum to 1");
   }
   const int k = d->n_fft / d->rebin;
-  const size_t lds = sizeof(float2) * ((size_t)d->n_fft * (sw_stride(b) + b) + (size_t)b * b) +
+  const size_t lds = sizeof(float2) * ((size_t)d->n_fft * sw_stride(b) + (size_t)b * t_stride(d->n_fft) + (size_t)b * b) +
                      sizeof(float) * ((size_t)k * k + kShBlock);
   if (lds > 150 * 1024) return sfail(PWFS_EUNSUPPORTED, "subaperture tables exceed the LDS (n_fft x b too large)");
   return PWFS_OK;
@@ -328,7 +339,7 @@ extern "C" int pwfs_sh_plan(const pwfs_sh_desc* d, int max_frames, void* ws, siz
   s->W = (float2*)p;
   p += a256(sizeof(float2) * nl * M * b);
   s->valid = (uint8_t*)p;
-  s->lds = sizeof(float2) * ((size_t)M * (sw_stride(b) + b) + (size_t)b * b) +
+  s->lds = sizeof(float2) * ((size_t)M * sw_stride(b) + (size_t)b * t_stride(M) + (size_t)b * b) +
            sizeof(float) * ((size_t)s->k * s->k + kShBlock);
   hipStream_t st = (hipStream_t)stream;
   if (hipMemcpyAsync(s->amp, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -340,8 +351,10 @@ extern "C" int pwfs_sh_plan(const pwfs_sh_desc* d, int max_frames, void* ws, siz
   }
   static bool lds_set = false;
   if (!lds_set) {
-    const void* fns[] = {(const void*)k_sh<0>, (const void*)k_sh<4>, (const void*)k_sh<7>, (const void*)k_sh<8>,
-                         (const void*)k_sh<16>};
+    const void* fns[] = {(const void*)k_sh<0, true>,  (const void*)k_sh<4, true>,  (const void*)k_sh<7, true>,
+                         (const void*)k_sh<8, true>,  (const void*)k_sh<16, true>, (const void*)k_sh<0, false>,
+                         (const void*)k_sh<4, false>, (const void*)k_sh<7, false>, (const void*)k_sh<8, false>,
+                         (const void*)k_sh<16, false>};
     for (const void* fn : fns)
       if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
         (void)hipGetLastError();
@@ -375,12 +388,20 @@ extern "C" int pwfs_sh_forward(pwfs_sh_t s, const float* opd, int nf, float* pix
   }
   const unsigned grid = (unsigned)((long long)nf * s->n * s->n);
   hipStream_t st = (hipStream_t)stream;
-  switch (s->b) {
-    case 4: hipLaunchKernelGGL(k_sh<4>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 7: hipLaunchKernelGGL(k_sh<7>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 8: hipLaunchKernelGGL(k_sh<8>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 16: hipLaunchKernelGGL(k_sh<16>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    default: hipLaunchKernelGGL(k_sh<0>, dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+  const bool fixt = s->M <= kTFixed;
+  switch (s->b * 2 + (fixt ? 1 : 0)) {
+    case 9: hipLaunchKernelGGL((k_sh<4, true>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 8: hipLaunchKernelGGL((k_sh<4, false>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 15: hipLaunchKernelGGL((k_sh<7, true>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 14: hipLaunchKernelGGL((k_sh<7, false>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 17: hipLaunchKernelGGL((k_sh<8, true>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 16: hipLaunchKernelGGL((k_sh<8, false>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 33: hipLaunchKernelGGL((k_sh<16, true>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 32: hipLaunchKernelGGL((k_sh<16, false>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    default:
+      if (fixt) hipLaunchKernelGGL((k_sh<0, true>), dim3(grid), dim3(kShBlock), s->lds, st, a);
+      else hipLaunchKernelGGL((k_sh<0, false>), dim3(grid), dim3(kShBlock), s->lds, st, a);
+      break;
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return sfail(PWFS_EHIP, "launch k_sh: %s", hipGetErrorString(e));
