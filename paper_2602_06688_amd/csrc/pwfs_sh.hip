@@ -82,7 +82,8 @@ __host__ __device__ constexpr int t_stride(int M) { return M <= kTFixed ? kTStri
 
 // BB: the subaperture width b at compile time (its row of DFT coefficients
 // then stays in registers while a thread sweeps a row of focal samples:
-// one LDS load per complex multiply-add), 0 for a run-time b.
+// one LDS load per complex multiply-add), 0 for a run-time b.  FIXT: M <=
+// 256, T stored at the fixed stride kTStride.
 template <int BB, bool FIXT>
 __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
   extern __shared__ float2 sh_mem[];
