@@ -259,8 +259,8 @@ __device__ __forceinline__ int space_index(int t, int slot) {
 // of the inverse transform has the same radix and the same L as stage s of
 // the forward one, so its twiddles are the conjugates of the forward ones.
 // Each lane then keeps the twiddles of all its butterflies in registers for
-// the whole kernel, and the LDS exchange buffer is padded by one float2
-// every 8 to spread the strided Stockham stores over the banks.
+// the whole kernel, and the LDS exchange buffer is padded (ExPad below) to
+// spread the strided Stockham stores over the banks.
 
 template <int N>
 struct Palindromic {
@@ -273,8 +273,41 @@ struct Palindromic {
   static constexpr bool value = check();
 };
 
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
-template <int N> struct PaddedLen { static constexpr int value = N + N / 8; };
+// Padding of the exchange buffer at stage boundary B (the stores after
+// stage B and the loads before stage B + 1): element i sits at
+// i + PB (i >> A).  One float2 in 8 spreads the radix-8 plans' strided
+// stores; the 4 4 3 4 4 plan of 768 has its own per boundary, chosen with a
+// bank model of each boundary's stores and loads (lanes of one 16- or
+// 32-lane LDS cycle on distinct banks): boundary 0 (stride-4 stores, paired
+// into 16-byte writes) 2 in 32, boundary 1 (runs of 4 lanes, 16 apart) 1 in
+// 4, boundaries 2 and 3 (runs of 16 and 48 lanes) none.  Each padding is
+// additive over offsets that are multiples of 64, so the addresses stay one
+// per-lane base plus immediates.
+template <int N, int B> struct ExPad { static constexpr int A = 3, PB = 1; };
+template <> struct ExPad<768, 0> { static constexpr int A = 5, PB = 2; };
+template <> struct ExPad<768, 1> { static constexpr int A = 2, PB = 1; };
+template <> struct ExPad<768, 2> { static constexpr int A = 0, PB = 0; };
+template <> struct ExPad<768, 3> { static constexpr int A = 0, PB = 0; };
+
+template <int N, int B>
+__device__ __forceinline__ int lds_pad(int i) {
+  using X = ExPad<N, B>;
+  if constexpr (X::PB == 0) return i;
+  else return i + X::PB * (i >> X::A);
+}
+template <int N> struct PaddedLen {
+  static constexpr int len() {
+    int m = N;
+    for (int b = 0; b + 1 < FftPlan<N>::NS; ++b) {
+      const int a = b == 0 ? ExPad<N, 0>::A : b == 1 ? ExPad<N, 1>::A : b == 2 ? ExPad<N, 2>::A : ExPad<N, 3>::A;
+      const int pb = b == 0 ? ExPad<N, 0>::PB : b == 1 ? ExPad<N, 1>::PB : b == 2 ? ExPad<N, 2>::PB : ExPad<N, 3>::PB;
+      const int l = N + pb * (N >> a);
+      if (l > m) m = l;
+    }
+    return m;
+  }
+  static constexpr int value = len();
+};
 
 template <int N, int S>
 struct StageTw {
@@ -333,16 +366,18 @@ __device__ __forceinline__ void stage_compute_reg(float2* v, const TW& tw) {
   }
 }
 
-template <int N, int R>
+// loads before stage B + 1 of radix R, from boundary B's layout
+template <int N, int R, int B>
 __device__ __forceinline__ void stage_load_pad(float2* v, int t, const float2* buf) {
   constexpr int T = FftPlan<N>::T, V = N / T, NB = V / R;
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[i * R + q] = buf[lds_pad(t + T * i + q * (N / R))];
+    for (int q = 0; q < R; ++q) v[i * R + q] = buf[lds_pad<N, B>(t + T * i + q * (N / R))];
 }
 
-template <int N, int R, int L>
+// stores after stage B (radix R, span L) in boundary B's layout
+template <int N, int R, int L, int B>
 __device__ __forceinline__ void stage_store_pad(const float2* v, int t, float2* buf) {
   constexpr int T = FftPlan<N>::T, V = N / T, NB = V / R;
 #pragma unroll
@@ -350,7 +385,7 @@ __device__ __forceinline__ void stage_store_pad(const float2* v, int t, float2* 
     const int j = t + T * i;
     const int base = (j / L) * L * R + (j % L);
 #pragma unroll
-    for (int q = 0; q < R; ++q) buf[lds_pad(base + q * L)] = v[i * R + q];
+    for (int q = 0; q < R; ++q) buf[lds_pad<N, B>(base + q * L)] = v[i * R + q];
   }
 }
 
@@ -377,14 +412,14 @@ __device__ __forceinline__ void fft_reg(float2* v, int t, float2* buf, const TwS
   }
   if constexpr (S > 0) {
     wave_sync();
-    stage_load_pad<N, SI::R>(v, t, buf);
+    stage_load_pad<N, SI::R, S - 1>(v, t, buf);
     wave_sync();
     stage_compute_reg<N, S, SI::R, INV>(v, tw_of<N, S>(tw));
   } else {
     stage_compute_reg<N, 0, NZ0, INV>(v, tw.s1);
   }
   if constexpr (S + 1 < P::NS) {
-    stage_store_pad<N, SI::R, SI::L>(v, t, buf);
+    stage_store_pad<N, SI::R, SI::L, S>(v, t, buf);
     fft_reg<N, INV, S + 1, NZ0>(v, t, buf, tw);
   }
 }
