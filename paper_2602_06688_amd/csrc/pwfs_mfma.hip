@@ -193,6 +193,10 @@ struct G2Args {
   float scale[PWFS_MAX_LAMBDA];
 };
 
+// Both stages run on the wave-specialised workgroup of mfma_gemm.hpp
+// (WsEngine, WsParts, ws_produce): 8 consumer waves on a 128 x 256 tile and
+// 4 producer waves keeping kWsDepth K steps of operands in flight.
+//
 // Stage 2: columns of C run over all frames of the pass (n = f Nc + c), so a
 // tile may straddle two frames and only the pass's last tile is ragged.  The
 // n_lam x n_mod products of one tile form one stream of K steps, and a
