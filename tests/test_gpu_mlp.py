@@ -61,6 +61,46 @@ def test_gemm_accumulates_with_beta_and_ignores_old_output_without():
     assert _rel(nan.cpu().numpy(), A.astype(np.float64) @ B.astype(np.float64).T) <= 2e-5
 
 
+def _bf16_exact(rng, shape):
+    """Standard normal values cut to 8 significant bits, so that a bf16 plane
+    holds them exactly and each product is exact in fp32."""
+    x = rng.standard_normal(shape).astype(np.float32)
+    return (x.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)
+
+
+# Shapes large enough for the wave-specialised tiles (128 x 128 at 512 tiles,
+# 128 x 256 at 1024), ragged in M and N, and one whose padded K (224) is not a
+# multiple of 64, which keeps the 256-lane tiles.
+@pytest.mark.parametrize("M,N,K", [(4096, 2048, 128), (8229, 4146, 192), (4096, 2048, 200)])
+def test_large_bf16_gemm_within_the_fp32_summation_bound(M, N, K):
+    P = _P()
+    rng = np.random.default_rng(M + 7 * N + K)
+    A = _bf16_exact(rng, (M, K))
+    B = _bf16_exact(rng, (N, K))
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = A64 @ B64.T
+    bound = (K * 2.0 ** -23) * (np.abs(A64) @ np.abs(B64).T)   # gamma_K |A| |B|^T, u = 2^-24, doubled
+    print(f"[gpu] large bf16 gemm {M}x{N}x{K}", flush=True)
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = P.gemm(Ad, Bd, precision=P.BF16)
+    torch.cuda.synchronize()
+    err = np.abs(C.cpu().numpy().astype(np.float64) - ref)
+    print(f"      max |err| / bound {float((err / bound).max()):.3f}", flush=True)
+    assert np.all(err <= bound)
+    # beta = 1 adds the old output in the epilogue of the same tiles
+    C0 = rng.standard_normal((M, N)).astype(np.float32)
+    out = torch.from_numpy(C0).cuda()
+    P.gemm(Ad, Bd, out=out, alpha=1.0, beta=1.0, precision=P.BF16)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - (ref + C0)) <= bound + 2.0 ** -23 * (np.abs(ref) + np.abs(C0)))
+    # the allocation-free entry point runs the same tiles: same bits
+    Cn = torch.full((M, N), float("nan"), device="cuda")
+    P.gemm_noalloc(Ad, Bd, Cn, precision=P.BF16)
+    torch.cuda.synchronize()
+    assert torch.equal(Cn, C)
+
+
 def _to_oracle(params, sizes):
     out, off = [], 0
     for i, o in zip(sizes[:-1], sizes[1:]):
