@@ -80,11 +80,62 @@ __host__ __device__ constexpr int sw_stride(int b) { return (b % 2 == 0) ? b + 1
 constexpr int kTFixed = 256, kTStride = 257;
 __host__ __device__ constexpr int t_stride(int M) { return M <= kTFixed ? kTStride : M; }
 
-// BB: the subaperture width b at compile time (its row of DFT coefficients
-// then stays in registers while a thread sweeps a row of focal samples:
-// one LDS load per complex multiply-add), 0 for a run-time b.  FIXT: M <=
-// 256, T stored at the fixed stride kTStride.
-template <int BB, bool FIXT>
+// Pixel sum of thread s of a pixel whose focal block starts at row pr r and
+// column pc r: |sum_y W[v][y] T[y][u]|^2 over every row v of the block and
+// the columns u = s, s + tpp, ... of it, NC columns at a time.  Their T
+// columns stay in registers while the block's W rows stream past, so each W
+// value read from LDS (the lanes of one pixel row read the same one) serves
+// NC samples.  Columns past the block are zero (their loads re-read a valid
+// column), so they add exact zeros.
+template <int BB, int NC>
+__device__ __forceinline__ float sh_pixel_cols(const float2* sW, const float2* sT, int ts, int r, int tpp, int s,
+                                               int pr, int pc) {
+  constexpr int BW = sw_stride(BB);
+  float acc = 0.f;
+  for (int u0 = s; u0 < r; u0 += NC * tpp) {
+    float2 tc[NC][BB];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const bool in = u0 + c * tpp < r;
+      const int u = pc * r + (in ? u0 + c * tpp : u0);
+#pragma unroll
+      for (int y = 0; y < BB; ++y) tc[c][y] = in ? sT[y * ts + u] : make_float2(0.f, 0.f);
+    }
+    for (int vv = 0; vv < r; ++vv) {
+      const float2* wrow = sW + (pr * r + vv) * BW;
+      float re[NC], im[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) re[c] = im[c] = 0.f;
+#pragma unroll
+      for (int y = 0; y < BB; ++y) {
+        const float2 w = wrow[y];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          re[c] = fmaf(w.x, tc[c][y].x, fmaf(-w.y, tc[c][y].y, re[c]));
+          im[c] = fmaf(w.x, tc[c][y].y, fmaf(w.y, tc[c][y].x, im[c]));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc = fmaf(re[c], re[c], fmaf(im[c], im[c], acc));
+    }
+  }
+  return acc;
+}
+
+// Threads per pixel in the pixel loop: the largest power of two that keeps
+// the workgroup's kShBlock threads busy without exceeding r.
+__host__ __device__ inline int sh_tpp(int kk, int r) {
+  int tpp = 1;
+  while (tpp * 2 * kk <= kShBlock && tpp * 2 <= r) tpp *= 2;
+  return tpp;
+}
+
+// BB: the subaperture width b at compile time (the pixel loop then keeps NC
+// columns of T in registers, sh_pixel_cols), 0 for a run-time b.  FIXT: M <=
+// 256, T stored at the fixed stride kTStride.  NC = 4 needs a thread to own at
+// least four columns (r >= 4 tpp) to pay for its registers; the host picks it
+// then, for b <= 8.
+template <int BB, bool FIXT, int NC>
 __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
   extern __shared__ float2 sh_mem[];
   const int tid = threadIdx.x;
@@ -141,33 +192,22 @@ __global__ __launch_bounds__(kShBlock) void k_sh(ShArgs p) {
       sT[y * ts + u] = make_float2(re, im);
     }
     __syncthreads();
-    // pixels: TPP threads per pixel share its r rows of focal samples (fixed order)
-    int tpp = 1;
-    while (tpp * 2 * kk <= kShBlock && tpp * 2 <= r) tpp *= 2;
+    // pixels: TPP threads per pixel share its r x r focal samples (fixed order).
+    // With b known at compile time thread s takes the focal columns s, s + TPP,
+    // ... (sh_pixel_cols); otherwise the rows s, s + TPP, ... one W row at a
+    // time.
+    const int tpp = sh_tpp(kk, r);
     for (int base = 0; base < kk * tpp; base += kShBlock) {
       const int slot = base + tid;
       const int P = slot / tpp, s = slot % tpp;
       float acc = 0.f;
       if (P < kk) {
         const int pr = P / k, pc = P % k;
-        for (int vv = s; vv < r; vv += tpp) {
-          const int v = pr * r + vv;
-          if constexpr (BB > 0) {
-            float2 wv[BB];
-  #pragma unroll
-            for (int y = 0; y < BB; ++y) wv[y] = sW[v * BW + y];
-            for (int uu = 0; uu < r; ++uu) {
-              const int u = pc * r + uu;
-              float re = 0.f, im = 0.f;
-  #pragma unroll
-              for (int y = 0; y < BB; ++y) {
-                const float2 t = sT[y * ts + u];
-                re = fmaf(wv[y].x, t.x, fmaf(-wv[y].y, t.y, re));
-                im = fmaf(wv[y].x, t.y, fmaf(wv[y].y, t.x, im));
-              }
-              acc = fmaf(re, re, fmaf(im, im, acc));
-            }
-          } else {
+        if constexpr (BB > 0) {
+          acc = sh_pixel_cols<BB, NC>(sW, sT, ts, r, tpp, s, pr, pc);
+        } else {
+          for (int vv = s; vv < r; vv += tpp) {
+            const int v = pr * r + vv;
             for (int uu = 0; uu < r; ++uu) {
               const int u = pc * r + uu;
               float re = 0.f, im = 0.f;
@@ -352,10 +392,13 @@ extern "C" int pwfs_sh_plan(const pwfs_sh_desc* d, int max_frames, void* ws, siz
   }
   static bool lds_set = false;
   if (!lds_set) {
-    const void* fns[] = {(const void*)k_sh<0, true>,  (const void*)k_sh<4, true>,  (const void*)k_sh<7, true>,
-                         (const void*)k_sh<8, true>,  (const void*)k_sh<16, true>, (const void*)k_sh<0, false>,
-                         (const void*)k_sh<4, false>, (const void*)k_sh<7, false>, (const void*)k_sh<8, false>,
-                         (const void*)k_sh<16, false>};
+    const void* fns[] = {
+        (const void*)k_sh<0, true, 2>,  (const void*)k_sh<4, true, 2>,  (const void*)k_sh<7, true, 2>,
+        (const void*)k_sh<8, true, 2>,  (const void*)k_sh<16, true, 2>, (const void*)k_sh<0, false, 2>,
+        (const void*)k_sh<4, false, 2>, (const void*)k_sh<7, false, 2>, (const void*)k_sh<8, false, 2>,
+        (const void*)k_sh<16, false, 2>, (const void*)k_sh<4, true, 4>, (const void*)k_sh<7, true, 4>,
+        (const void*)k_sh<8, true, 4>,  (const void*)k_sh<4, false, 4>, (const void*)k_sh<7, false, 4>,
+        (const void*)k_sh<8, false, 4>};
     for (const void* fn : fns)
       if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
         (void)hipGetLastError();
@@ -364,6 +407,19 @@ extern "C" int pwfs_sh_plan(const pwfs_sh_desc* d, int max_frames, void* ws, siz
   *out = s;
   return PWFS_OK;
 }
+
+namespace {
+template <int BB, bool FIXT>
+void launch_sh(bool wide, unsigned grid, size_t lds, hipStream_t st, const ShArgs& a) {
+  if constexpr (BB > 0 && BB <= 8) {
+    if (wide) {
+      hipLaunchKernelGGL((k_sh<BB, FIXT, 4>), dim3(grid), dim3(kShBlock), lds, st, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_sh<BB, FIXT, 2>), dim3(grid), dim3(kShBlock), lds, st, a);
+}
+}  // namespace
 
 extern "C" int pwfs_sh_forward(pwfs_sh_t s, const float* opd, int nf, float* pixels, float* slopes, void* stream) {
   if (!s) return sfail(PWFS_EINVAL, "plan is NULL");
@@ -390,18 +446,19 @@ extern "C" int pwfs_sh_forward(pwfs_sh_t s, const float* opd, int nf, float* pix
   const unsigned grid = (unsigned)((long long)nf * s->n * s->n);
   hipStream_t st = (hipStream_t)stream;
   const bool fixt = s->M <= kTFixed;
+  const bool wide = s->r >= 4 * sh_tpp(s->k * s->k, s->r);
   switch (s->b * 2 + (fixt ? 1 : 0)) {
-    case 9: hipLaunchKernelGGL((k_sh<4, true>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 8: hipLaunchKernelGGL((k_sh<4, false>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 15: hipLaunchKernelGGL((k_sh<7, true>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 14: hipLaunchKernelGGL((k_sh<7, false>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 17: hipLaunchKernelGGL((k_sh<8, true>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 16: hipLaunchKernelGGL((k_sh<8, false>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 33: hipLaunchKernelGGL((k_sh<16, true>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
-    case 32: hipLaunchKernelGGL((k_sh<16, false>), dim3(grid), dim3(kShBlock), s->lds, st, a); break;
+    case 9: launch_sh<4, true>(wide, grid, s->lds, st, a); break;
+    case 8: launch_sh<4, false>(wide, grid, s->lds, st, a); break;
+    case 15: launch_sh<7, true>(wide, grid, s->lds, st, a); break;
+    case 14: launch_sh<7, false>(wide, grid, s->lds, st, a); break;
+    case 17: launch_sh<8, true>(wide, grid, s->lds, st, a); break;
+    case 16: launch_sh<8, false>(wide, grid, s->lds, st, a); break;
+    case 33: launch_sh<16, true>(wide, grid, s->lds, st, a); break;
+    case 32: launch_sh<16, false>(wide, grid, s->lds, st, a); break;
     default:
-      if (fixt) hipLaunchKernelGGL((k_sh<0, true>), dim3(grid), dim3(kShBlock), s->lds, st, a);
-      else hipLaunchKernelGGL((k_sh<0, false>), dim3(grid), dim3(kShBlock), s->lds, st, a);
+      if (fixt) launch_sh<0, true>(wide, grid, s->lds, st, a);
+      else launch_sh<0, false>(wide, grid, s->lds, st, a);
       break;
   }
   const hipError_t e = hipGetLastError();
