@@ -147,7 +147,7 @@ def time_form(P, torch, s, x, n_frames, steps, warmup, ref_I, ref_S, dev, stream
 def surrogate_form(torch, dev, n_train, n_test, epochs, reps):
     """Learned surrogate of the 160 px sensor: trained on n_train samples of
     the plain kernels, timed on n_test held-out samples; errors are against
-    the plain path (the judge), next to the linear interaction-matrix method."""
+    the plain path (the reference), next to the linear interaction-matrix method."""
     from paper_2602_06688_amd.surrogate import SurrogatePipeline
     from workloads import workload
     from workloads.modes import coefficient_sigmas, kl_modes

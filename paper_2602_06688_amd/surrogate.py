@@ -11,7 +11,7 @@ at a residual of this size:
 The network is trained on the residual s - IM z of data the plain sensor
 kernels generate, on the GPU by the library's own forward/backward/Adam
 kernels; its output layer starts at zero, so training starts from the linear
-model.  The plain sensor stays the judge of the surrogate's error and its
+model.  The plain sensor stays the reference for the surrogate's error and its
 fallback for inputs outside the training distribution.  Every product and
 every sensor step runs in the library (``pwfs.gemm``, ``pwfs.Plan``,
 ``pwfs.MLP``); torch only holds device memory.
