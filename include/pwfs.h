@@ -49,7 +49,7 @@ typedef struct pwfs_plan_s* pwfs_plan_t;
 typedef enum {
   PWFS_OK = 0,
   PWFS_EINVAL = -1,        /* bad argument or sensor description        */
-  PWFS_EUNSUPPORTED = -2,  /* valid, but a size this build does not run */
+  PWFS_EUNSUPPORTED = -2,  /* valid, but a size this library does not run */
   PWFS_EWORKSPACE = -3,    /* workspace missing, too small or misaligned */
   PWFS_EHIP = -4,          /* a HIP runtime call or launch failed       */
   PWFS_ESTATE = -5         /* call out of order (e.g. frames > max)     */

@@ -78,7 +78,7 @@ def _build():
 
 
 def _descriptions(path):
-    """Groups (sensors, frames) the driver plans: the workloads' sensors in
+    """Groups (sensors, frames) that abi_driver plans: the workloads' sensors in
     every precision, the six-sensor heterogeneous plan, and the GPU tests'
     edge sensors."""
     sys.path.insert(0, ROOT)
