@@ -53,6 +53,9 @@ def _compare(D, n, M, r, ob, opd, label, frames=None):
     (32, 8, 16, 2, 0.0),     # b = 4
     (20, 4, 20, 4, 0.0),     # b = 5: run-time width
     (64, 4, 48, 4, 0.1),     # b = 16
+    (16, 2, 48, 4, 0.0),     # b = 8, one thread per pixel: four focal columns per register group
+    (16, 2, 60, 5, 0.1),     # b = 8, 5 columns: a group of four and one with a single live column
+    (16, 4, 64, 4, 0.0),     # b = 4, four columns per register group
 ])
 def test_small_sensors_match_oracle(D, n, M, r, ob):
     rng = np.random.default_rng(D * M + r)
@@ -115,6 +118,7 @@ def _compare_poly(D, n, M, r, ob, lam_ref, lams, ws, opd, label, frames=None):
     (40, 5, 32, 4, 0.3),     # b = 8
     (28, 4, 60, 15, 0.1),    # b = 7, 15 x 15 samples per pixel
     (20, 4, 20, 4, 0.0),     # b = 5: run-time width
+    (16, 2, 60, 5, 0.1),     # b = 8, four focal columns per register group and a ragged one
 ])
 def test_polychromatic_small_sensors_match_oracle(D, n, M, r, ob):
     """Three wavelengths (600, 750, 900 nm; the grid fixed at 600 nm) against
